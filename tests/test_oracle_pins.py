@@ -1,0 +1,504 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each test names the passage of the paper (or the textbook fact) that fixes the
+expected value.  Together they are chosen so that a dropped term, a wrong sign,
+a transposed index or a wrong branch anywhere in the oracle fails one of them.
+"""
+from __future__ import annotations
+
+import cmath
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import amploss, blind, operators as ops, stagm
+from oracle.geometry import build_geometry, cover_count, multiplicity, overlap_width, GeometryError
+from oracle.od2p import (admm_undecomposed, augmented_lagrangian, init_state, merge, od2pm_run,
+                         od2pm_step, forward_sub, adjoint_sub, subdomain_illumination, snr_db)
+from tests.oracle_problems import oracle_problem, tiny_spec
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+RNG = np.random.default_rng(1234)
+
+
+def crandn(*shape, rng=RNG):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+# ---------------------------------------------------------------------------
+# T1  the unitary DFT (problem statement: F is the normalized DFT)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("p", [4, 6, 8])
+def test_fft_matches_textbook_dft(p):
+    x = crandn(p, p)
+    want = np.zeros((p, p), dtype=np.complex128)
+    for kr in range(p):
+        for kc in range(p):
+            s = 0j
+            for r in range(p):
+                for c in range(p):
+                    s += x[r, c] * cmath.exp(-2j * math.pi * (r * kr + c * kc) / p)
+            want[kr, kc] = s / p
+    np.testing.assert_allclose(ops.fft2(x), want, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(ops.ifft2(want), x, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("p", [16, 32, 64])
+def test_parseval(p):
+    x = crandn(p, p)
+    assert abs(np.linalg.norm(ops.fft2(x)) - np.linalg.norm(x)) < 1e-12 * np.linalg.norm(x)
+
+
+# ---------------------------------------------------------------------------
+# T2, T3  A, A*, and the diagonal A*A (eq. AtA)
+# ---------------------------------------------------------------------------
+
+def _small_scan(n=24, p=8, step=4, jitter=1, seed=3):
+    off, grid = synthetic.raster_offsets(n, p, step, jitter, np.random.default_rng(seed))
+    w = synthetic.make_probe(p, 3.0, 0.05) + 0.05 * crandn(p, p)   # generic probe, no symmetry
+    return off, grid, w
+
+
+def test_adjoint_identity():
+    off, _, w = _small_scan()
+    u = crandn(24, 24)
+    y = crandn(len(off), 8, 8)
+    lhs = np.vdot(ops.forward(u, w, off), y)
+    rhs = np.vdot(u, ops.adjoint(y, w, off, u.shape))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_AtA_is_diagonal_illumination():
+    off, _, w = _small_scan()
+    u = crandn(24, 24)
+    AtAu = ops.adjoint(ops.forward(u, w, off), w, off, u.shape)
+    den = ops.illumination(w, off, u.shape)
+    np.testing.assert_allclose(AtAu, den * u, rtol=0, atol=1e-12)
+    # brute force of the diagonal: per pixel, sum |w|^2 over the windows covering it
+    bf = np.zeros(u.shape)
+    for (r0, c0) in off:
+        for a in range(8):
+            for b in range(8):
+                bf[r0 + a, c0 + b] += abs(w[a, b]) ** 2
+    np.testing.assert_allclose(den, bf, rtol=0, atol=1e-13)
+
+
+def test_forward_is_windowed_product():
+    off, _, w = _small_scan()
+    u = crandn(24, 24)
+    X = ops.forward(u, w, off)
+    j = 7
+    r0, c0 = off[j]
+    patch = np.array([[u[r0 + a, c0 + b] * w[a, b] for b in range(8)] for a in range(8)])
+    np.testing.assert_allclose(X[j], np.fft.fft2(patch) / 8.0, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# T4, T5, T6  ST-AGM, its gradient and its closed-form proximal map (Sec. 2.2)
+# ---------------------------------------------------------------------------
+
+def _brute_prox_magnitude(ay, b, eps, lam, n=400001):
+    top = max(ay, math.sqrt(b)) * 1.5 + 1e-3
+    rho = np.linspace(0.0, top, n)
+    obj = stagm.g_eps(rho, b, eps) + 0.5 * lam * (rho - ay) ** 2
+    return rho[int(np.argmin(obj))], top / (n - 1)
+
+
+@pytest.mark.parametrize("eps", [0.1, 0.5, 0.9])
+@pytest.mark.parametrize("lam", [0.05, 0.5, 1.0, 2.0, 4.0, 50.0])
+def test_prox_matches_bruteforce_1d(eps, lam):
+    rng = np.random.default_rng(int(eps * 100 + lam * 7))
+    for _ in range(25):
+        b = float(rng.uniform(0.0, 5.0))
+        ay = float(rng.uniform(0.0, 3.0) * math.sqrt(b) + rng.uniform(0, 0.2))
+        want, h = _brute_prox_magnitude(ay, b, eps, lam)
+        got = abs(complex(stagm.prox(np.array([ay + 0j]), np.array([b]), eps, lam)[0]))
+        assert abs(got - want) <= 2 * h, (eps, lam, b, ay, got, want)
+
+
+def test_prox_garbled_threshold_reading():
+    # eps=0.5, lam=4, f=4, |y|=0.3: the literal print |y| < eps - (1-eps)/lam*sqrt(f) = 0.25 says
+    # "AGM branch"; the reading (eps - (1-eps)/lam)*sqrt(f) = 0.75 says "truncated branch".  Brute
+    # force decides.
+    want, h = _brute_prox_magnitude(0.3, 4.0, 0.5, 4.0)
+    got = abs(complex(stagm.prox(np.array([0.3 + 0j]), np.array([4.0]), 0.5, 4.0)[0]))
+    assert abs(got - want) <= 2 * h
+    assert abs(got - 0.3 * 4.0 / (4.0 - 1.0)) < 1e-12        # truncated-branch value 0.4
+
+
+def test_prox_keeps_phase_bruteforce_2d():
+    eps, lam, b = 0.5, 2.0, 2.0
+    y = 0.4 * cmath.exp(1.1j)
+    g = np.linspace(-2.5, 2.5, 1201)
+    zr, zi = np.meshgrid(g, g, indexing="ij")
+    z = zr + 1j * zi
+    obj = stagm.g_eps(z, b, eps) + 0.5 * lam * np.abs(z - y) ** 2
+    k = np.unravel_index(np.argmin(obj), obj.shape)
+    got = complex(stagm.prox(np.array([y]), np.array([b]), eps, lam)[0])
+    assert abs(got - z[k]) < 2 * (g[1] - g[0])
+
+
+def test_prox_special_cases():
+    eps = 0.5
+    kappa = (1 - eps) / eps
+    ys = crandn(1000) * 2
+    f = np.abs(crandn(1000)) ** 2
+    # lam < (1-eps)/eps: never truncated -> AGM prox everywhere
+    lam = 0.3 * kappa
+    z = stagm.prox(ys, f, eps, lam)
+    np.testing.assert_allclose(z, ys / np.abs(ys) * (np.sqrt(f) + lam * np.abs(ys)) / (1 + lam), atol=1e-14)
+    # lam == (1-eps)/eps: finite everywhere
+    assert np.all(np.isfinite(stagm.prox(ys, f, eps, kappa)))
+    # f = 0: z = lam y / (1 + lam)
+    for lam in (0.1, 2.0):
+        np.testing.assert_allclose(stagm.prox(ys, np.zeros(1000), eps, lam), lam * ys / (1 + lam), atol=1e-14)
+    # y = 0 with f > 0: a minimiser on the circle |z| = sqrt(f)/(1+lam); sign(0) = +1
+    z0 = stagm.prox(np.zeros(3, complex), np.array([1.0, 4.0, 9.0]), eps, 0.1)
+    np.testing.assert_allclose(z0, np.array([1.0, 2.0, 3.0]) / 1.1, atol=1e-15)
+
+
+def test_stagm_continuity_and_minimiser():
+    # g_eps is continuous at |x| = eps sqrt(b) and its minimum sits at |x| = sqrt(b) for eps < 1
+    for eps in (0.1, 0.5, 0.9):
+        b = 2.3
+        edge = eps * math.sqrt(b)
+        lo = stagm.g_eps(np.array([edge * (1 - 1e-12)]), b, eps)[0]
+        hi = stagm.g_eps(np.array([edge]), b, eps)[0]
+        assert abs(lo - hi) < 1e-10
+        rho = np.linspace(0, 3, 300001)
+        assert abs(rho[np.argmin(stagm.g_eps(rho, b, eps))] - math.sqrt(b)) < 1e-4
+    # eps > 1 moves the global minimiser to the origin (Fig. 2 discussion)
+    rho = np.linspace(0, 3, 30001)
+    assert rho[np.argmin(stagm.g_eps(rho, 2.3, 1.5))] == 0.0
+
+
+def test_gradient_finite_difference_and_lipschitz():
+    rng = np.random.default_rng(5)
+    eps = 0.5
+    for _ in range(200):
+        x = complex(rng.standard_normal(), rng.standard_normal())
+        b = float(rng.uniform(0.01, 4))
+        h = 1e-6
+        gr = (stagm.g_eps(x + h, b, eps) - stagm.g_eps(x - h, b, eps)) / (2 * h)
+        gi = (stagm.g_eps(x + 1j * h, b, eps) - stagm.g_eps(x - 1j * h, b, eps)) / (2 * h)
+        if abs(abs(x) - eps * math.sqrt(b)) > 1e-4:
+            assert abs(complex(stagm.grad_g(x, b, eps)) - complex(gr, gi)) < 1e-6
+    L = stagm.lipschitz(eps)
+    x1 = crandn(20000, rng=rng)
+    x2 = crandn(20000, rng=rng)
+    b = rng.uniform(0.0, 4, 20000)
+    ratio = np.abs(stagm.grad_g(x1, b, eps) - stagm.grad_g(x2, b, eps)) / np.abs(x1 - x2)
+    assert ratio.max() <= L + 1e-12
+
+
+# ---------------------------------------------------------------------------
+# T13  geometry: frame-first decomposition (Sec. 2.1, Sec. 3.1) against printed figures
+# ---------------------------------------------------------------------------
+
+def _golden_rows():
+    rows = []
+    with open(os.path.join(GOLDEN, "paper_geometry.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                rows.append(line.split()[:7])
+    return rows
+
+
+@pytest.mark.parametrize("row", _golden_rows())
+def test_geometry_against_paper_figures(row):
+    n, p, step = int(row[0]), int(row[1]), int(row[2])
+    dy, dx = (int(t) for t in row[3].split("x"))
+    off, grid = synthetic.raster_offsets(n, p, step, 0, None)
+    if row[4] != "-":
+        assert grid == (int(row[4]), int(row[4]))
+    sub = synthetic.block_partition(grid, dy, dx)
+    geom = build_geometry(n, n, p, off, sub)
+    if row[5] != "-":
+        counts = [int(np.sum(sub == d)) // grid[0] for d in range(geom.D)]
+        assert counts == [int(t) for t in row[5].split(",")]
+    for d in range(geom.D - 1):
+        assert overlap_width(geom, d, d + 1)[1] == int(row[6]) == p - step
+
+
+def test_geometry_pairs_and_multiplicity_bruteforce():
+    rng = np.random.default_rng(9)
+    off, grid = synthetic.raster_offsets(64, 16, 6, 2, rng)
+    sub = synthetic.block_partition(grid, 3, 3)
+    geom = build_geometry(64, 64, 16, off, sub)
+    # brute force: each subdomain's pixel set = union of its windows' bounding box
+    cover = np.zeros((geom.D, 64, 64), dtype=bool)
+    for d in range(geom.D):
+        js = np.nonzero(sub == d)[0]
+        r0, c0 = off[js, 0].min(), off[js, 1].min()
+        r1, c1 = off[js, 0].max() + 16, off[js, 1].max() + 16
+        cover[d, r0:r1, c0:c1] = True
+    pairs = {(a, b) for a in range(geom.D) for b in range(a + 1, geom.D) if np.any(cover[a] & cover[b])}
+    assert pairs == {(a, b) for (a, b, _) in geom.pairs}
+    assert len(pairs) == 20      # 12 edge + 8 diagonal neighbours of a 3x3 block grid
+    for d in range(geom.D):
+        r0, c0, r1, c1 = geom.rects[d]
+        k_bf = cover[:, r0:r1, c0:c1].sum(axis=0) - 1
+        np.testing.assert_array_equal(multiplicity(geom, d), k_bf)
+    np.testing.assert_array_equal(cover_count(geom), cover.sum(axis=0))
+
+
+def test_geometry_rejects_bad_input():
+    off, grid = synthetic.raster_offsets(32, 8, 4, 0, None)
+    sub = synthetic.block_partition(grid, 1, 2)
+    bad = off.copy()
+    bad[3, 1] = 30
+    with pytest.raises(GeometryError):
+        build_geometry(32, 32, 8, bad, sub)
+    with pytest.raises(GeometryError):
+        build_geometry(32, 32, 8, off, np.where(sub == 1, 2, sub))   # subdomain 1 empty
+
+
+# ---------------------------------------------------------------------------
+# T7  stationarity identities (eqs. Stationary1, Stationary2)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("eta", [0.1, 2.0])
+def test_stationarity_after_each_step(eta):
+    P = oracle_problem(tiny_spec(dy=2, dx=2, n=32, step=4, jitter=1), eta=eta)
+    g, w, f = P["geom"], P["pr"]["w"], P["f"]
+    st = init_state(g)
+    st, _ = od2pm_step(g, w, f, st, P["eps"], eta, P["r"])
+    st, _ = od2pm_step(g, w, f, st, P["eps"], eta, P["r"])
+    # grad G(z^{n+1}) = eta Gamma^{n+1}
+    np.testing.assert_allclose(stagm.grad_g(st.z, f, P["eps"]), eta * st.gamma, atol=1e-12)
+    # eta A_d*(A_d u_d + Gamma_d - z_d) + r sum pi^T Lam_{d,.} = 0
+    X = forward_sub(g, w, st.u)
+    for d in range(g.D):
+        res = eta * adjoint_sub(g, w, X + st.gamma - st.z, d)
+        for (i1, i2, rc) in g.pairs:
+            if d in (i1, i2):
+                e = i2 if d == i1 else i1
+                res[g.restrict(d, rc)] += P["r"] * st.lam[(d, e)]
+        assert np.abs(res).max() < 1e-10
+
+
+def test_truncation_branch_fires_with_large_eta():
+    P = oracle_problem(tiny_spec(n=32, p=16, step=4, radius=6), eta=2.0)
+    g, w, f = P["geom"], P["pr"]["w"], P["f"]
+    st = init_state(g)
+    fired = 0
+    for _ in range(10):
+        X = forward_sub(g, w, st.u)
+        y = st.gamma + X
+        fired += int(np.sum(np.abs(y) < (P["eps"] - (1 - P["eps"]) / 2.0) * np.sqrt(f)))
+        st, _ = od2pm_step(g, w, f, st, P["eps"], 2.0, P["r"])
+    assert fired > 0
+
+
+# ---------------------------------------------------------------------------
+# T8, T10  fixed point and global-phase equivariance
+# ---------------------------------------------------------------------------
+
+def test_noise_free_truth_is_fixed_point():
+    P = oracle_problem(tiny_spec(dy=2, dx=2, n=32, step=4))
+    g, w, f = P["geom"], P["pr"]["w"], P["f"]
+    phase = np.exp(0.7j)
+    ut = P["pr"]["u_true"] * phase
+    st = init_state(g)
+    st.u = [ut[g.rects[d, 0]:g.rects[d, 2], g.rects[d, 1]:g.rects[d, 3]].copy() for d in range(g.D)]
+    new, stats = od2pm_step(g, w, f, st, P["eps"], P["eta"], P["r"])
+    for d in range(g.D):
+        np.testing.assert_allclose(new.u[d], st.u[d], atol=1e-12)
+    assert np.abs(new.gamma).max() < 1e-12
+    assert stats["RF"] < 1e-12
+
+
+def test_global_phase_equivariance():
+    P = oracle_problem(tiny_spec(dy=1, dx=2))
+    g, w, f = P["geom"], P["pr"]["w"], P["f"]
+    # a generic start: with y = 0 somewhere the tie rule sign(0) = +1 is not equivariant
+    rng = np.random.default_rng(2)
+    sa = init_state(g)
+    sa.u = [1.0 + 0.1 * crandn(*a.shape, rng=rng) for a in sa.u]
+    phase = np.exp(-1.3j)
+    sb = sa.copy()
+    sb.u = [phase * a for a in sb.u]
+    a, _ = od2pm_run(g, w, f, P["eps"], P["eta"], P["r"], 6, state=sa)
+    b, _ = od2pm_run(g, w, f, P["eps"], P["eta"], P["r"], 6, state=sb)
+    for d in range(g.D):
+        np.testing.assert_allclose(b.u[d], phase * a.u[d], atol=1e-11)
+
+
+# ---------------------------------------------------------------------------
+# T9  one subdomain = ADMM without decomposition (Table 1, D = 1)
+# ---------------------------------------------------------------------------
+
+def test_one_subdomain_equals_undecomposed_admm():
+    P = oracle_problem(tiny_spec(dy=1, dx=1, n=28, step=4, jitter=1))
+    g, w, f = P["geom"], P["pr"]["w"], P["f"]
+    st, _ = od2pm_run(g, w, f, P["eps"], P["eta"], P["r"], 8)
+    u_full, gamma = admm_undecomposed((28, 28), w, P["pr"]["offsets"], f, P["eps"], P["eta"], 8)
+    r0, c0, r1, c1 = g.rects[0]
+    np.testing.assert_allclose(st.u[0], u_full[r0:r1, c0:c1], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(st.gamma, gamma, rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# T11  the augmented Lagrangian is non-increasing for (r, eta) in K (Lemma 2.6)
+# ---------------------------------------------------------------------------
+
+def test_lagrangian_non_increasing_in_parameter_set():
+    P = oracle_problem(tiny_spec(dy=1, dx=2, n=24, step=4))
+    g, w, f = P["geom"], P["pr"]["w"], P["f"]
+    eps = P["eps"]
+    L = stagm.lipschitz(eps)
+    den = P["den"]
+    nAtA = max(float(a.max()) for a in den)                      # ||A_d* A_d|| (diagonal)
+    nPiA = max(math.sqrt(float(den[d][g.restrict(d, rc)].max()))  # ||pi A_d*||
+               for (i1, i2, rc) in g.pairs for d in (i1, i2))
+    c0 = max(2 * nAtA, nPiA)
+    c1 = 2 * nPiA ** 2
+    eta = 1.1 * max(6 * L + 2 * L * L + 2 * c1 / c0 ** 2 * (L + 1) ** 2, 1.0)
+    r = 1.1 * c0 * eta
+    st = init_state(g)
+    st, _ = od2pm_step(g, w, f, st, eps, eta, r)
+    vals = [augmented_lagrangian(g, w, f, st, eps, eta, r)]
+    for _ in range(15):
+        st, _ = od2pm_step(g, w, f, st, eps, eta, r)
+        vals.append(augmented_lagrangian(g, w, f, st, eps, eta, r))
+    assert all(b <= a + 1e-9 * abs(a) for a, b in zip(vals, vals[1:])), vals
+
+
+# ---------------------------------------------------------------------------
+# T12  convergence to a whole-domain stationary point (remark after Thm 2.8)
+# ---------------------------------------------------------------------------
+
+def test_merged_solution_is_whole_domain_stationary():
+    P = oracle_problem(tiny_spec(dy=1, dx=2, n=24, step=3, jitter=0, radius=3.5))
+    g, w, f = P["geom"], P["pr"]["w"], P["f"]
+    off = P["pr"]["offsets"]
+
+    def opt_residual(u):
+        X = ops.forward(u, w, off)
+        return np.linalg.norm(ops.adjoint(stagm.grad_g(X, f, P["eps"]), w, off, u.shape))
+
+    r0 = opt_residual(np.ones((24, 24), complex))
+    st, hist = od2pm_run(g, w, f, P["eps"], P["eta"], P["r"], 400)
+    u = merge(g, st.u)
+    assert hist[-1]["RF"] < 1e-3 * hist[0]["RF"]
+    assert opt_residual(u) < 1e-3 * r0
+
+
+# ---------------------------------------------------------------------------
+# T18  resume: K1 then K2 iterations equals K1 + K2 iterations, bit for bit
+# ---------------------------------------------------------------------------
+
+def test_resume_is_bit_exact():
+    P = oracle_problem(tiny_spec(dy=2, dx=2, n=32, step=4))
+    g, w, f = P["geom"], P["pr"]["w"], P["f"]
+    a, _ = od2pm_run(g, w, f, P["eps"], P["eta"], P["r"], 7)
+    b, _ = od2pm_run(g, w, f, P["eps"], P["eta"], P["r"], 3)
+    b, _ = od2pm_run(g, w, f, P["eps"], P["eta"], P["r"], 4, state=b.copy())
+    for d in range(g.D):
+        assert np.array_equal(a.u[d], b.u[d])
+    assert np.array_equal(a.gamma, b.gamma)
+
+
+def test_merge_and_snr():
+    P = oracle_problem(tiny_spec(dy=1, dx=2))
+    g = P["geom"]
+    ut = P["pr"]["u_true"]
+    parts = [ut[g.rects[d, 0]:g.rects[d, 2], g.rects[d, 1]:g.rects[d, 3]].copy() for d in range(g.D)]
+    parts[1] = parts[1] + 0.0   # identical copies -> merge returns the image on covered pixels
+    m = merge(g, parts)
+    covered = cover_count(g) > 0
+    np.testing.assert_allclose(m[covered], ut[covered], atol=1e-15)
+    assert snr_db(ut * np.exp(0.4j), ut) > 250   # perfect up to the global phase
+
+
+# ---------------------------------------------------------------------------
+# T14, T15, T16  blind recovery (Sec. 3.2, Algorithm 3)
+# ---------------------------------------------------------------------------
+
+def test_blind_with_frozen_probe_equals_nonblind():
+    P = oracle_problem(tiny_spec(dy=2, dx=2, n=32, step=4))
+    g, w, f = P["geom"], P["pr"]["w"], P["f"]
+    nb, _ = od2pm_run(g, w, f, P["eps"], P["eta"], P["r"], 5)
+    bl, _ = blind.od2bp_run(g, f, w, P["eps"], P["eta"], P["r"], np.inf, 5)
+    for d in range(g.D):
+        np.testing.assert_allclose(bl.u[d], nb.u[d], atol=1e-12)
+    np.testing.assert_allclose(bl.w, w, atol=1e-15)
+
+
+def test_blind_truth_is_fixed_point():
+    P = oracle_problem(tiny_spec(dy=1, dx=2, n=28, step=4))
+    g, w, f = P["geom"], P["pr"]["w"], P["f"]
+    ut = P["pr"]["u_true"]
+    st = blind.init_state(g, w)
+    st.u = [ut[g.rects[d, 0]:g.rects[d, 2], g.rects[d, 1]:g.rects[d, 3]].copy() for d in range(g.D)]
+    new, _ = blind.od2bp_step(g, f, st, P["eps"], P["eta"], P["r"], mu=3.0, gamma_p=0.5)
+    for d in range(g.D):
+        np.testing.assert_allclose(new.u[d], st.u[d], atol=1e-12)
+        np.testing.assert_allclose(new.w_sub[d], w, atol=1e-12)
+    np.testing.assert_allclose(new.w, w, atol=1e-12)
+
+
+def test_support_projection():
+    x = crandn(16, 16)
+    m = (RNG.random((16, 16)) < 0.6).astype(float)
+    px = blind.project_support(x, m)
+    np.testing.assert_allclose(blind.project_support(px, m), px, atol=1e-13)     # idempotent
+    np.testing.assert_allclose(np.fft.fft2(px, norm="ortho") * (1 - m), 0, atol=1e-13)
+    np.testing.assert_allclose(blind.project_support(x, np.ones((16, 16))), x, atol=1e-13)
+
+
+def test_blind_step_probe_update_solves_its_subproblem():
+    # W-step (eq. blind_W) minimises eta/2||B(W,U)-Z+Gamma||^2 + mu/2||W - w + Delta||^2:
+    # its gradient in w_d must vanish at the returned copy.
+    P = oracle_problem(tiny_spec(dy=1, dx=2, n=24, step=4))
+    g, w, f = P["geom"], P["pr"]["w"], P["f"]
+    st = blind.init_state(g, 0.9 * w)
+    st, _ = blind.od2bp_step(g, f, st, P["eps"], P["eta"], P["r"], mu=2.0)
+    prev = st.copy()
+    new, _ = blind.od2bp_step(g, f, prev, P["eps"], P["eta"], P["r"], mu=2.0)
+    from oracle.od2p import local_offsets
+    X = np.empty_like(prev.gamma)
+    for d in range(g.D):
+        X[g.frames_of[d]] = ops.forward(prev.u[d], prev.w_sub[d], local_offsets(g, d))
+    z = stagm.prox(prev.gamma + X, f, P["eps"], P["eta"])
+    gam = prev.gamma + X - z
+    for d in range(g.D):
+        grad = 2.0 * (new.w_sub[d] - new.w + prev.delta[d])
+        for jj, off in zip(g.frames_of[d], local_offsets(g, d)):
+            patch = ops.gather(prev.u[d], off, g.p)
+            resid = ops.fft2(new.w_sub[d] * patch) - z[jj] + gam[jj]
+            grad = grad + P["eta"] / 2.0 * 2 * np.conj(patch) * ops.ifft2(resid)
+        assert np.abs(grad).max() < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# T17  gradient of the amplitude loss against central finite differences
+# ---------------------------------------------------------------------------
+
+def test_amplitude_loss_gradient_finite_difference():
+    rng = np.random.default_rng(17)
+    off, _, w = _small_scan(n=24, p=8, step=4)
+    ut = 0.5 + 0.5 * rng.random((24, 24)) * np.exp(1j * rng.random((24, 24)))
+    f = ops.intensities(ut, w, off)
+    u = ut * (1 + 0.1 * crandn(24, 24, rng=rng))
+    L, gu, gw = amploss.grad(u, w, off, f)
+    h = 1e-6
+    for (a, b) in [(3, 4), (10, 12), (20, 7)]:
+        e = np.zeros_like(u)
+        e[a, b] = 1
+        dr = (amploss.loss(u + h * e, w, off, f) - amploss.loss(u - h * e, w, off, f)) / (2 * h)
+        di = (amploss.loss(u + 1j * h * e, w, off, f) - amploss.loss(u - 1j * h * e, w, off, f)) / (2 * h)
+        assert abs(gu[a, b] - complex(dr, di)) < 1e-6 * max(1.0, abs(gu[a, b]))
+    for (a, b) in [(2, 3), (4, 4)]:
+        e = np.zeros_like(w)
+        e[a, b] = 1
+        dr = (amploss.loss(u, w + h * e, off, f) - amploss.loss(u, w - h * e, off, f)) / (2 * h)
+        di = (amploss.loss(u, w + 1j * h * e, off, f) - amploss.loss(u, w - 1j * h * e, off, f)) / (2 * h)
+        assert abs(gw[a, b] - complex(dr, di)) < 1e-6 * max(1.0, abs(gw[a, b]))
+    # at the truth the loss and both gradients vanish
+    L0, gu0, gw0 = amploss.grad(ut, w, off, f)
+    assert L0 < 1e-20 and np.abs(gu0).max() < 1e-10 and np.abs(gw0).max() < 1e-10
