@@ -1,0 +1,10 @@
+"""Overlapping-domain-decomposition ptychography (OD2P / OD2Pm / OD2BP) on MI355X.
+
+The hot path lives in libodp.so (HIP kernels for gfx950 behind the C ABI of
+include/odp.h); this package is its thin binding.  Importing it does not load
+the library; the first call does, and fails loudly if it was not built.
+"""
+from ._lib import (ODP_DFT_SPLIT_BF16, ODP_FFT_F32, EXPORTS, OdpError, lib)  # noqa: F401
+from .api import Geometry, Plan, State, prox_stagm  # noqa: F401
+
+__version__ = "0.1.0"

@@ -1,0 +1,233 @@
+"""Python binding of libodp.so.  Argument marshalling only: every step runs in the
+HIP kernels; PyTorch supplies device memory and the stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from ._lib import (ODP_FFT_F32, PlanInfo, Problem, StateLayout, check, lib)
+
+
+def _stream(stream=None) -> C.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None) -> C.c_void_p:
+    if t is None:
+        return C.c_void_p(0)
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _c64(t: torch.Tensor, shape=None) -> torch.Tensor:
+    if t.dtype != torch.complex64:
+        raise TypeError("expected complex64")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def prox_stagm(y: torch.Tensor, sqrt_f: torch.Tensor, eps: float, lam: float,
+               out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Elementwise Prox_{G_eps; lam}(y) against sqrt(f) (odp_prox_stagm)."""
+    _c64(y)
+    if sqrt_f.dtype != torch.float32 or sqrt_f.numel() != y.numel():
+        raise ValueError("sqrt_f must be float32 with y's element count")
+    z = torch.empty_like(y) if out is None else out
+    check(lib().odp_prox_stagm(_ptr(y), _ptr(sqrt_f), y.numel(), float(eps), float(lam), _ptr(z),
+                               _stream(stream)))
+    return z
+
+
+@dataclass
+class Geometry:
+    rects: np.ndarray      # [D,4] (r0, c0, r1, c1)
+    usub_off: np.ndarray   # [D]
+    pairs: np.ndarray      # [n_pairs, 6] (i1, i2, r0, c0, r1, c1)
+    lam_off: np.ndarray    # [n_pairs]
+    cover: np.ndarray      # [H, W]
+
+
+class State:
+    """One device state buffer of a plan (u_d, Gamma, Lam; blind: w, w_d, Delta)."""
+
+    def __init__(self, plan: "Plan", buf: torch.Tensor):
+        self.plan = plan
+        self.buf = buf
+
+    def _view(self, off: int, n: int) -> torch.Tensor:
+        return self.buf[off: off + 8 * n].view(torch.complex64)
+
+    def u_sub(self) -> list[torch.Tensor]:
+        g = self.plan.geometry()
+        out = []
+        for d in range(self.plan.info.D):
+            r0, c0, r1, c1 = (int(v) for v in g.rects[d])
+            base = self.plan.layout.u_sub + 8 * int(g.usub_off[d])
+            out.append(self._view(base, (r1 - r0) * (c1 - c0)).view(r1 - r0, c1 - c0))
+        return out
+
+    def gamma(self) -> torch.Tensor:
+        i = self.plan.info
+        return self._view(self.plan.layout.gamma, i.J * i.p * i.p).view(i.J, i.p, i.p)
+
+    def lam(self) -> dict:
+        """{(a, b): Lam_{a,b}} on Omega_a cap Omega_b for both orders of every pair."""
+        g = self.plan.geometry()
+        out = {}
+        for q in range(len(g.pairs)):
+            a, b, r0, c0, r1, c1 = (int(v) for v in g.pairs[q])
+            h, w = r1 - r0, c1 - c0
+            both = self._view(self.plan.layout.lam + 8 * int(g.lam_off[q]), 2 * h * w).view(2, h, w)
+            out[(a, b)] = both[0]
+            out[(b, a)] = both[1]
+        return out
+
+    def probe(self) -> torch.Tensor:
+        p = self.plan.info.p
+        return self._view(self.plan.layout.w, p * p).view(p, p)
+
+    def probe_copies(self) -> torch.Tensor:
+        i = self.plan.info
+        return self._view(self.plan.layout.w_sub, i.D * i.p * i.p).view(i.D, i.p, i.p)
+
+    def probe_multipliers(self) -> torch.Tensor:
+        i = self.plan.info
+        return self._view(self.plan.layout.delta, i.D * i.p * i.p).view(i.D, i.p, i.p)
+
+    def clone(self) -> "State":
+        return State(self.plan, self.buf.clone())
+
+
+class Plan:
+    """A validated problem (odp_plan) plus its device workspace once bound."""
+
+    def __init__(self, H: int, W: int, p: int, offsets, frame_sub, D: int | None = None,
+                 eps: float = 0.5, eta: float = 0.1, r: float = 0.0, mu: float = 0.0,
+                 gamma: float = 0.0, transform: int = ODP_FFT_F32, blind: bool = False,
+                 probe_fmask=None):
+        L = lib()
+        self._off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32).reshape(-1, 2))
+        self._sub = np.ascontiguousarray(np.asarray(frame_sub, dtype=np.int32).reshape(-1))
+        self._mask = None if probe_fmask is None else np.ascontiguousarray(np.asarray(probe_fmask, dtype=np.uint8))
+        if D is None:
+            D = int(self._sub.max()) + 1 if len(self._sub) else 0
+        prob = Problem(H=H, W=W, p=p, J=len(self._off),
+                       offsets=self._off.ctypes.data_as(C.POINTER(C.c_int32)), D=D,
+                       frame_sub=self._sub.ctypes.data_as(C.POINTER(C.c_int32)),
+                       eps=eps, eta=eta, r=r, mu=mu, gamma=gamma, transform=transform,
+                       blind=1 if blind else 0,
+                       probe_fmask=(self._mask.ctypes.data_as(C.POINTER(C.c_uint8))
+                                    if self._mask is not None else None))
+        h = C.c_void_p()
+        check(L.odp_plan_create(C.byref(prob), C.byref(h)))
+        self._h = h
+        self.info = PlanInfo()
+        check(L.odp_plan_get_info(self._h, C.byref(self.info)))
+        self.layout = StateLayout()
+        check(L.odp_state_get_layout(self._h, C.byref(self.layout)))
+        self.params = dict(eps=eps, eta=eta, r=r, mu=mu, gamma=gamma)
+        self.blind = blind
+        self._geom = None
+        self.workspace = None
+        self._keep = ()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().odp_plan_destroy(h)
+            self._h = None
+
+    # ---- geometry exports (host, no device needed) ----
+    def geometry(self) -> Geometry:
+        if self._geom is None:
+            i = self.info
+            rects = np.zeros((i.D, 4), np.int32)
+            uoff = np.zeros(i.D, np.int64)
+            pairs = np.zeros((max(i.n_pairs, 0), 6), np.int32)
+            loff = np.zeros(max(i.n_pairs, 0), np.int64)
+            cover = np.zeros((i.H, i.W), np.int32)
+            L = lib()
+            check(L.odp_plan_get_rects(self._h, rects.ctypes.data, uoff.ctypes.data))
+            if i.n_pairs:
+                check(L.odp_plan_get_pairs(self._h, pairs.ctypes.data, loff.ctypes.data))
+            check(L.odp_plan_get_cover(self._h, cover.ctypes.data))
+            self._geom = Geometry(rects, uoff, pairs, loff, cover)
+        return self._geom
+
+    # ---- device side ----
+    def bind(self, sqrt_f: torch.Tensor, w: torch.Tensor, stream=None) -> "Plan":
+        i = self.info
+        if sqrt_f.dtype != torch.float32 or tuple(sqrt_f.shape) != (i.J, i.p, i.p):
+            raise ValueError("sqrt_f must be float32 [J, p, p]")
+        _c64(w, (i.p, i.p))
+        self.workspace = torch.empty(i.workspace_bytes, dtype=torch.uint8, device=sqrt_f.device)
+        check(lib().odp_plan_bind(self._h, _ptr(self.workspace), _ptr(sqrt_f), _ptr(w), _stream(stream)))
+        self._keep = (sqrt_f, w)
+        return self
+
+    def illum_max(self) -> float:
+        v = C.c_double()
+        check(lib().odp_plan_illum_max(self._h, C.byref(v)))
+        return v.value
+
+    def set_params(self, stream=None, **kw) -> None:
+        self.params.update(kw)
+        p = self.params
+        check(lib().odp_plan_set_params(self._h, p["eps"], p["eta"], p["r"], p["mu"], p["gamma"],
+                                        _stream(stream)))
+
+    def forward(self, u: torch.Tensor, w: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+        i = self.info
+        _c64(u, (i.H, i.W))
+        _c64(w, (i.p, i.p))
+        out = torch.empty((i.J, i.p, i.p), dtype=torch.complex64, device=u.device) if out is None else out
+        _c64(out, (i.J, i.p, i.p))
+        check(lib().odp_forward(self._h, _ptr(u), _ptr(w), _ptr(out), _stream(stream)))
+        return out
+
+    def adjoint(self, frames: torch.Tensor, w: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+        i = self.info
+        _c64(frames, (i.J, i.p, i.p))
+        _c64(w, (i.p, i.p))
+        out = torch.empty((i.H, i.W), dtype=torch.complex64, device=frames.device) if out is None else out
+        _c64(out, (i.H, i.W))
+        check(lib().odp_adjoint(self._h, _ptr(frames), _ptr(w), _ptr(out), _stream(stream)))
+        return out
+
+    def new_state(self, w0: torch.Tensor | None = None, device=None, stream=None) -> State:
+        dev = device if device is not None else self.workspace.device
+        buf = torch.empty(self.info.state_bytes, dtype=torch.uint8, device=dev)
+        check(lib().odp_state_init(self._h, _ptr(buf), _ptr(w0), _stream(stream)))
+        return State(self, buf)
+
+    def iterate(self, state: State, n_iter: int, stats: bool = False, stream=None):
+        st = (torch.empty((n_iter, 3), dtype=torch.float64, device=state.buf.device)
+              if stats and n_iter > 0 else None)
+        check(lib().odp_admm_iterate(self._h, _ptr(state.buf), int(n_iter), _ptr(st), _stream(stream)))
+        return st
+
+    def merge(self, state: State, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        i = self.info
+        out = torch.empty((i.H, i.W), dtype=torch.complex64, device=state.buf.device) if out is None else out
+        check(lib().odp_merge(self._h, _ptr(state.buf), _ptr(out), _stream(stream)))
+        return out
+
+    def amp_loss(self, u: torch.Tensor, w: torch.Tensor, grad_u: bool = True, grad_w: bool = True,
+                 stream=None):
+        i = self.info
+        _c64(u, (i.H, i.W))
+        _c64(w, (i.p, i.p))
+        loss = torch.empty(1, dtype=torch.float64, device=u.device)
+        gu = torch.empty_like(u) if grad_u else None
+        gw = torch.empty_like(w) if grad_w else None
+        check(lib().odp_amp_loss(self._h, _ptr(u), _ptr(w), _ptr(loss), _ptr(gu), _ptr(gw), _stream(stream)))
+        return loss, gu, gw

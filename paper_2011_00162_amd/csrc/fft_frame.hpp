@@ -1,0 +1,337 @@
+// fft_frame.hpp -- 2-D unitary DFT of one p x p frame per workgroup, for gfx950.
+//
+// The frame transform F of the measurement model (Sec. 2 of the paper: the
+// normalized 2-D DFT) is computed as a three-step Cooley-Tukey factorisation of
+// each axis, p = 16 * N2:
+//     row index r = N2*r1 + r2,  frequency kr = k1 + 16*k2   (same for columns)
+//     F_p x (kr) = sum_r2 W_N2^{r2 k2} * W_p^{r2 k1} * [ sum_r1 W_16^{r1 k1} x(N2 r1 + r2) ]
+// Stage A: radix-16 DFT over r1 of every (r2, column) line, in registers;
+//          twiddle W_p^{r2 k1}; exchange through LDS.
+// Stage B: the same over the column index c1, in place in LDS.
+// Stage C: the N2 x N2 DFT over (r2, c2) of every (k1_row, k1_col) block.
+// Each thread holds 16 complex values in every stage (T = p*p/16 threads).
+// LDS rows are padded by N2 complex values so that the stage-B column reads of a
+// wavefront hit all 64 banks once per half-wave; stage-C reads are contiguous
+// runs of N2 values (128-bit loads).
+//
+// The inverse runs the stages backwards with conjugated twiddles.  Neither
+// direction scales; the caller applies 1/p per direction (unitary F).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace odp {
+
+__device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 c_sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 c_mul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 c_mulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 c_scale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 c_rot(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+// multiply by W^m (forward, W = exp(-2 pi i/n)) or its conjugate (inverse), tw = W^m
+template <bool INV>
+__device__ __forceinline__ float2 c_tw(float2 a, float2 tw) {
+  return INV ? c_mulc(a, tw) : c_mul(a, tw);
+}
+
+// cos(2 pi m / 16) and sin(2 pi m / 16), m = 0..15, from the closed forms
+// cos(pi/8) = sqrt(2 + sqrt 2)/2, sin(pi/8) = sqrt(2 - sqrt 2)/2, cos(pi/4) = sqrt(2)/2.
+#define ODP_C8 0.92387953251128675613f
+#define ODP_S8 0.38268343236508977173f
+#define ODP_R2 0.70710678118654752440f
+
+__device__ __forceinline__ float2 w16(int m) {  // forward twiddle exp(-2 pi i m / 16)
+  // m is a compile-time constant after unrolling
+  const float c[16] = {1.f, ODP_C8, ODP_R2, ODP_S8, 0.f, -ODP_S8, -ODP_R2, -ODP_C8,
+                       -1.f, -ODP_C8, -ODP_R2, -ODP_S8, 0.f, ODP_S8, ODP_R2, ODP_C8};
+  const float s[16] = {0.f, ODP_S8, ODP_R2, ODP_C8, 1.f, ODP_C8, ODP_R2, ODP_S8,
+                       0.f, -ODP_S8, -ODP_R2, -ODP_C8, -1.f, -ODP_C8, -ODP_R2, -ODP_S8};
+  return make_float2(c[m & 15], -s[m & 15]);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft2(float2& a, float2& b) {
+  float2 t = a;
+  a = c_add(t, b);
+  b = c_sub(t, b);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2& x3) {
+  float2 s02 = c_add(x0, x2), d02 = c_sub(x0, x2);
+  float2 s13 = c_add(x1, x3), d13 = c_rot<INV>(c_sub(x1, x3));
+  x0 = c_add(s02, s13);
+  x2 = c_sub(s02, s13);
+  x1 = c_add(d02, d13);
+  x3 = c_sub(d02, d13);
+}
+
+// In-place length-8 DFT, natural order in and out (8 = 4 x 2, n = 2 n1 + n2).
+template <bool INV>
+__device__ __forceinline__ void dft8(float2* v) {
+  dft4<INV>(v[0], v[2], v[4], v[6]);   // n2 = 0 -> a0[k1] at v[2 k1]
+  dft4<INV>(v[1], v[3], v[5], v[7]);   // n2 = 1 -> a1[k1] at v[2 k1 + 1]
+  // twiddle W8^{k1} on a1: W8^1 = (r, -r), W8^2 = -i, W8^3 = (-r, -r)
+  v[3] = c_tw<INV>(v[3], make_float2(ODP_R2, -ODP_R2));
+  v[5] = c_rot<INV>(v[5]);
+  v[7] = c_tw<INV>(v[7], make_float2(-ODP_R2, -ODP_R2));
+  float2 o[8];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    float2 a = v[2 * k1], b = v[2 * k1 + 1];
+    o[k1] = c_add(a, b);       // k2 = 0
+    o[k1 + 4] = c_sub(a, b);   // k2 = 1
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = o[k];
+}
+
+// In-place length-16 DFT, natural order in and out (16 = 4 x 4, n = 4 n1 + n2).
+template <bool INV>
+__device__ __forceinline__ void dft16(float2* v) {
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft4<INV>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+  // now v[4 k1 + n2] = a[n2][k1]; twiddle W16^{n2 k1}
+#pragma unroll
+  for (int k1 = 1; k1 < 4; ++k1)
+#pragma unroll
+    for (int n2 = 1; n2 < 4; ++n2) v[4 * k1 + n2] = c_tw<INV>(v[4 * k1 + n2], w16(n2 * k1));
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) dft4<INV>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+  // v[4 k1 + k2] = X[k1 + 4 k2]: transpose to natural order
+  float2 o[16];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) o[k1 + 4 * k2] = v[4 * k1 + k2];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = o[k];
+}
+
+template <int P>
+struct Frame {
+  static constexpr int N2 = P / 16;      // second radix per axis
+  static constexpr int T = P * N2;       // threads per frame = p*p/16
+  static constexpr int LP = P + N2;      // padded LDS row pitch (complex elements)
+  static constexpr int LDS = P * LP;     // LDS complex elements per frame
+  static constexpr int NC = (N2 * N2 >= 16) ? 1 : 16 / (N2 * N2);  // stage-C blocks per thread
+
+  // Stage-A line of thread t: column and r2.  Value r1 sits at row N2*r1 + r2.
+  __device__ static __forceinline__ int a_col(int t) { return t % P; }
+  __device__ static __forceinline__ int a_r2(int t) { return t / P; }
+
+  // ---- forward ---------------------------------------------------------------
+  // v: the 16 spatial values of this thread's stage-A line (already multiplied
+  // by the probe).  On return v holds 16 frequencies, see freq().
+  __device__ static void forward(float2* v, float2* lds, const float2* __restrict__ tw, int t) {
+    const int col = a_col(t), r2 = a_r2(t);
+    dft16<false>(v);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      float2 x = (r2 == 0 || k == 0) ? v[k] : c_mul(v[k], tw[r2 * k]);
+      lds[(N2 * k + r2) * LP + col] = x;
+    }
+    __syncthreads();
+    stage_b<false>(lds, tw, t);
+    __syncthreads();
+    stage_c_fwd(v, lds, t);
+  }
+
+  // ---- inverse ---------------------------------------------------------------
+  // v: 16 frequencies in the freq() layout.  On return v holds the 16 spatial
+  // values of this thread's stage-A line (unscaled inverse DFT).
+  __device__ static void inverse(float2* v, float2* lds, const float2* __restrict__ tw, int t) {
+    stage_c_inv(v, lds, t);
+    __syncthreads();
+    stage_b<true>(lds, tw, t);
+    __syncthreads();
+    const int col = a_col(t), r2 = a_r2(t);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      float2 x = lds[(N2 * k + r2) * LP + col];
+      v[k] = (r2 == 0 || k == 0) ? x : c_mulc(x, tw[r2 * k]);
+    }
+    dft16<true>(v);
+  }
+
+  template <bool INV>
+  __device__ static __forceinline__ void stage_b(float2* lds, const float2* __restrict__ tw, int t) {
+    const int c2 = t % N2, R = t / N2;
+    float2 v[16];
+    float2* row = lds + R * LP + c2;
+    if (INV) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        float2 x = row[N2 * k];
+        v[k] = (c2 == 0 || k == 0) ? x : c_mulc(x, tw[c2 * k]);
+      }
+      dft16<true>(v);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) row[N2 * k] = v[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) v[k] = row[N2 * k];
+      dft16<false>(v);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) row[N2 * k] = (c2 == 0 || k == 0) ? v[k] : c_mul(v[k], tw[c2 * k]);
+    }
+  }
+
+  // Natural frequency (kr, kc) of value e held by thread t after forward().
+  __device__ static __forceinline__ void freq(int t, int e, int& kr, int& kc) {
+    if constexpr (P == 32) {            // 4 blocks of 2x2 per thread
+      const int b = t + 64 * (e >> 2);
+      const int k1c = b & 15, k1r = b >> 4;
+      const int k2r = (e >> 1) & 1, k2c = e & 1;
+      kr = k1r + 16 * k2r;
+      kc = k1c + 16 * k2c;
+    } else if constexpr (P == 64) {     // one 4x4 block per thread
+      const int k1c = t & 15, k1r = t >> 4;
+      kr = k1r + 16 * (e >> 2);
+      kc = k1c + 16 * (e & 3);
+    } else {                            // P == 128: two lines of 8 per thread
+      const int L = t + 1024 * (e >> 3);
+      const int k1c = L & 15, k2r = (L >> 4) & 7, k1r = L >> 7;
+      kr = k1r + 16 * k2r;
+      kc = k1c + 16 * (e & 7);
+    }
+  }
+
+  __device__ static __forceinline__ void stage_c_fwd(float2* v, float2* lds, int t) {
+    if constexpr (P == 32) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int b = t + 64 * q, k1c = b & 15, k1r = b >> 4;
+        const float2* base = lds + (2 * k1r) * LP + 2 * k1c;
+        float4 r0 = *reinterpret_cast<const float4*>(base);
+        float4 r1 = *reinterpret_cast<const float4*>(base + LP);
+        float2 a00 = make_float2(r0.x, r0.y), a01 = make_float2(r0.z, r0.w);
+        float2 a10 = make_float2(r1.x, r1.y), a11 = make_float2(r1.z, r1.w);
+        dft2<false>(a00, a10);
+        dft2<false>(a01, a11);
+        dft2<false>(a00, a01);
+        dft2<false>(a10, a11);
+        v[4 * q + 0] = a00; v[4 * q + 1] = a01; v[4 * q + 2] = a10; v[4 * q + 3] = a11;
+      }
+    } else if constexpr (P == 64) {
+      const int k1c = t & 15, k1r = t >> 4;
+      const float2* base = lds + (4 * k1r) * LP + 4 * k1c;
+      float2 a[16];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float4 lo = *reinterpret_cast<const float4*>(base + r * LP);
+        float4 hi = *reinterpret_cast<const float4*>(base + r * LP + 2);
+        a[4 * r + 0] = make_float2(lo.x, lo.y); a[4 * r + 1] = make_float2(lo.z, lo.w);
+        a[4 * r + 2] = make_float2(hi.x, hi.y); a[4 * r + 3] = make_float2(hi.z, hi.w);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) dft4<false>(a[c], a[4 + c], a[8 + c], a[12 + c]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dft4<false>(a[4 * r], a[4 * r + 1], a[4 * r + 2], a[4 * r + 3]);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] = a[e];
+    } else {  // P == 128: DFT8 over r2 (lines k1r,k1c,c2), then DFT8 over c2 (lines k1r,k2r,k1c)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int L = t + 1024 * q;
+        const int c2 = L & 7, k1c = (L >> 3) & 15, k1r = L >> 7;
+        float2* base = lds + (8 * k1r) * LP + 8 * k1c + c2;
+        float2 a[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) a[r] = base[r * LP];
+        dft8<false>(a);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) base[r * LP] = a[r];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int L = t + 1024 * q;
+        const int k1c = L & 15, k2r = (L >> 4) & 7, k1r = L >> 7;
+        const float2* base = lds + (8 * k1r + k2r) * LP + 8 * k1c;
+        float2 a[8];
+#pragma unroll
+        for (int c = 0; c < 8; c += 2) {
+          float4 x = *reinterpret_cast<const float4*>(base + c);
+          a[c] = make_float2(x.x, x.y);
+          a[c + 1] = make_float2(x.z, x.w);
+        }
+        dft8<false>(a);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v[8 * q + c] = a[c];
+      }
+    }
+  }
+
+  // Exact reverse of stage_c_fwd (inverse DFTs, results written back to LDS).
+  __device__ static __forceinline__ void stage_c_inv(float2* v, float2* lds, int t) {
+    if constexpr (P == 32) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int b = t + 64 * q, k1c = b & 15, k1r = b >> 4;
+        float2* base = lds + (2 * k1r) * LP + 2 * k1c;
+        float2 a00 = v[4 * q + 0], a01 = v[4 * q + 1], a10 = v[4 * q + 2], a11 = v[4 * q + 3];
+        dft2<true>(a00, a01);
+        dft2<true>(a10, a11);
+        dft2<true>(a00, a10);
+        dft2<true>(a01, a11);
+        *reinterpret_cast<float4*>(base) = make_float4(a00.x, a00.y, a01.x, a01.y);
+        *reinterpret_cast<float4*>(base + LP) = make_float4(a10.x, a10.y, a11.x, a11.y);
+      }
+    } else if constexpr (P == 64) {
+      const int k1c = t & 15, k1r = t >> 4;
+      float2* base = lds + (4 * k1r) * LP + 4 * k1c;
+      float2 a[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) a[e] = v[e];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dft4<true>(a[4 * r], a[4 * r + 1], a[4 * r + 2], a[4 * r + 3]);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) dft4<true>(a[c], a[4 + c], a[8 + c], a[12 + c]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        *reinterpret_cast<float4*>(base + r * LP) =
+            make_float4(a[4 * r].x, a[4 * r].y, a[4 * r + 1].x, a[4 * r + 1].y);
+        *reinterpret_cast<float4*>(base + r * LP + 2) =
+            make_float4(a[4 * r + 2].x, a[4 * r + 2].y, a[4 * r + 3].x, a[4 * r + 3].y);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int L = t + 1024 * q;
+        const int k1c = L & 15, k2r = (L >> 4) & 7, k1r = L >> 7;
+        float2* base = lds + (8 * k1r + k2r) * LP + 8 * k1c;
+        float2 a[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) a[c] = v[8 * q + c];
+        dft8<true>(a);
+#pragma unroll
+        for (int c = 0; c < 8; c += 2)
+          *reinterpret_cast<float4*>(base + c) = make_float4(a[c].x, a[c].y, a[c + 1].x, a[c + 1].y);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int L = t + 1024 * q;
+        const int c2 = L & 7, k1c = (L >> 3) & 15, k1r = L >> 7;
+        float2* base = lds + (8 * k1r) * LP + 8 * k1c + c2;
+        float2 a[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) a[r] = base[r * LP];
+        dft8<true>(a);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) base[r * LP] = a[r];
+      }
+    }
+  }
+};
+
+}  // namespace odp

@@ -1,0 +1,566 @@
+// kernels.hip -- HIP kernels of the OD2P / OD2Pm / OD2BP hot path for gfx950.
+//
+// Frame kernels run one workgroup per scan frame (p*p/16 threads, 16 complex
+// values per thread, frame transform through LDS, see fft_frame.hpp).  Pixel
+// kernels run one 256-thread workgroup per 4 x 64 tile of a cell (a rectangle
+// covered by one fixed set of subdomains), so every descriptor load is uniform.
+#include <hip/hip_runtime.h>
+
+#include "fft_frame.hpp"
+#include "odp_internal.hpp"
+
+namespace odp {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide sum in a fixed order (deterministic); every thread gets the total.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  constexpr int NW = NT / 64;
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) t += sh[i];
+  return t;
+}
+
+__device__ __forceinline__ void atomic_add_c(float2* p, float2 v) {
+  unsafeAtomicAdd(&p->x, v.x);
+  unsafeAtomicAdd(&p->y, v.y);
+}
+
+// Closed-form proximal map of the ST-AGM (eq. Prox_sol), with precomputed
+// coefficients: thr = eps - (1-eps)/lam (truncated branch when |y| < thr*sqrt f),
+// ctr = lam/(lam - (1-eps)/eps) (only used when thr > 0), ca = 1/(1+lam),
+// cb = lam/(1+lam).  sign(0) = +1.
+struct ProxC {
+  float thr, ctr, ca, cb;
+};
+
+__host__ __device__ inline ProxC prox_coeffs(double eps, double lam) {
+  const double kappa = (1.0 - eps) / eps;
+  ProxC c;
+  c.thr = (float)(eps - (1.0 - eps) / lam);
+  c.ctr = lam > kappa ? (float)(lam / (lam - kappa)) : 0.0f;
+  c.ca = (float)(1.0 / (1.0 + lam));
+  c.cb = (float)(lam / (1.0 + lam));
+  return c;
+}
+
+__device__ __forceinline__ float2 prox_stagm(float2 y, float sf, const ProxC& c) {
+  const float ay = sqrtf(y.x * y.x + y.y * y.y);
+  const float rho = (ay < c.thr * sf) ? fmaxf(0.0f, ay * c.ctr) : fmaf(sf, c.ca, ay * c.cb);
+  if (ay > 0.0f) {
+    const float s = rho / ay;
+    return make_float2(y.x * s, y.y * s);
+  }
+  return make_float2(rho, 0.0f);
+}
+
+// g_eps(x; b) of eq. obj-1 from |x| and sqrt(b), in FP64
+__device__ __forceinline__ double g_eps(double ax, double sb, double eps) {
+  return (ax < eps * sb) ? 0.5 * (1.0 - eps) * (sb * sb - ax * ax / eps) : 0.5 * (ax - sb) * (ax - sb);
+}
+
+__device__ __forceinline__ int sweep_frame(int32_t chunk, int32_t J, const int32_t* order) {
+  // XCD-aware slicing: workgroup b runs on XCD b % 8; each XCD takes a
+  // contiguous slice of the subdomain-grouped frame order, so neighbouring
+  // windows (which share image pixels and accumulators) share one L2.
+  const int b = blockIdx.x;
+  const int pos = (b % NXCD) * chunk + b / NXCD;
+  return pos < J ? order[pos] : -1;
+}
+
+// ---------------------------------------------------------------------------
+// K1: frame sweep (Alg. 2 Steps 1-2 for the frames, and the A_d* part of Step 3)
+//   X = F(w o S_j u_d); y = Gamma + X; z = Prox(y); Gamma <- y - z;
+//   non-blind: num_d += S_j^T(conj(w) o F^{-1}(z - Gamma))
+//   blind:     phi_j = F^{-1}(z - Gamma) (the probe and image steps need it twice)
+// ---------------------------------------------------------------------------
+template <int P, bool BLIND, bool STATS>
+__global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
+  using F = Frame<P>;
+  __shared__ float2 lds[F::LDS];
+  __shared__ double red[F::T / 64];
+  const int j = sweep_frame(a.chunk, a.J, a.order);
+  if (j < 0) return;  // uniform over the workgroup
+  const int t = threadIdx.x;
+  const FrameDesc fd = a.frames[j];
+  const float2* w = a.w + (a.w_per_sub ? (size_t)fd.sub * P * P : 0);
+  const int col = F::a_col(t), r2 = F::a_r2(t);
+  const float inv_p = 1.0f / (float)P;
+
+  float2 v[16];
+#pragma unroll
+  for (int r1 = 0; r1 < 16; ++r1) {
+    const int row = F::N2 * r1 + r2;
+    v[r1] = c_mul(a.u[fd.base + (int64_t)row * fd.pitch + col], w[row * P + col]);
+  }
+  F::forward(v, lds, a.tw, t);
+
+  double mis = 0.0, gsum = 0.0;
+  const size_t fbase = (size_t)j * P * P;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    int kr, kc;
+    F::freq(t, e, kr, kc);
+    const size_t idx = fbase + kr * P + kc;
+    const float2 X = c_scale(v[e], inv_p);
+    const float sf = a.sqrt_f[idx];
+    const float2 y = c_add(a.gamma[idx], X);
+    const float2 z = prox_stagm(y, sf, pc);
+    const float2 g = c_sub(y, z);
+    a.gamma[idx] = g;
+    v[e] = c_sub(z, g);
+    if (STATS) {
+      const double ax = sqrt((double)X.x * X.x + (double)X.y * X.y);
+      mis += fabs(ax - (double)sf);
+      gsum += g_eps(ax, (double)sf, (double)a.eps);
+    }
+  }
+  if (STATS) {
+    mis = block_sum<F::T>(mis, red);
+    gsum = block_sum<F::T>(gsum, red);
+    if (t == 0) {
+      a.part[2 * j] = mis;
+      a.part[2 * j + 1] = gsum;
+    }
+  }
+  __syncthreads();  // stage-C reads of all threads done before inverse writes reuse LDS
+  F::inverse(v, lds, a.tw, t);
+#pragma unroll
+  for (int r1 = 0; r1 < 16; ++r1) {
+    const int row = F::N2 * r1 + r2;
+    const float2 phi = c_scale(v[r1], inv_p);
+    if (BLIND) {
+      a.phi[fbase + row * P + col] = phi;
+    } else {
+      atomic_add_c(&a.num[fd.base + (int64_t)row * fd.pitch + col], c_mulc(phi, w[row * P + col]));
+    }
+  }
+}
+
+hipError_t launch_sweep(int p, const SweepArgs& a, hipStream_t s) {
+  const ProxC pc = prox_coeffs(a.eps, a.eta);
+  const dim3 grid(NXCD * a.chunk);
+  const bool st = a.part != nullptr, bl = a.phi != nullptr;
+#define ODP_SWEEP(PP)                                                                        \
+  if (p == PP) {                                                                             \
+    constexpr int T = Frame<PP>::T;                                                          \
+    if (bl && st) hipLaunchKernelGGL((k_sweep<PP, true, true>), grid, dim3(T), 0, s, a, pc);   \
+    else if (bl) hipLaunchKernelGGL((k_sweep<PP, true, false>), grid, dim3(T), 0, s, a, pc);   \
+    else if (st) hipLaunchKernelGGL((k_sweep<PP, false, true>), grid, dim3(T), 0, s, a, pc);   \
+    else hipLaunchKernelGGL((k_sweep<PP, false, false>), grid, dim3(T), 0, s, a, pc);          \
+    return hipGetLastError();                                                                \
+  }
+  ODP_SWEEP(32)
+  ODP_SWEEP(64)
+  ODP_SWEEP(128)
+#undef ODP_SWEEP
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// K3: pixel update (Alg. 2 Steps 1 (v), 3 (u) and 4 (Lam)) on one cell tile.
+//   v_{a,b} = (u_a + u_b + Lam_{a,b} + Lam_{b,a}) / 2        from the iterate n
+//   u_d     = (eta num_d + r sum_{e != d} (v_{d,e} - Lam_{d,e}) + gamma u_d) * rcp_d
+//   Lam_{d,e} += u_d^{new} - v_{d,e}
+// Pairs (s, t), s < t, of the cell's subdomain list are stored at index
+// t(t-1)/2 + s, so every register index below is a compile-time constant.
+// ---------------------------------------------------------------------------
+template <bool STATS>
+__global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
+  __shared__ double red[4];
+  const TileDesc td = a.tiles[blockIdx.x];
+  const CellDesc* cd = a.cells + td.cell;
+  const int m = cd->m;
+  const int tr = threadIdx.x / TILE_COLS, tc = threadIdx.x % TILE_COLS;
+  const bool act = tr < td.nr && tc < td.nc;
+  const int y = td.r0 + tr, x = td.c0 + tc;
+
+  float2 uo[MAXS], un[MAXS];
+  if (act) {
+    float2 acc[MAXS];
+    int64_t idx[MAXS];
+#pragma unroll
+    for (int s = 0; s < MAXS; ++s) {
+      if (s < m) {
+        idx[s] = cd->ubase[s] + (int64_t)y * cd->upitch[s] + x;
+        uo[s] = a.u[idx[s]];
+        acc[s] = c_add(c_scale(a.num[idx[s]], a.eta), c_scale(uo[s], a.gamma));
+      }
+    }
+#pragma unroll
+    for (int t = 1; t < MAXS; ++t) {
+#pragma unroll
+      for (int s = 0; s < t; ++s) {
+        if (t < m) {
+          const int q = t * (t - 1) / 2 + s;
+          const int64_t li = cd->lbase[q] + (int64_t)y * cd->lpitch[q] + x;
+          const float2 lab = a.lam[li], lba = a.lam[li + cd->lstride[q]];
+          const float2 v = c_scale(c_add(c_add(uo[s], uo[t]), c_add(lab, lba)), 0.5f);
+          acc[s] = c_add(acc[s], c_scale(c_sub(v, lab), a.r));
+          acc[t] = c_add(acc[t], c_scale(c_sub(v, lba), a.r));
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < MAXS; ++s) {
+      if (s < m) {
+        const float rc = a.rcp[idx[s]];
+        un[s] = rc == 0.0f ? uo[s] : c_scale(acc[s], rc);
+        a.u[idx[s]] = un[s];
+        a.num[idx[s]] = make_float2(0.0f, 0.0f);
+      }
+    }
+#pragma unroll
+    for (int t = 1; t < MAXS; ++t) {
+#pragma unroll
+      for (int s = 0; s < t; ++s) {
+        if (t < m) {
+          const int q = t * (t - 1) / 2 + s;
+          const int64_t li = cd->lbase[q] + (int64_t)y * cd->lpitch[q] + x;
+          const int64_t lj = li + cd->lstride[q];
+          const float2 lab = a.lam[li], lba = a.lam[lj];
+          const float2 v = c_scale(c_add(c_add(uo[s], uo[t]), c_add(lab, lba)), 0.5f);
+          a.lam[li] = c_add(lab, c_sub(un[s], v));
+          a.lam[lj] = c_add(lba, c_sub(un[t], v));
+        }
+      }
+    }
+  }
+  if (STATS) {
+#pragma unroll
+    for (int s = 0; s < MAXS; ++s) {
+      if (s < m) {  // m is uniform: every thread takes part in the reductions
+        double du = 0.0, uu = 0.0;
+        if (act) {
+          const double dx = (double)un[s].x - uo[s].x, dy = (double)un[s].y - uo[s].y;
+          du = dx * dx + dy * dy;
+          uu = (double)un[s].x * un[s].x + (double)un[s].y * un[s].y;
+        }
+        du = block_sum<256>(du, red);
+        uu = block_sum<256>(uu, red);
+        if (threadIdx.x == 0) {
+          a.part[((size_t)blockIdx.x * MAXS + s) * 2] = du;
+          a.part[((size_t)blockIdx.x * MAXS + s) * 2 + 1] = uu;
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_pixel(const PixelArgs& a, bool stats, hipStream_t s) {
+  if (a.n_tiles == 0) return hipSuccess;
+  if (stats) hipLaunchKernelGGL(k_pixel<true>, dim3(a.n_tiles), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_pixel<false>, dim3(a.n_tiles), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// K0: illumination den_d = sum_{j in d} S_j^T |w_d|^2 (eq. AtA) in FP64, in the
+// fixed order of the subdomain's frame list, and rcp = 1/(eta den + r k + gamma).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_illum(IllumArgs a) {
+  const TileDesc td = a.tiles[blockIdx.x];
+  const CellDesc* cd = a.cells + td.cell;
+  const int tr = threadIdx.x / TILE_COLS, tc = threadIdx.x % TILE_COLS;
+  if (!(tr < td.nr && tc < td.nc)) return;
+  const int y = td.r0 + tr, x = td.c0 + tc;
+  const int yi = cd->r0 + y, xi = cd->c0 + x;  // image coordinates
+  const int m = cd->m, p = a.p;
+  for (int s = 0; s < m; ++s) {
+    const int d = cd->sub[s];
+    const int64_t idx = cd->ubase[s] + (int64_t)y * cd->upitch[s] + x;
+    double den;
+    if (a.recompute_den) {
+      const float2* w = a.w + (a.w_per_sub ? (size_t)d * p * p : 0);
+      den = 0.0;
+      for (int k = a.sub_first[d]; k < a.sub_first[d + 1]; ++k) {
+        const int j = a.order[k];
+        const int dy = yi - a.offsets[2 * j], dx = xi - a.offsets[2 * j + 1];
+        if ((unsigned)dy < (unsigned)p && (unsigned)dx < (unsigned)p) {
+          const float2 ww = w[dy * p + dx];
+          den += (double)ww.x * ww.x + (double)ww.y * ww.y;
+        }
+      }
+      a.den[idx] = den;
+    } else {
+      den = a.den[idx];
+    }
+    const double q = a.eta * den + a.r * (double)(m - 1) + a.gamma;
+    a.rcp[idx] = q == 0.0 ? 0.0f : (float)(1.0 / q);
+  }
+}
+
+hipError_t launch_illum(const IllumArgs& a, hipStream_t s) {
+  if (a.n_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_illum, dim3(a.n_tiles), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Operators A and A* on the whole image (Sec. 2)
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(Frame<P>::T) void k_forward(const float2* __restrict__ u, int W,
+                                                         const float2* __restrict__ w,
+                                                         const float2* __restrict__ tw,
+                                                         const int32_t* __restrict__ off,
+                                                         float2* __restrict__ out) {
+  using F = Frame<P>;
+  __shared__ float2 lds[F::LDS];
+  const int j = blockIdx.x, t = threadIdx.x;
+  const int col = F::a_col(t), r2 = F::a_r2(t);
+  const int64_t base = (int64_t)off[2 * j] * W + off[2 * j + 1];
+  float2 v[16];
+#pragma unroll
+  for (int r1 = 0; r1 < 16; ++r1) {
+    const int row = F::N2 * r1 + r2;
+    v[r1] = c_mul(u[base + (int64_t)row * W + col], w[row * P + col]);
+  }
+  F::forward(v, lds, tw, t);
+  const float inv_p = 1.0f / (float)P;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    int kr, kc;
+    F::freq(t, e, kr, kc);
+    out[(size_t)j * P * P + kr * P + kc] = c_scale(v[e], inv_p);
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(Frame<P>::T) void k_adjoint(const float2* __restrict__ frames,
+                                                         const float2* __restrict__ w,
+                                                         const float2* __restrict__ tw,
+                                                         const int32_t* __restrict__ off,
+                                                         float2* __restrict__ u, int W) {
+  using F = Frame<P>;
+  __shared__ float2 lds[F::LDS];
+  const int j = blockIdx.x, t = threadIdx.x;
+  float2 v[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    int kr, kc;
+    F::freq(t, e, kr, kc);
+    v[e] = frames[(size_t)j * P * P + kr * P + kc];
+  }
+  F::inverse(v, lds, tw, t);
+  const int col = F::a_col(t), r2 = F::a_r2(t);
+  const int64_t base = (int64_t)off[2 * j] * W + off[2 * j + 1];
+  const float inv_p = 1.0f / (float)P;
+#pragma unroll
+  for (int r1 = 0; r1 < 16; ++r1) {
+    const int row = F::N2 * r1 + r2;
+    atomic_add_c(&u[base + (int64_t)row * W + col], c_mulc(c_scale(v[r1], inv_p), w[row * P + col]));
+  }
+}
+
+hipError_t launch_forward(int p, const float2* u, int H, int W, const float2* w, const float2* tw,
+                          const int32_t* offsets, int J, float2* out, hipStream_t s) {
+  (void)H;
+  if (p == 32) hipLaunchKernelGGL(k_forward<32>, dim3(J), dim3(Frame<32>::T), 0, s, u, W, w, tw, offsets, out);
+  else if (p == 64) hipLaunchKernelGGL(k_forward<64>, dim3(J), dim3(Frame<64>::T), 0, s, u, W, w, tw, offsets, out);
+  else if (p == 128) hipLaunchKernelGGL(k_forward<128>, dim3(J), dim3(Frame<128>::T), 0, s, u, W, w, tw, offsets, out);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(int p, const float2* frames, const float2* w, const float2* tw,
+                          const int32_t* offsets, int J, float2* u_out, int H, int W, hipStream_t s) {
+  hipError_t e = launch_fill(u_out, (int64_t)H * W, make_float2(0.f, 0.f), s);
+  if (e != hipSuccess) return e;
+  if (p == 32) hipLaunchKernelGGL(k_adjoint<32>, dim3(J), dim3(Frame<32>::T), 0, s, frames, w, tw, offsets, u_out, W);
+  else if (p == 64) hipLaunchKernelGGL(k_adjoint<64>, dim3(J), dim3(Frame<64>::T), 0, s, frames, w, tw, offsets, u_out, W);
+  else if (p == 128) hipLaunchKernelGGL(k_adjoint<128>, dim3(J), dim3(Frame<128>::T), 0, s, frames, w, tw, offsets, u_out, W);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// elementwise prox, fills, copies
+// ---------------------------------------------------------------------------
+__global__ void k_prox(const float2* __restrict__ y, const float* __restrict__ sf, int64_t n, ProxC pc,
+                       float2* z) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    z[i] = prox_stagm(y[i], sf[i], pc);
+}
+
+hipError_t launch_prox(const float2* y, const float* sf, int64_t n, float eps, float lam, float2* z,
+                       hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_prox, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, s, y, sf, n,
+                     prox_coeffs(eps, lam), z);
+  return hipGetLastError();
+}
+
+__global__ void k_fill(float2* p, int64_t n, float2 v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill(float2* p, int64_t n, float2 value, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, s, p, n, value);
+  return hipGetLastError();
+}
+
+__global__ void k_copy(float2* d, const float2* src, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = src[i];
+}
+
+hipError_t launch_copy(float2* dst, const float2* src, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// bind-time reductions: max of den (FP64) and sum of sqrt f (FP64), fixed order
+// ---------------------------------------------------------------------------
+constexpr int RED_BLOCKS = 1024;
+
+__global__ __launch_bounds__(256) void k_sum_max_part(const double* x, int64_t n, const float* y, int64_t ny,
+                                                      double* part) {
+  __shared__ double sh[4];
+  double mx = 0.0, sm = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)RED_BLOCKS * 256) mx = fmax(mx, x[i]);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ny; i += (int64_t)RED_BLOCKS * 256) sm += (double)y[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  mx = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+  sm = block_sum<256>(sm, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = mx;
+    part[2 * blockIdx.x + 1] = sm;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sum_max_final(const double* part, double* out) {
+  __shared__ double sh[4];
+  double mx = 0.0, sm = 0.0;
+  for (int i = threadIdx.x; i < RED_BLOCKS; i += 256) {
+    mx = fmax(mx, part[2 * i]);
+    sm += part[2 * i + 1];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  mx = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+  sm = block_sum<256>(sm, sh);
+  if (threadIdx.x == 0) {
+    out[0] = mx;
+    out[1] = sm;
+  }
+}
+
+hipError_t launch_sum_max(const double* x, int64_t n, const float* y, int64_t ny, double* out, hipStream_t s) {
+  // out[0] = max x, out[1] = sum y; out[2 .. 2 + 2*RED_BLOCKS) is scratch
+  hipLaunchKernelGGL(k_sum_max_part, dim3(RED_BLOCKS), dim3(256), 0, s, x, n, y, ny, out + 2);
+  hipLaunchKernelGGL(k_sum_max_final, dim3(1), dim3(256), 0, s, out + 2, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// per-iteration statistics: RF, RE, G_eps (Sec. 4, eq. STAGM), fixed order
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_stats_reduce(const double* frame_part, int J, const double* tile_part,
+                                                      const int32_t* re_list, const int32_t* re_first, int D,
+                                                      double* scratch) {
+  __shared__ double sh[4];
+  const int b = blockIdx.x;
+  double s0 = 0.0, s1 = 0.0;
+  if (b < D) {
+    for (int k = re_first[b] + threadIdx.x; k < re_first[b + 1]; k += 256) {
+      const int e = re_list[k];
+      s0 += tile_part[2 * (size_t)e];
+      s1 += tile_part[2 * (size_t)e + 1];
+    }
+  } else {
+    for (int k = threadIdx.x; k < J; k += 256) {
+      s0 += frame_part[2 * k];
+      s1 += frame_part[2 * k + 1];
+    }
+  }
+  s0 = block_sum<256>(s0, sh);
+  s1 = block_sum<256>(s1, sh);
+  if (threadIdx.x == 0) {
+    scratch[2 * b] = s0;
+    scratch[2 * b + 1] = s1;
+  }
+}
+
+__global__ void k_stats_final(const double* scratch, int D, const double* sum_sf, double* out3) {
+  if (threadIdx.x != 0) return;
+  double re = 0.0;
+  for (int d = 0; d < D; ++d) {
+    const double num = scratch[2 * d], den = scratch[2 * d + 1];
+    const double v = den > 0.0 ? sqrt(num / den) : 0.0;
+    re = fmax(re, v);
+  }
+  out3[0] = scratch[2 * D] / sum_sf[0];
+  out3[1] = re;
+  out3[2] = scratch[2 * D + 1];
+}
+
+hipError_t launch_stats(const double* frame_part, int J, const double* tile_part, const int32_t* re_list,
+                        const int32_t* re_first, int D, const double* sum_sf, double* out3, double* scratch,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_stats_reduce, dim3(D + 1), dim3(256), 0, s, frame_part, J, tile_part, re_list, re_first,
+                     D, scratch);
+  hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(64), 0, s, scratch, D, sum_sf, out3);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// merge (Sec. 4): mean of the copies over each pixel, 1 where no subdomain
+// ---------------------------------------------------------------------------
+__global__ void k_merge(const float2* __restrict__ usub, const int32_t* __restrict__ rects,
+                        const int64_t* __restrict__ uoff, int D, int H, int W, float2* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)H * W) return;
+  const int y = (int)(i / W), x = (int)(i % W);
+  float sx = 0.f, sy = 0.f;
+  int n = 0;
+  for (int d = 0; d < D; ++d) {
+    const int r0 = rects[4 * d], c0 = rects[4 * d + 1], r1 = rects[4 * d + 2], c1 = rects[4 * d + 3];
+    if (y >= r0 && y < r1 && x >= c0 && x < c1) {
+      const float2 v = usub[uoff[d] + (int64_t)(y - r0) * (c1 - c0) + (x - c0)];
+      sx += v.x;
+      sy += v.y;
+      ++n;
+    }
+  }
+  out[i] = n ? make_float2(sx / n, sy / n) : make_float2(1.f, 0.f);
+}
+
+hipError_t launch_merge(const float2* u_sub, const int32_t* rects, const int64_t* usub_off, int D, int H, int W,
+                        float2* out, hipStream_t s) {
+  const int64_t n = (int64_t)H * W;
+  hipLaunchKernelGGL(k_merge, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, u_sub, rects, usub_off, D, H, W,
+                     out);
+  return hipGetLastError();
+}
+
+}  // namespace odp

@@ -1,0 +1,152 @@
+// odp_internal.hpp -- structures shared by the host plan code and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace odp {
+
+constexpr int MAXS = 8;                        // most subdomains over one pixel
+constexpr int MAXP = MAXS * (MAXS - 1) / 2;    // most pairs over one pixel
+constexpr int TILE_ROWS = 4;                   // pixel-update tile: 4 x 64 pixels, 256 threads
+constexpr int TILE_COLS = 64;
+constexpr int NXCD = 8;                        // MI355X accelerator complex dies
+
+// A cell is a rectangle of image pixels covered by the same set of subdomains
+// (the cuts are the subdomain rectangle edges).  k_d = m - 1 on the whole cell.
+struct CellDesc {
+  int32_t m;                 // number of subdomains covering the cell
+  int32_t npair;             // m (m - 1) / 2
+  int32_t r0, c0;            // top-left pixel in the image
+  int32_t sub[MAXS];         // subdomain ids, ascending
+  int32_t upitch[MAXS];      // row pitch of each subdomain array
+  int64_t ubase[MAXS];       // u_sub index of the cell's top-left in each subdomain
+  int64_t lbase[MAXP];       // lam index of the top-left in Lam_{a,b}; Lam_{b,a} is lstride later
+  int64_t lstride[MAXP];
+  int32_t lpitch[MAXP];
+  int8_t pa[MAXP], pb[MAXP]; // positions in sub[] of the pair's subdomains (pa < pb)
+};
+
+struct TileDesc {
+  int32_t cell;
+  int32_t r0, c0;            // relative to the cell's top-left
+  int32_t nr, nc;
+  int32_t pad[3];
+};
+
+struct FrameDesc {
+  int64_t base;              // u_sub index of the window's top-left inside its subdomain
+  int32_t pitch;             // row pitch of that subdomain
+  int32_t sub;               // subdomain id
+};
+
+// ---------------------------------------------------------------- launch args
+struct SweepArgs {
+  const float2* u;           // u_sub
+  float2* num;               // A_d*(z - Gamma) accumulators, one per u_sub pixel
+  const float2* w;           // probe [p][p] (non-blind) or copies [D][p][p] (blind)
+  int w_per_sub;             // 1: w indexed by subdomain (blind)
+  const float2* tw;          // W_p^m, m < p
+  float2* gamma;             // [J][p][p]
+  const float* sqrt_f;       // [J][p][p]
+  const FrameDesc* frames;
+  const int32_t* order;      // frame processing order (grouped by subdomain)
+  int32_t J, chunk;          // frames, frames per XCD slice
+  float eps, eta;
+  double* part;              // [J][2] stats partials (L1 misfit, G_eps) or null
+  float2* phi;               // blind: F^{-1}(z - Gamma) per frame, natural layout, or null
+};
+
+struct PixelArgs {
+  float2* u;                 // u_sub (updated in place)
+  float2* num;               // accumulators (read, then cleared)
+  const float* rcp;          // 1 / (eta den + r k + gamma); 0 = held pixel
+  float2* lam;
+  const CellDesc* cells;
+  const TileDesc* tiles;
+  int32_t n_tiles;
+  float eta, r, gamma;
+  double* part;              // [n_tiles][MAXS][2] (|du|^2, |u|^2) or null
+};
+
+struct IllumArgs {           // den and rcp on every subdomain pixel
+  const float2* w;           // probe or probe copies
+  int w_per_sub;
+  const FrameDesc* frames;
+  const int32_t* order;      // frames grouped by subdomain
+  const int32_t* sub_first;  // [D+1] ranges of order per subdomain
+  const int32_t* offsets;    // [J][2]
+  const int32_t* rects;      // [D][4]
+  const CellDesc* cells;
+  const TileDesc* tiles;
+  int32_t n_tiles, p;
+  double* den;               // [p_sub]
+  float* rcp;                // [p_sub]
+  double eta, r, gamma;
+  int recompute_den;         // 0: reuse den, only rebuild rcp
+};
+
+hipError_t launch_sweep(int p, const SweepArgs& a, hipStream_t s);
+hipError_t launch_pixel(const PixelArgs& a, bool stats, hipStream_t s);
+hipError_t launch_illum(const IllumArgs& a, hipStream_t s);
+hipError_t launch_forward(int p, const float2* u, int H, int W, const float2* w, const float2* tw,
+                          const int32_t* offsets, int J, float2* out, hipStream_t s);
+hipError_t launch_adjoint(int p, const float2* frames, const float2* w, const float2* tw,
+                          const int32_t* offsets, int J, float2* u_out, int H, int W, hipStream_t s);
+hipError_t launch_prox(const float2* y, const float* sf, int64_t n, float eps, float lam, float2* z,
+                       hipStream_t s);
+hipError_t launch_fill(float2* p, int64_t n, float2 value, hipStream_t s);
+hipError_t launch_sum_max(const double* x, int64_t n, const float* y, int64_t ny, double* out,
+                          hipStream_t s);
+hipError_t launch_stats(const double* frame_part, int J, const double* tile_part,
+                        const int32_t* re_list, const int32_t* re_first, int D, const double* sum_sf,
+                        double* out3, double* scratch, hipStream_t s);
+hipError_t launch_merge(const float2* u_sub, const int32_t* rects, const int64_t* usub_off, int D,
+                        int H, int W, float2* out, hipStream_t s);
+hipError_t launch_copy(float2* dst, const float2* src, int64_t n, hipStream_t s);
+
+// blind (Alg. 3) pieces
+struct ProbeArgs {
+  const float2* u;           // u_sub (iterate n)
+  const float2* phi;         // F^{-1}(Z - Gamma) per frame
+  const FrameDesc* frames;
+  const int32_t* order;
+  const int32_t* sub_first;
+  int32_t D, p;
+  float2* w;                 // shared probe w (out: w^{n+1})
+  float2* w_sub;             // copies [D][p][p] (in W^n, out W^{n+1})
+  float2* delta;             // [D][p][p] (in Delta^n, out Delta^{n+1})
+  const float* fmask;        // [p][p] support indicator or null
+  const float2* tw;
+  double eta, mu;
+  float2* scratch;           // [p][p] work buffer
+};
+hipError_t launch_probe_update(const ProbeArgs& a, hipStream_t s);
+
+struct ScatterArgs {         // num += S_j^T (conj(w_d) o phi_j), per frame
+  const float2* phi;
+  const float2* w_sub;
+  const FrameDesc* frames;
+  int32_t J, p;
+  float2* num;
+};
+hipError_t launch_blind_scatter(const ScatterArgs& a, hipStream_t s);
+
+struct LossArgs {
+  const float2* u; int H, W;
+  const float2* w;
+  const float2* tw;
+  const float* sqrt_f;
+  const int32_t* offsets;
+  int32_t J;
+  double* frame_loss;        // [J]
+  float2* grad_u;            // [H][W] or null (atomic accumulation, cleared by the caller)
+  float2* phi;               // [J][p][p] F^{-1} g_j (for the probe gradient) or null
+};
+hipError_t launch_loss(int p, const LossArgs& a, hipStream_t s);
+hipError_t launch_probe_grad(const float2* u, int H, int W, const float2* phi, const int32_t* offsets,
+                             int J, int p, double* loss_parts, double* loss_out, float2* grad_w,
+                             hipStream_t s);
+
+}  // namespace odp

@@ -1,0 +1,661 @@
+// plan.cpp -- host side of the C ABI: validation, decomposition geometry,
+// workspace/state layout and the entry points that launch the kernels.
+//
+// Geometry follows Sec. 2.1 and Sec. 3.1 of the paper: frames are partitioned
+// first; subdomain d is the bounding rectangle of its frames' windows; the pair
+// set holds every intersecting pair; k_d(x) (sum over pairs of pi^T pi) is the
+// number of other subdomains containing x.  On one GPU the subdomains are index
+// ranges of one launch, not separate processes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/odp.h"
+#include "odp_internal.hpp"
+
+using namespace odp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define ODP_HIP(call)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) return fail(ODP_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Pair {
+  int32_t a, b, r0, c0, r1, c1;
+  int64_t off;  // lam index of Lam_{a,b}; Lam_{b,a} follows after h*w
+};
+
+}  // namespace
+
+struct odp_plan {
+  int32_t H = 0, W = 0, p = 0, J = 0, D = 0;
+  double eps = 0, eta = 0, r = 0, mu = 0, gamma = 0;
+  int32_t transform = ODP_FFT_F32, blind = 0;
+  std::vector<int32_t> offsets, frame_sub;
+  std::vector<float> fmask;  // empty = no projection
+  // geometry
+  std::vector<int32_t> rects;  // [D][4]
+  std::vector<int64_t> usub_off;
+  int64_t p_sub = 0;
+  std::vector<Pair> pairs;
+  int64_t n_lam = 0;
+  std::vector<CellDesc> cells;
+  std::vector<TileDesc> tiles;
+  int32_t max_cover = 0;
+  std::vector<FrameDesc> frames;
+  std::vector<int32_t> order, sub_first;
+  std::vector<int32_t> re_list, re_first;
+  std::vector<float2> tw;
+  int32_t chunk = 0;
+  // workspace layout (byte offsets)
+  struct {
+    size_t tw, w, frames, order, sub_first, offsets, rects, usub_off, cells, tiles, re_list, re_first, den, rcp,
+        num, fpart, tpart, stat_scratch, misc, phi, fmask, probe_tmp, bytes;
+  } ws{};
+  struct {
+    size_t u_sub, gamma, lam, w, w_sub, delta, bytes;
+  } st{};
+  // bound state
+  char* wsp = nullptr;
+  const float* sqrt_f = nullptr;
+  double illum_max = 0.0;
+
+  template <class T>
+  T* W_(size_t off) const { return reinterpret_cast<T*>(wsp + off); }
+};
+
+namespace {
+
+int build_geometry(odp_plan* P) {
+  const int J = P->J, D = P->D, p = P->p, H = P->H, W = P->W;
+  // rectangles
+  P->rects.assign((size_t)D * 4, 0);
+  std::vector<int> count(D, 0);
+  for (int d = 0; d < D; ++d) {
+    P->rects[4 * d] = H;
+    P->rects[4 * d + 1] = W;
+    P->rects[4 * d + 2] = 0;
+    P->rects[4 * d + 3] = 0;
+  }
+  for (int j = 0; j < J; ++j) {
+    const int d = P->frame_sub[j], r = P->offsets[2 * j], c = P->offsets[2 * j + 1];
+    int32_t* R = &P->rects[4 * d];
+    R[0] = std::min(R[0], r);
+    R[1] = std::min(R[1], c);
+    R[2] = std::max(R[2], r + p);
+    R[3] = std::max(R[3], c + p);
+    ++count[d];
+  }
+  for (int d = 0; d < D; ++d)
+    if (count[d] == 0) return fail(ODP_EGEOM, "subdomain " + std::to_string(d) + " has no frames");
+  P->usub_off.resize(D);
+  int64_t off = 0;
+  for (int d = 0; d < D; ++d) {
+    P->usub_off[d] = off;
+    off += (int64_t)(P->rects[4 * d + 2] - P->rects[4 * d]) * (P->rects[4 * d + 3] - P->rects[4 * d + 1]);
+  }
+  P->p_sub = off;
+  // pairs (all intersecting, i1 < i2)
+  P->pairs.clear();
+  int64_t loff = 0;
+  for (int a = 0; a < D; ++a)
+    for (int b = a + 1; b < D; ++b) {
+      const int32_t* A = &P->rects[4 * a];
+      const int32_t* B = &P->rects[4 * b];
+      const int r0 = std::max(A[0], B[0]), c0 = std::max(A[1], B[1]);
+      const int r1 = std::min(A[2], B[2]), c1 = std::min(A[3], B[3]);
+      if (r0 < r1 && c0 < c1) {
+        P->pairs.push_back(Pair{a, b, r0, c0, r1, c1, loff});
+        loff += 2LL * (r1 - r0) * (c1 - c0);
+      }
+    }
+  P->n_lam = loff;
+  // cells: cut the image at every rectangle edge
+  std::vector<int> rc = {0, H}, cc = {0, W};
+  for (int d = 0; d < D; ++d) {
+    rc.push_back(P->rects[4 * d]);
+    rc.push_back(P->rects[4 * d + 2]);
+    cc.push_back(P->rects[4 * d + 1]);
+    cc.push_back(P->rects[4 * d + 3]);
+  }
+  std::sort(rc.begin(), rc.end());
+  rc.erase(std::unique(rc.begin(), rc.end()), rc.end());
+  std::sort(cc.begin(), cc.end());
+  cc.erase(std::unique(cc.begin(), cc.end()), cc.end());
+  // pair lookup
+  std::vector<int> pair_of((size_t)D * D, -1);
+  for (size_t q = 0; q < P->pairs.size(); ++q) {
+    pair_of[(size_t)P->pairs[q].a * D + P->pairs[q].b] = (int)q;
+  }
+  P->cells.clear();
+  P->tiles.clear();
+  P->max_cover = 0;
+  for (size_t yi = 0; yi + 1 < rc.size(); ++yi)
+    for (size_t xi = 0; xi + 1 < cc.size(); ++xi) {
+      const int r0 = rc[yi], r1 = rc[yi + 1], c0 = cc[xi], c1 = cc[xi + 1];
+      std::vector<int> S;
+      for (int d = 0; d < D; ++d) {
+        const int32_t* R = &P->rects[4 * d];
+        if (R[0] <= r0 && r1 <= R[2] && R[1] <= c0 && c1 <= R[3]) S.push_back(d);
+      }
+      if (S.empty()) continue;
+      P->max_cover = std::max<int32_t>(P->max_cover, (int32_t)S.size());
+      if ((int)S.size() > MAXS)
+        return fail(ODP_EUNSUPPORTED, "more than " + std::to_string(MAXS) + " subdomains overlap one pixel");
+      CellDesc cd;
+      std::memset(&cd, 0, sizeof(cd));
+      cd.m = (int32_t)S.size();
+      cd.npair = cd.m * (cd.m - 1) / 2;
+      cd.r0 = r0;
+      cd.c0 = c0;
+      for (int s = 0; s < cd.m; ++s) {
+        const int d = S[s];
+        const int32_t* R = &P->rects[4 * d];
+        cd.sub[s] = d;
+        cd.upitch[s] = R[3] - R[1];
+        cd.ubase[s] = P->usub_off[d] + (int64_t)(r0 - R[0]) * (R[3] - R[1]) + (c0 - R[1]);
+      }
+      for (int t = 1; t < cd.m; ++t)
+        for (int s = 0; s < t; ++s) {
+          const int q = t * (t - 1) / 2 + s;
+          const int pq = pair_of[(size_t)S[s] * D + S[t]];
+          if (pq < 0) return fail(ODP_EGEOM, "internal: missing pair");
+          const Pair& pr = P->pairs[pq];
+          const int pw = pr.c1 - pr.c0, ph = pr.r1 - pr.r0;
+          cd.lbase[q] = pr.off + (int64_t)(r0 - pr.r0) * pw + (c0 - pr.c0);
+          cd.lstride[q] = (int64_t)ph * pw;
+          cd.lpitch[q] = pw;
+          cd.pa[q] = (int8_t)s;
+          cd.pb[q] = (int8_t)t;
+        }
+      const int cell = (int)P->cells.size();
+      P->cells.push_back(cd);
+      for (int ty = 0; ty < r1 - r0; ty += TILE_ROWS)
+        for (int tx = 0; tx < c1 - c0; tx += TILE_COLS) {
+          TileDesc td;
+          std::memset(&td, 0, sizeof(td));
+          td.cell = cell;
+          td.r0 = ty;
+          td.c0 = tx;
+          td.nr = std::min(TILE_ROWS, r1 - r0 - ty);
+          td.nc = std::min(TILE_COLS, c1 - c0 - tx);
+          P->tiles.push_back(td);
+        }
+    }
+  // RE reduction lists: (tile, slot) entries per subdomain, tile order
+  std::vector<std::vector<int32_t>> per(D);
+  for (size_t t = 0; t < P->tiles.size(); ++t) {
+    const CellDesc& cd = P->cells[P->tiles[t].cell];
+    for (int s = 0; s < cd.m; ++s) per[cd.sub[s]].push_back((int32_t)(t * MAXS + s));
+  }
+  P->re_first.assign(D + 1, 0);
+  P->re_list.clear();
+  for (int d = 0; d < D; ++d) {
+    P->re_first[d] = (int32_t)P->re_list.size();
+    P->re_list.insert(P->re_list.end(), per[d].begin(), per[d].end());
+  }
+  P->re_first[D] = (int32_t)P->re_list.size();
+  // frames: base index inside the owning subdomain; processing order grouped by subdomain
+  P->frames.resize(J);
+  for (int j = 0; j < J; ++j) {
+    const int d = P->frame_sub[j];
+    const int32_t* R = &P->rects[4 * d];
+    FrameDesc fd;
+    fd.pitch = R[3] - R[1];
+    fd.base = P->usub_off[d] + (int64_t)(P->offsets[2 * j] - R[0]) * fd.pitch + (P->offsets[2 * j + 1] - R[1]);
+    fd.sub = d;
+    P->frames[j] = fd;
+  }
+  P->order.resize(J);
+  for (int j = 0; j < J; ++j) P->order[j] = j;
+  std::stable_sort(P->order.begin(), P->order.end(),
+                   [&](int a, int b) { return P->frame_sub[a] < P->frame_sub[b]; });
+  P->sub_first.assign(D + 1, 0);
+  for (int j = 0; j < J; ++j) P->sub_first[P->frame_sub[j] + 1]++;
+  for (int d = 0; d < D; ++d) P->sub_first[d + 1] += P->sub_first[d];
+  P->chunk = (J + NXCD - 1) / NXCD;
+  // twiddles W_p^m = exp(-2 pi i m / p), FP64 on the host
+  P->tw.resize(p);
+  for (int m = 0; m < p; ++m) {
+    const double a = 2.0 * M_PI * (double)m / (double)p;
+    P->tw[m] = make_float2((float)std::cos(a), (float)-std::sin(a));
+  }
+  return ODP_OK;
+}
+
+void layout(odp_plan* P) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  const size_t pp = (size_t)P->p * P->p;
+  P->ws.tw = take(sizeof(float2) * P->p);
+  P->ws.w = take(sizeof(float2) * pp);
+  P->ws.frames = take(sizeof(FrameDesc) * P->J);
+  P->ws.order = take(sizeof(int32_t) * P->J);
+  P->ws.sub_first = take(sizeof(int32_t) * (P->D + 1));
+  P->ws.offsets = take(sizeof(int32_t) * 2 * P->J);
+  P->ws.rects = take(sizeof(int32_t) * 4 * P->D);
+  P->ws.usub_off = take(sizeof(int64_t) * P->D);
+  P->ws.cells = take(sizeof(CellDesc) * P->cells.size());
+  P->ws.tiles = take(sizeof(TileDesc) * P->tiles.size());
+  P->ws.re_list = take(sizeof(int32_t) * std::max<size_t>(1, P->re_list.size()));
+  P->ws.re_first = take(sizeof(int32_t) * (P->D + 1));
+  P->ws.den = take(sizeof(double) * P->p_sub);
+  P->ws.rcp = take(sizeof(float) * P->p_sub);
+  P->ws.num = take(sizeof(float2) * P->p_sub);
+  P->ws.fpart = take(sizeof(double) * 2 * P->J);
+  P->ws.tpart = take(sizeof(double) * 2 * MAXS * std::max<size_t>(1, P->tiles.size()));
+  P->ws.stat_scratch = take(sizeof(double) * 2 * (P->D + 1));
+  P->ws.misc = take(sizeof(double) * (2 + 2 * 1024 + 8));
+  P->ws.phi = P->blind ? take(sizeof(float2) * pp * P->J) : 0;
+  P->ws.fmask = take(sizeof(float) * pp);
+  P->ws.probe_tmp = take(sizeof(float2) * pp);
+  P->ws.bytes = o;
+  size_t s = 0;
+  auto stake = [&](size_t bytes) {
+    const size_t at = s;
+    s = align256(s + bytes);
+    return at;
+  };
+  P->st.u_sub = stake(sizeof(float2) * P->p_sub);
+  P->st.gamma = stake(sizeof(float2) * pp * P->J);
+  P->st.lam = stake(sizeof(float2) * std::max<int64_t>(1, P->n_lam));
+  P->st.w = P->blind ? stake(sizeof(float2) * pp) : 0;
+  P->st.w_sub = P->blind ? stake(sizeof(float2) * pp * P->D) : 0;
+  P->st.delta = P->blind ? stake(sizeof(float2) * pp * P->D) : 0;
+  P->st.bytes = s;
+}
+
+int check_params(double eps, double eta, double r, double mu, double gamma, int D, int blind) {
+  if (!(eps > 0.0 && eps < 1.0)) return fail(ODP_EINVAL, "eps must lie in (0, 1)");
+  if (!(eta > 0.0)) return fail(ODP_EINVAL, "eta must be positive");
+  if (D > 1 && !(r > 0.0)) return fail(ODP_EINVAL, "r must be positive when D > 1");
+  if (!(r >= 0.0)) return fail(ODP_EINVAL, "r must be non-negative");
+  if (blind && !(mu > 0.0)) return fail(ODP_EINVAL, "mu must be positive for blind recovery");
+  if (!(gamma >= 0.0)) return fail(ODP_EINVAL, "gamma must be non-negative");
+  return ODP_OK;
+}
+
+IllumArgs illum_args(const odp_plan* P, const float2* w, int per_sub, int recompute) {
+  IllumArgs a;
+  a.w = w;
+  a.w_per_sub = per_sub;
+  a.frames = P->W_<FrameDesc>(P->ws.frames);
+  a.order = P->W_<int32_t>(P->ws.order);
+  a.sub_first = P->W_<int32_t>(P->ws.sub_first);
+  a.offsets = P->W_<int32_t>(P->ws.offsets);
+  a.rects = P->W_<int32_t>(P->ws.rects);
+  a.cells = P->W_<CellDesc>(P->ws.cells);
+  a.tiles = P->W_<TileDesc>(P->ws.tiles);
+  a.n_tiles = (int32_t)P->tiles.size();
+  a.p = P->p;
+  a.den = P->W_<double>(P->ws.den);
+  a.rcp = P->W_<float>(P->ws.rcp);
+  a.eta = P->eta;
+  a.r = P->r;
+  a.gamma = P->gamma;
+  a.recompute_den = recompute;
+  return a;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* odp_last_error(void) { return g_err.c_str(); }
+const char* odp_version(void) { return "odp 0.1 (gfx950)"; }
+
+int odp_plan_create(const odp_problem* prob, odp_plan** out) {
+  if (!prob || !out) return fail(ODP_EINVAL, "null argument");
+  *out = nullptr;
+  if (prob->p != 32 && prob->p != 64 && prob->p != 128)
+    return fail(ODP_EUNSUPPORTED, "p must be 32, 64 or 128");
+  if (prob->H < prob->p || prob->W < prob->p) return fail(ODP_EINVAL, "image smaller than the probe");
+  if (prob->J < 1 || !prob->offsets || !prob->frame_sub) return fail(ODP_EINVAL, "no frames");
+  if (prob->D < 1) return fail(ODP_EINVAL, "D must be >= 1");
+  if (prob->transform != ODP_FFT_F32 && prob->transform != ODP_DFT_SPLIT_BF16)
+    return fail(ODP_EINVAL, "unknown transform");
+  if (prob->transform == ODP_DFT_SPLIT_BF16)
+    return fail(ODP_EUNSUPPORTED, "split-BF16 DFT transform is not built into this library");
+  int rc = check_params(prob->eps, prob->eta, prob->r, prob->mu, prob->gamma, prob->D, prob->blind);
+  if (rc) return rc;
+  if ((int64_t)prob->H * prob->W >= (int64_t)1 << 31) return fail(ODP_EUNSUPPORTED, "image too large");
+  for (int j = 0; j < prob->J; ++j) {
+    const int r = prob->offsets[2 * j], c = prob->offsets[2 * j + 1];
+    if (r < 0 || c < 0 || r + prob->p > prob->H || c + prob->p > prob->W)
+      return fail(ODP_EGEOM, "window " + std::to_string(j) + " leaves the image");
+    if (prob->frame_sub[j] < 0 || prob->frame_sub[j] >= prob->D)
+      return fail(ODP_EGEOM, "frame_sub out of range at frame " + std::to_string(j));
+  }
+  odp_plan* P = new (std::nothrow) odp_plan();
+  if (!P) return fail(ODP_ENOMEM, "host allocation failed");
+  P->H = prob->H;
+  P->W = prob->W;
+  P->p = prob->p;
+  P->J = prob->J;
+  P->D = prob->D;
+  P->eps = prob->eps;
+  P->eta = prob->eta;
+  P->r = prob->r;
+  P->mu = prob->mu;
+  P->gamma = prob->gamma;
+  P->transform = prob->transform;
+  P->blind = prob->blind ? 1 : 0;
+  P->offsets.assign(prob->offsets, prob->offsets + 2 * (size_t)prob->J);
+  P->frame_sub.assign(prob->frame_sub, prob->frame_sub + prob->J);
+  if (prob->probe_fmask) {
+    P->fmask.resize((size_t)prob->p * prob->p);
+    for (size_t i = 0; i < P->fmask.size(); ++i) P->fmask[i] = prob->probe_fmask[i] ? 1.0f : 0.0f;
+  }
+  try {
+    rc = build_geometry(P);
+  } catch (const std::bad_alloc&) {
+    rc = fail(ODP_ENOMEM, "host allocation failed");
+  }
+  if (rc) {
+    delete P;
+    return rc;
+  }
+  layout(P);
+  *out = P;
+  return ODP_OK;
+}
+
+void odp_plan_destroy(odp_plan* plan) { delete plan; }
+
+int odp_plan_get_info(const odp_plan* P, odp_plan_info* o) {
+  if (!P || !o) return fail(ODP_EINVAL, "null argument");
+  o->H = P->H;
+  o->W = P->W;
+  o->p = P->p;
+  o->J = P->J;
+  o->D = P->D;
+  o->n_pairs = (int32_t)P->pairs.size();
+  o->max_cover = P->max_cover;
+  o->n_cells = (int32_t)P->cells.size();
+  o->n_tiles = (int32_t)P->tiles.size();
+  o->p_sub = P->p_sub;
+  o->n_lam = P->n_lam;
+  o->workspace_bytes = P->ws.bytes;
+  o->state_bytes = P->st.bytes;
+  return ODP_OK;
+}
+
+int odp_state_get_layout(const odp_plan* P, odp_state_layout* o) {
+  if (!P || !o) return fail(ODP_EINVAL, "null argument");
+  o->u_sub = P->st.u_sub;
+  o->gamma = P->st.gamma;
+  o->lam = P->st.lam;
+  o->w = P->st.w;
+  o->w_sub = P->st.w_sub;
+  o->delta = P->st.delta;
+  o->bytes = P->st.bytes;
+  return ODP_OK;
+}
+
+int odp_plan_get_rects(const odp_plan* P, int32_t* rects, int64_t* usub_off) {
+  if (!P || !rects) return fail(ODP_EINVAL, "null argument");
+  std::memcpy(rects, P->rects.data(), sizeof(int32_t) * P->rects.size());
+  if (usub_off) std::memcpy(usub_off, P->usub_off.data(), sizeof(int64_t) * P->usub_off.size());
+  return ODP_OK;
+}
+
+int odp_plan_get_pairs(const odp_plan* P, int32_t* pairs, int64_t* lam_off) {
+  if (!P || !pairs) return fail(ODP_EINVAL, "null argument");
+  for (size_t q = 0; q < P->pairs.size(); ++q) {
+    const Pair& pr = P->pairs[q];
+    int32_t* o = pairs + 6 * q;
+    o[0] = pr.a; o[1] = pr.b; o[2] = pr.r0; o[3] = pr.c0; o[4] = pr.r1; o[5] = pr.c1;
+    if (lam_off) lam_off[q] = pr.off;
+  }
+  return ODP_OK;
+}
+
+int odp_plan_get_cover(const odp_plan* P, int32_t* cover) {
+  if (!P || !cover) return fail(ODP_EINVAL, "null argument");
+  std::fill(cover, cover + (size_t)P->H * P->W, 0);
+  for (const CellDesc& cd : P->cells) (void)cd;
+  for (const TileDesc& td : P->tiles) {
+    const CellDesc& cd = P->cells[td.cell];
+    for (int y = 0; y < td.nr; ++y)
+      for (int x = 0; x < td.nc; ++x)
+        cover[(size_t)(cd.r0 + td.r0 + y) * P->W + (cd.c0 + td.c0 + x)] = cd.m;
+  }
+  return ODP_OK;
+}
+
+int odp_plan_bind(odp_plan* P, void* dev_ws, const float* dev_sqrt_f, const odp_c32* dev_w, hipStream_t s) {
+  if (!P || !dev_ws || !dev_sqrt_f || !dev_w) return fail(ODP_EINVAL, "null argument");
+  if (reinterpret_cast<uintptr_t>(dev_ws) & 255) return fail(ODP_EINVAL, "workspace must be 256-byte aligned");
+  P->wsp = static_cast<char*>(dev_ws);
+  P->sqrt_f = dev_sqrt_f;
+  const size_t pp = (size_t)P->p * P->p;
+  auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(P->wsp + off, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  ODP_HIP(up(P->ws.tw, P->tw.data(), sizeof(float2) * P->tw.size()));
+  ODP_HIP(hipMemcpyAsync(P->wsp + P->ws.w, dev_w, sizeof(float2) * pp, hipMemcpyDeviceToDevice, s));
+  ODP_HIP(up(P->ws.frames, P->frames.data(), sizeof(FrameDesc) * P->frames.size()));
+  ODP_HIP(up(P->ws.order, P->order.data(), sizeof(int32_t) * P->order.size()));
+  ODP_HIP(up(P->ws.sub_first, P->sub_first.data(), sizeof(int32_t) * P->sub_first.size()));
+  ODP_HIP(up(P->ws.offsets, P->offsets.data(), sizeof(int32_t) * P->offsets.size()));
+  ODP_HIP(up(P->ws.rects, P->rects.data(), sizeof(int32_t) * P->rects.size()));
+  ODP_HIP(up(P->ws.usub_off, P->usub_off.data(), sizeof(int64_t) * P->usub_off.size()));
+  ODP_HIP(up(P->ws.cells, P->cells.data(), sizeof(CellDesc) * P->cells.size()));
+  ODP_HIP(up(P->ws.tiles, P->tiles.data(), sizeof(TileDesc) * P->tiles.size()));
+  ODP_HIP(up(P->ws.re_list, P->re_list.data(), sizeof(int32_t) * P->re_list.size()));
+  ODP_HIP(up(P->ws.re_first, P->re_first.data(), sizeof(int32_t) * P->re_first.size()));
+  if (!P->fmask.empty()) ODP_HIP(up(P->ws.fmask, P->fmask.data(), sizeof(float) * pp));
+  ODP_HIP(launch_fill(P->W_<float2>(P->ws.num), P->p_sub, make_float2(0.f, 0.f), s));
+  ODP_HIP(launch_illum(illum_args(P, P->W_<float2>(P->ws.w), 0, 1), s));
+  double* misc = P->W_<double>(P->ws.misc);
+  ODP_HIP(launch_sum_max(P->W_<double>(P->ws.den), P->p_sub, dev_sqrt_f, (int64_t)P->J * pp, misc, s));
+  double host[2] = {0, 0};
+  ODP_HIP(hipMemcpyAsync(host, misc, sizeof(host), hipMemcpyDeviceToHost, s));
+  ODP_HIP(hipStreamSynchronize(s));
+  P->illum_max = host[0];
+  return ODP_OK;
+}
+
+int odp_plan_illum_max(const odp_plan* P, double* out) {
+  if (!P || !out) return fail(ODP_EINVAL, "null argument");
+  if (!P->wsp) return fail(ODP_EINVAL, "plan is not bound");
+  *out = P->illum_max;
+  return ODP_OK;
+}
+
+int odp_plan_set_params(odp_plan* P, double eps, double eta, double r, double mu, double gamma, hipStream_t s) {
+  if (!P) return fail(ODP_EINVAL, "null argument");
+  int rc = check_params(eps, eta, r, mu, gamma, P->D, P->blind);
+  if (rc) return rc;
+  P->eps = eps;
+  P->eta = eta;
+  P->r = r;
+  P->mu = mu;
+  P->gamma = gamma;
+  if (P->wsp) ODP_HIP(launch_illum(illum_args(P, P->W_<float2>(P->ws.w), 0, 0), s));
+  return ODP_OK;
+}
+
+int odp_forward(const odp_plan* P, const odp_c32* u, const odp_c32* w, odp_c32* out, hipStream_t s) {
+  if (!P || !u || !w || !out) return fail(ODP_EINVAL, "null argument");
+  if (!P->wsp) return fail(ODP_EINVAL, "plan is not bound");
+  ODP_HIP(launch_forward(P->p, reinterpret_cast<const float2*>(u), P->H, P->W, reinterpret_cast<const float2*>(w),
+                         P->W_<float2>(P->ws.tw), P->W_<int32_t>(P->ws.offsets), P->J,
+                         reinterpret_cast<float2*>(out), s));
+  return ODP_OK;
+}
+
+int odp_adjoint(const odp_plan* P, const odp_c32* frames, const odp_c32* w, odp_c32* u_out, hipStream_t s) {
+  if (!P || !frames || !w || !u_out) return fail(ODP_EINVAL, "null argument");
+  if (!P->wsp) return fail(ODP_EINVAL, "plan is not bound");
+  ODP_HIP(launch_adjoint(P->p, reinterpret_cast<const float2*>(frames), reinterpret_cast<const float2*>(w),
+                         P->W_<float2>(P->ws.tw), P->W_<int32_t>(P->ws.offsets), P->J,
+                         reinterpret_cast<float2*>(u_out), P->H, P->W, s));
+  return ODP_OK;
+}
+
+int odp_prox_stagm(const odp_c32* y, const float* sqrt_f, int64_t count, float eps, float lambda, odp_c32* z,
+                   hipStream_t s) {
+  if (count < 0) return fail(ODP_EINVAL, "negative count");
+  if (count > 0 && (!y || !sqrt_f || !z)) return fail(ODP_EINVAL, "null argument");
+  if (!(eps > 0.f && eps < 1.f)) return fail(ODP_EINVAL, "eps must lie in (0, 1)");
+  if (!(lambda > 0.f)) return fail(ODP_EINVAL, "lambda must be positive");
+  ODP_HIP(launch_prox(reinterpret_cast<const float2*>(y), sqrt_f, count, eps, lambda, reinterpret_cast<float2*>(z),
+                      s));
+  return ODP_OK;
+}
+
+int odp_state_init(const odp_plan* P, void* dev_state, const odp_c32* dev_w0, hipStream_t s) {
+  if (!P || !dev_state) return fail(ODP_EINVAL, "null argument");
+  if (P->blind && !dev_w0) return fail(ODP_EINVAL, "blind state needs an initial probe");
+  char* b = static_cast<char*>(dev_state);
+  const size_t pp = (size_t)P->p * P->p;
+  ODP_HIP(launch_fill(reinterpret_cast<float2*>(b + P->st.u_sub), P->p_sub, make_float2(1.f, 0.f), s));
+  ODP_HIP(launch_fill(reinterpret_cast<float2*>(b + P->st.gamma), (int64_t)pp * P->J, make_float2(0.f, 0.f), s));
+  ODP_HIP(launch_fill(reinterpret_cast<float2*>(b + P->st.lam), P->n_lam, make_float2(0.f, 0.f), s));
+  if (P->blind) {
+    const float2* w0 = reinterpret_cast<const float2*>(dev_w0);
+    ODP_HIP(launch_copy(reinterpret_cast<float2*>(b + P->st.w), w0, (int64_t)pp, s));
+    for (int d = 0; d < P->D; ++d)
+      ODP_HIP(launch_copy(reinterpret_cast<float2*>(b + P->st.w_sub) + d * pp, w0, (int64_t)pp, s));
+    ODP_HIP(launch_fill(reinterpret_cast<float2*>(b + P->st.delta), (int64_t)pp * P->D, make_float2(0.f, 0.f), s));
+  }
+  return ODP_OK;
+}
+
+static SweepArgs sweep_args(const odp_plan* P, char* b, double* stats) {
+  SweepArgs a;
+  a.u = reinterpret_cast<const float2*>(b + P->st.u_sub);
+  a.num = P->W_<float2>(P->ws.num);
+  a.w = P->blind ? reinterpret_cast<const float2*>(b + P->st.w_sub) : P->W_<float2>(P->ws.w);
+  a.w_per_sub = P->blind;
+  a.tw = P->W_<float2>(P->ws.tw);
+  a.gamma = reinterpret_cast<float2*>(b + P->st.gamma);
+  a.sqrt_f = P->sqrt_f;
+  a.frames = P->W_<FrameDesc>(P->ws.frames);
+  a.order = P->W_<int32_t>(P->ws.order);
+  a.J = P->J;
+  a.chunk = P->chunk;
+  a.eps = (float)P->eps;
+  a.eta = (float)P->eta;
+  a.part = stats ? P->W_<double>(P->ws.fpart) : nullptr;
+  a.phi = P->blind ? P->W_<float2>(P->ws.phi) : nullptr;
+  return a;
+}
+
+static PixelArgs pixel_args(const odp_plan* P, char* b, double* stats) {
+  PixelArgs a;
+  a.u = reinterpret_cast<float2*>(b + P->st.u_sub);
+  a.num = P->W_<float2>(P->ws.num);
+  a.rcp = P->W_<float>(P->ws.rcp);
+  a.lam = reinterpret_cast<float2*>(b + P->st.lam);
+  a.cells = P->W_<CellDesc>(P->ws.cells);
+  a.tiles = P->W_<TileDesc>(P->ws.tiles);
+  a.n_tiles = (int32_t)P->tiles.size();
+  a.eta = (float)P->eta;
+  a.r = (float)P->r;
+  a.gamma = (float)P->gamma;
+  a.part = stats ? P->W_<double>(P->ws.tpart) : nullptr;
+  return a;
+}
+
+static int finish_stats(const odp_plan* P, double* stats, hipStream_t s) {
+  ODP_HIP(launch_stats(P->W_<double>(P->ws.fpart), P->J, P->W_<double>(P->ws.tpart), P->W_<int32_t>(P->ws.re_list),
+                       P->W_<int32_t>(P->ws.re_first), P->D, P->W_<double>(P->ws.misc) + 1, stats,
+                       P->W_<double>(P->ws.stat_scratch), s));
+  return ODP_OK;
+}
+
+int odp_admm_iterate(odp_plan* P, void* dev_state, int32_t n_iter, double* dev_stats, hipStream_t s) {
+  if (!P || !dev_state) return fail(ODP_EINVAL, "null argument");
+  if (!P->wsp) return fail(ODP_EINVAL, "plan is not bound");
+  if (n_iter < 0) return fail(ODP_EINVAL, "negative iteration count");
+  char* b = static_cast<char*>(dev_state);
+  for (int it = 0; it < n_iter; ++it) {
+    double* st = dev_stats ? dev_stats + 3 * (size_t)it : nullptr;
+    if (P->blind) {
+      int rc = odp_blind_sweep(P, dev_state, st, s);
+      if (rc) return rc;
+      rc = odp_probe_update(P, dev_state, s);
+      if (rc) return rc;
+      rc = odp_blind_pixel_update(P, dev_state, st, s);
+      if (rc) return rc;
+      continue;
+    }
+    ODP_HIP(launch_sweep(P->p, sweep_args(P, b, st), s));
+    ODP_HIP(launch_pixel(pixel_args(P, b, st), st != nullptr, s));
+    if (st) {
+      int rc = finish_stats(P, st, s);
+      if (rc) return rc;
+    }
+  }
+  return ODP_OK;
+}
+
+int odp_blind_sweep(odp_plan* P, void* dev_state, double* dev_stats, hipStream_t s) {
+  if (!P || !dev_state) return fail(ODP_EINVAL, "null argument");
+  if (!P->blind) return fail(ODP_EINVAL, "plan is not blind");
+  (void)dev_stats;
+  return fail(ODP_EUNSUPPORTED, "blind recovery is not built into this library yet");
+}
+
+int odp_probe_update(odp_plan* P, void* dev_state, hipStream_t s) {
+  (void)s;
+  if (!P || !dev_state) return fail(ODP_EINVAL, "null argument");
+  if (!P->blind) return fail(ODP_EINVAL, "plan is not blind");
+  return fail(ODP_EUNSUPPORTED, "blind recovery is not built into this library yet");
+}
+
+int odp_blind_pixel_update(odp_plan* P, void* dev_state, double* dev_stats, hipStream_t s) {
+  (void)s;
+  (void)dev_stats;
+  if (!P || !dev_state) return fail(ODP_EINVAL, "null argument");
+  if (!P->blind) return fail(ODP_EINVAL, "plan is not blind");
+  return fail(ODP_EUNSUPPORTED, "blind recovery is not built into this library yet");
+}
+
+int odp_merge(const odp_plan* P, const void* dev_state, odp_c32* u_out, hipStream_t s) {
+  if (!P || !dev_state || !u_out) return fail(ODP_EINVAL, "null argument");
+  if (!P->wsp) return fail(ODP_EINVAL, "plan is not bound");
+  const char* b = static_cast<const char*>(dev_state);
+  ODP_HIP(launch_merge(reinterpret_cast<const float2*>(b + P->st.u_sub), P->W_<int32_t>(P->ws.rects),
+                       P->W_<int64_t>(P->ws.usub_off), P->D, P->H, P->W, reinterpret_cast<float2*>(u_out), s));
+  return ODP_OK;
+}
+
+int odp_amp_loss(const odp_plan* P, const odp_c32* u, const odp_c32* w, double* loss_out, odp_c32* grad_u,
+                 odp_c32* grad_w, hipStream_t s) {
+  (void)s;
+  if (!P || !u || !w || !loss_out) return fail(ODP_EINVAL, "null argument");
+  (void)grad_u;
+  (void)grad_w;
+  return fail(ODP_EUNSUPPORTED, "amplitude loss is not built into this library yet");
+}
+
+}  // extern "C"

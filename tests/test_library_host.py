@@ -1,0 +1,110 @@
+"""Host-side checks of libodp.so that need no GPU: it loads, exports every symbol
+include/odp.h declares, validates its inputs, and its index maps (built in C++)
+agree bit for bit with the oracle's independently written geometry.
+"""
+from __future__ import annotations
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synthetic
+import paper_2011_00162_amd as odp
+from paper_2011_00162_amd._lib import EXPORTS, OdpError, ODP_EGEOM, ODP_EINVAL, ODP_EUNSUPPORTED
+from oracle.geometry import build_geometry, cover_count
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "odp.h")).read()
+    declared = set(re.findall(r"\b(odp_[a-z_0-9]+)\s*\(", header))
+    assert declared == set(EXPORTS)
+    L = odp.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+    assert b"gfx950" in L.odp_version()
+
+
+def _specs():
+    s = [synthetic.CONFIGS[k] for k in ("c1", "c2", "c5")]
+    s += synthetic.batch_specs(64)[:6]
+    s.append(synthetic.ProblemSpec("paper256", n=256, sigma=4, p=64, radius=24, quad=0.02, step=8,
+                                   jitter=0, dy=1, dx=2, peak=None, iters=1, seed=0))
+    s.append(synthetic.ProblemSpec("narrow", n=200, sigma=4, p=32, radius=12, quad=0.02, step=6,
+                                   jitter=2, dy=3, dx=9, peak=None, iters=1, seed=4))
+    return s
+
+
+@pytest.mark.parametrize("spec", _specs(), ids=lambda s: s.name)
+def test_geometry_bit_exact_against_oracle(spec):
+    pr = synthetic.draw_problem(spec)
+    og = build_geometry(spec.n, spec.n, spec.p, pr["offsets"], pr["frame_sub"])
+    plan = odp.Plan(spec.n, spec.n, spec.p, pr["offsets"], pr["frame_sub"], r=1.0, mu=1.0)
+    g = plan.geometry()
+    np.testing.assert_array_equal(g.rects, og.rects)
+    want_pairs = np.array([(a, b, *rc) for (a, b, rc) in og.pairs], dtype=np.int32).reshape(-1, 6)
+    np.testing.assert_array_equal(g.pairs, want_pairs)
+    np.testing.assert_array_equal(g.cover, cover_count(og))
+    assert plan.info.max_cover == int(cover_count(og).max())
+    # packed u_sub offsets follow the subdomain order; multiplier storage holds 2 per pair pixel
+    sizes = (og.rects[:, 2] - og.rects[:, 0]) * (og.rects[:, 3] - og.rects[:, 1])
+    np.testing.assert_array_equal(g.usub_off, np.concatenate([[0], np.cumsum(sizes)[:-1]]))
+    areas = [(rc[2] - rc[0]) * (rc[3] - rc[1]) for (_, _, rc) in og.pairs]
+    assert plan.info.n_lam == 2 * sum(areas)
+    assert plan.info.p_sub == int(sizes.sum())
+
+
+def test_c2_and_c5_pair_counts():
+    # 4x4 blocks: 12 horizontal + 12 vertical + 18 diagonal = 42 pairs; 8x8: 210
+    for key, want in (("c2", 42), ("c5", 210)):
+        spec = synthetic.CONFIGS[key]
+        pr = synthetic.draw_problem(spec)
+        plan = odp.Plan(spec.n, spec.n, spec.p, pr["offsets"], pr["frame_sub"], r=1.0, mu=1.0)
+        assert plan.info.n_pairs == want
+
+
+def _plan_args(**kw):
+    off, grid = synthetic.raster_offsets(64, 32, 8, 0, None)
+    sub = synthetic.block_partition(grid, 1, 2)
+    a = dict(H=64, W=64, p=32, offsets=off, frame_sub=sub, eps=0.5, eta=0.1, r=1.0)
+    a.update(kw)
+    return a
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(eps=1.0), ODP_EINVAL),
+    (dict(eps=0.0), ODP_EINVAL),
+    (dict(eta=0.0), ODP_EINVAL),
+    (dict(r=0.0), ODP_EINVAL),
+    (dict(p=48), ODP_EUNSUPPORTED),
+    (dict(H=16), ODP_EINVAL),
+])
+def test_plan_rejects_bad_parameters(kw, code):
+    with pytest.raises(OdpError) as e:
+        odp.Plan(**_plan_args(**kw))
+    assert e.value.code == code
+
+
+def test_plan_rejects_bad_geometry():
+    a = _plan_args()
+    off = a["offsets"].copy()
+    off[2, 1] = 40          # 40 + 32 > 64
+    with pytest.raises(OdpError) as e:
+        odp.Plan(**{**a, "offsets": off})
+    assert e.value.code == ODP_EGEOM
+    sub = a["frame_sub"].copy()
+    with pytest.raises(OdpError) as e:
+        odp.Plan(**{**a, "frame_sub": np.where(sub == 1, 2, sub), "D": 3})   # subdomain 1 empty
+    assert e.value.code == ODP_EGEOM
+    with pytest.raises(OdpError) as e:
+        odp.Plan(**{**a, "frame_sub": sub + 5, "D": 2})
+    assert e.value.code == ODP_EGEOM
+
+
+def test_one_subdomain_needs_no_overlap_penalty():
+    a = _plan_args(r=0.0, frame_sub=np.zeros(len(_plan_args()["offsets"]), np.int32))
+    plan = odp.Plan(**a)
+    assert plan.info.D == 1 and plan.info.n_pairs == 0 and plan.info.n_lam == 0
