@@ -19,8 +19,8 @@ EXPORTS = [
     "odp_plan_create", "odp_plan_destroy", "odp_plan_get_info", "odp_state_get_layout",
     "odp_plan_get_rects", "odp_plan_get_pairs", "odp_plan_get_cover", "odp_plan_bind",
     "odp_plan_illum_max", "odp_plan_set_params", "odp_forward", "odp_adjoint", "odp_prox_stagm",
-    "odp_state_init", "odp_admm_iterate", "odp_blind_sweep", "odp_probe_update",
-    "odp_blind_pixel_update", "odp_merge", "odp_amp_loss", "odp_last_error", "odp_version",
+    "odp_state_init", "odp_admm_iterate", "odp_frame_sweep", "odp_probe_update",
+    "odp_pixel_update", "odp_merge", "odp_amp_loss", "odp_last_error", "odp_version",
 ]
 
 
@@ -80,9 +80,9 @@ def lib() -> C.CDLL:
         "odp_prox_stagm": (C.c_int, [vp, vp, i64, f32, f32, vp, vp]),
         "odp_state_init": (C.c_int, [vp, vp, vp, vp]),
         "odp_admm_iterate": (C.c_int, [vp, vp, i32, vp, vp]),
-        "odp_blind_sweep": (C.c_int, [vp, vp, vp, vp]),
+        "odp_frame_sweep": (C.c_int, [vp, vp, vp, vp]),
         "odp_probe_update": (C.c_int, [vp, vp, vp]),
-        "odp_blind_pixel_update": (C.c_int, [vp, vp, vp, vp]),
+        "odp_pixel_update": (C.c_int, [vp, vp, vp, vp]),
         "odp_merge": (C.c_int, [vp, vp, vp, vp]),
         "odp_amp_loss": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
         "odp_last_error": (C.c_char_p, []),

@@ -215,6 +215,15 @@ class Plan:
         check(lib().odp_admm_iterate(self._h, _ptr(state.buf), int(n_iter), _ptr(st), _stream(stream)))
         return st
 
+    def frame_sweep(self, state: State, stats: torch.Tensor | None = None, stream=None) -> None:
+        check(lib().odp_frame_sweep(self._h, _ptr(state.buf), _ptr(stats), _stream(stream)))
+
+    def probe_update(self, state: State, stream=None) -> None:
+        check(lib().odp_probe_update(self._h, _ptr(state.buf), _stream(stream)))
+
+    def pixel_update(self, state: State, stats: torch.Tensor | None = None, stream=None) -> None:
+        check(lib().odp_pixel_update(self._h, _ptr(state.buf), _ptr(stats), _stream(stream)))
+
     def merge(self, state: State, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         i = self.info
         out = torch.empty((i.H, i.W), dtype=torch.complex64, device=state.buf.device) if out is None else out

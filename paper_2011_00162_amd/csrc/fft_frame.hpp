@@ -16,6 +16,8 @@
 //
 // The inverse runs the stages backwards with conjugated twiddles.  Neither
 // direction scales; the caller applies 1/p per direction (unitary F).
+// Twiddles come from a host-computed (FP64, rounded to FP32) table
+// tw[i][k] = W_p^{i k}, i < N2, k < 16, shared by stages A and B.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -127,16 +129,23 @@ struct Frame {
   // Stage-A line of thread t: column and r2.  Value r1 sits at row N2*r1 + r2.
   __device__ static __forceinline__ int a_col(int t) { return t % P; }
   __device__ static __forceinline__ int a_r2(int t) { return t / P; }
+  // r2 is constant over a wavefront when p >= 64: make that visible to the
+  // compiler so the stage-A twiddle row is fetched with scalar loads.
+  __device__ static __forceinline__ int uniform_r2(int t) {
+    if constexpr (P >= 64) return __builtin_amdgcn_readfirstlane(t / P);
+    return t / P;
+  }
 
   // ---- forward ---------------------------------------------------------------
   // v: the 16 spatial values of this thread's stage-A line (already multiplied
   // by the probe).  On return v holds 16 frequencies, see freq().
   __device__ static void forward(float2* v, float2* lds, const float2* __restrict__ tw, int t) {
     const int col = a_col(t), r2 = a_r2(t);
+    const float2* ta = tw + 16 * uniform_r2(t);
     dft16<false>(v);
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-      float2 x = (r2 == 0 || k == 0) ? v[k] : c_mul(v[k], tw[r2 * k]);
+      const float2 x = k == 0 ? v[k] : c_mul(v[k], ta[k]);
       lds[(N2 * k + r2) * LP + col] = x;
     }
     __syncthreads();
@@ -154,10 +163,11 @@ struct Frame {
     stage_b<true>(lds, tw, t);
     __syncthreads();
     const int col = a_col(t), r2 = a_r2(t);
+    const float2* ta = tw + 16 * uniform_r2(t);
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-      float2 x = lds[(N2 * k + r2) * LP + col];
-      v[k] = (r2 == 0 || k == 0) ? x : c_mulc(x, tw[r2 * k]);
+      const float2 x = lds[(N2 * k + r2) * LP + col];
+      v[k] = k == 0 ? x : c_mulc(x, ta[k]);
     }
     dft16<true>(v);
   }
@@ -165,13 +175,20 @@ struct Frame {
   template <bool INV>
   __device__ static __forceinline__ void stage_b(float2* lds, const float2* __restrict__ tw, int t) {
     const int c2 = t % N2, R = t / N2;
-    float2 v[16];
+    const float4* tb4 = reinterpret_cast<const float4*>(tw + 16 * c2);
+    float2 v[16], w[16];
+#pragma unroll
+    for (int k = 0; k < 16; k += 2) {
+      const float4 q = tb4[k / 2];
+      w[k] = make_float2(q.x, q.y);
+      w[k + 1] = make_float2(q.z, q.w);
+    }
     float2* row = lds + R * LP + c2;
     if (INV) {
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
-        float2 x = row[N2 * k];
-        v[k] = (c2 == 0 || k == 0) ? x : c_mulc(x, tw[c2 * k]);
+        const float2 x = row[N2 * k];
+        v[k] = k == 0 ? x : c_mulc(x, w[k]);
       }
       dft16<true>(v);
 #pragma unroll
@@ -181,7 +198,7 @@ struct Frame {
       for (int k = 0; k < 16; ++k) v[k] = row[N2 * k];
       dft16<false>(v);
 #pragma unroll
-      for (int k = 0; k < 16; ++k) row[N2 * k] = (c2 == 0 || k == 0) ? v[k] : c_mul(v[k], tw[c2 * k]);
+      for (int k = 0; k < 16; ++k) row[N2 * k] = k == 0 ? v[k] : c_mul(v[k], w[k]);
     }
   }
 

@@ -2,7 +2,7 @@
 //
 // Frame kernels run one workgroup per scan frame (p*p/16 threads, 16 complex
 // values per thread, frame transform through LDS, see fft_frame.hpp).  Pixel
-// kernels run one 256-thread workgroup per 4 x 64 tile of a cell (a rectangle
+// kernels run one 256-thread workgroup per 8 x 32 tile of a cell (a rectangle
 // covered by one fixed set of subdomains), so every descriptor load is uniform.
 #include <hip/hip_runtime.h>
 
@@ -60,13 +60,16 @@ __host__ __device__ inline ProxC prox_coeffs(double eps, double lam) {
 }
 
 __device__ __forceinline__ float2 prox_stagm(float2 y, float sf, const ProxC& c) {
-  const float ay = sqrtf(y.x * y.x + y.y * y.y);
-  const float rho = (ay < c.thr * sf) ? fmaxf(0.0f, ay * c.ctr) : fmaf(sf, c.ca, ay * c.cb);
-  if (ay > 0.0f) {
-    const float s = rho / ay;
+  const float a2 = y.x * y.x + y.y * y.y;
+  if (a2 > 0.0f) {
+    const float inv = __builtin_amdgcn_rsqf(a2);   // 1/|y|, about 1 ulp
+    const float ay = a2 * inv;
+    const float rho = (ay < c.thr * sf) ? fmaxf(0.0f, ay * c.ctr) : fmaf(sf, c.ca, ay * c.cb);
+    const float s = rho * inv;
     return make_float2(y.x * s, y.y * s);
   }
-  return make_float2(rho, 0.0f);
+  // y = 0: every phase is a minimiser; sign(0) = +1
+  return make_float2((0.0f < c.thr * sf) ? 0.0f : sf * c.ca, 0.0f);
 }
 
 // g_eps(x; b) of eq. obj-1 from |x| and sqrt(b), in FP64
@@ -84,10 +87,12 @@ __device__ __forceinline__ int sweep_frame(int32_t chunk, int32_t J, const int32
 }
 
 // ---------------------------------------------------------------------------
-// K1: frame sweep (Alg. 2 Steps 1-2 for the frames, and the A_d* part of Step 3)
+// K1: frame sweep (Alg. 2 Steps 1-2 for the frames, the A_d* half of Step 3)
 //   X = F(w o S_j u_d); y = Gamma + X; z = Prox(y); Gamma <- y - z;
-//   non-blind: num_d += S_j^T(conj(w) o F^{-1}(z - Gamma))
-//   blind:     phi_j = F^{-1}(z - Gamma) (the probe and image steps need it twice)
+//   psi_j = conj(w) o F^{-1}(z - Gamma)   (blind: F^{-1}(z - Gamma), the probe
+//   and image steps each apply their own probe copy)
+// Each frame's output goes to its own slot of psi, so no two workgroups write
+// the same address; the pixel update pulls the covering frames in a fixed order.
 // ---------------------------------------------------------------------------
 template <int P, bool BLIND, bool STATS>
 __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
@@ -98,7 +103,8 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
   if (j < 0) return;  // uniform over the workgroup
   const int t = threadIdx.x;
   const FrameDesc fd = a.frames[j];
-  const float2* w = a.w + (a.w_per_sub ? (size_t)fd.sub * P * P : 0);
+  const size_t woff = a.w_per_sub ? (size_t)fd.sub * P * P : 0;
+  const float2* w = a.w + woff;
   const int col = F::a_col(t), r2 = F::a_r2(t);
   const float inv_p = 1.0f / (float)P;
 
@@ -123,7 +129,7 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
     const float2 z = prox_stagm(y, sf, pc);
     const float2 g = c_sub(y, z);
     a.gamma[idx] = g;
-    v[e] = c_sub(z, g);
+    v[e] = c_scale(c_sub(z, g), inv_p);   // both 1/p factors of the unitary pair applied here
     if (STATS) {
       const double ax = sqrt((double)X.x * X.x + (double)X.y * X.y);
       mis += fabs(ax - (double)sf);
@@ -140,22 +146,18 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
   }
   __syncthreads();  // stage-C reads of all threads done before inverse writes reuse LDS
   F::inverse(v, lds, a.tw, t);
+  const float2* wo = a.w_out + woff;
 #pragma unroll
   for (int r1 = 0; r1 < 16; ++r1) {
     const int row = F::N2 * r1 + r2;
-    const float2 phi = c_scale(v[r1], inv_p);
-    if (BLIND) {
-      a.phi[fbase + row * P + col] = phi;
-    } else {
-      atomic_add_c(&a.num[fd.base + (int64_t)row * fd.pitch + col], c_mulc(phi, w[row * P + col]));
-    }
+    a.psi[fbase + row * P + col] = BLIND ? v[r1] : c_mulc(v[r1], wo[row * P + col]);
   }
 }
 
 hipError_t launch_sweep(int p, const SweepArgs& a, hipStream_t s) {
   const ProxC pc = prox_coeffs(a.eps, a.eta);
   const dim3 grid(NXCD * a.chunk);
-  const bool st = a.part != nullptr, bl = a.phi != nullptr;
+  const bool st = a.part != nullptr, bl = a.blind != 0;
 #define ODP_SWEEP(PP)                                                                        \
   if (p == PP) {                                                                             \
     constexpr int T = Frame<PP>::T;                                                          \
@@ -173,35 +175,69 @@ hipError_t launch_sweep(int p, const SweepArgs& a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// K3: pixel update (Alg. 2 Steps 1 (v), 3 (u) and 4 (Lam)) on one cell tile.
+// K3: pixel update (Alg. 2 Steps 1 (v), 3 (u) and 4 (Lam); Alg. 3 Step 4 (U)
+// and the Lam half of Step 5) on one 8 x 32 tile of a cell.
+//   num_d   = sum_{j in d, window covers x} psi_j(x - o_j)    (A_d*(z - Gamma), fixed order)
 //   v_{a,b} = (u_a + u_b + Lam_{a,b} + Lam_{b,a}) / 2        from the iterate n
-//   u_d     = (eta num_d + r sum_{e != d} (v_{d,e} - Lam_{d,e}) + gamma u_d) * rcp_d
+//   u_d     = (eta num_d + r sum_{e != d} (v_{d,e} - Lam_{d,e}) + gamma u_d) / (eta den_d + r k + gamma)
 //   Lam_{d,e} += u_d^{new} - v_{d,e}
+// Blind: num_d and the FP64 illumination den_d = sum |w_d|^2 both use the new
+// probe copy w_d, in the same pull.  Non-blind: the reciprocal comes from bind.
 // Pairs (s, t), s < t, of the cell's subdomain list are stored at index
 // t(t-1)/2 + s, so every register index below is a compile-time constant.
 // ---------------------------------------------------------------------------
-template <bool STATS>
+template <bool STATS, bool BLIND>
 __global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
   __shared__ double red[4];
-  const TileDesc td = a.tiles[blockIdx.x];
+  const int tile = blockIdx.x;
+  const TileDesc td = a.tiles[tile];
   const CellDesc* cd = a.cells + td.cell;
-  const int m = cd->m;
+  const int m = cd->m, p = a.p;
   const int tr = threadIdx.x / TILE_COLS, tc = threadIdx.x % TILE_COLS;
   const bool act = tr < td.nr && tc < td.nc;
   const int y = td.r0 + tr, x = td.c0 + tc;
+  const int yi = cd->r0 + y, xi = cd->c0 + x;  // image coordinates
 
   float2 uo[MAXS], un[MAXS];
-  if (act) {
-    float2 acc[MAXS];
-    int64_t idx[MAXS];
+  float2 acc[MAXS];
+  float rc[MAXS];
+  int64_t idx[MAXS];
 #pragma unroll
-    for (int s = 0; s < MAXS; ++s) {
-      if (s < m) {
+  for (int s = 0; s < MAXS; ++s) {
+    if (s < m) {
+      // A_d*(z - Gamma) at this pixel: the covering frames of subdomain sub[s]
+      float2 num = make_float2(0.f, 0.f);
+      double den = 0.0;
+      const float2* ws = BLIND ? a.w_sub + (size_t)cd->sub[s] * p * p : nullptr;
+      const int k1 = a.tf_first[tile * MAXS + s + 1];
+      for (int k = a.tf_first[tile * MAXS + s]; k < k1; ++k) {
+        const int j = a.tf_list[k];
+        const int dy = yi - a.offsets[2 * j], dx = xi - a.offsets[2 * j + 1];
+        if (act && (unsigned)dy < (unsigned)p && (unsigned)dx < (unsigned)p) {
+          const float2 ps = a.psi[(size_t)j * p * p + dy * p + dx];
+          if (BLIND) {
+            const float2 ww = ws[dy * p + dx];
+            num = c_add(num, c_mulc(ps, ww));
+            den += (double)ww.x * ww.x + (double)ww.y * ww.y;
+          } else {
+            num = c_add(num, ps);
+          }
+        }
+      }
+      if (act) {
         idx[s] = cd->ubase[s] + (int64_t)y * cd->upitch[s] + x;
         uo[s] = a.u[idx[s]];
-        acc[s] = c_add(c_scale(a.num[idx[s]], a.eta), c_scale(uo[s], a.gamma));
+        acc[s] = c_add(c_scale(num, a.eta), c_scale(uo[s], a.gamma));
+        if (BLIND) {
+          const double q = (double)a.eta * den + (double)a.r * (double)(m - 1) + (double)a.gamma;
+          rc[s] = q == 0.0 ? 0.0f : (float)(1.0 / q);
+        } else {
+          rc[s] = a.rcp[idx[s]];
+        }
       }
     }
+  }
+  if (act) {
 #pragma unroll
     for (int t = 1; t < MAXS; ++t) {
 #pragma unroll
@@ -219,10 +255,8 @@ __global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
 #pragma unroll
     for (int s = 0; s < MAXS; ++s) {
       if (s < m) {
-        const float rc = a.rcp[idx[s]];
-        un[s] = rc == 0.0f ? uo[s] : c_scale(acc[s], rc);
+        un[s] = rc[s] == 0.0f ? uo[s] : c_scale(acc[s], rc[s]);
         a.u[idx[s]] = un[s];
-        a.num[idx[s]] = make_float2(0.0f, 0.0f);
       }
     }
 #pragma unroll
@@ -254,45 +288,50 @@ __global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
         du = block_sum<256>(du, red);
         uu = block_sum<256>(uu, red);
         if (threadIdx.x == 0) {
-          a.part[((size_t)blockIdx.x * MAXS + s) * 2] = du;
-          a.part[((size_t)blockIdx.x * MAXS + s) * 2 + 1] = uu;
+          a.part[((size_t)tile * MAXS + s) * 2] = du;
+          a.part[((size_t)tile * MAXS + s) * 2 + 1] = uu;
         }
       }
     }
   }
 }
 
-hipError_t launch_pixel(const PixelArgs& a, bool stats, hipStream_t s) {
+hipError_t launch_pixel(const PixelArgs& a, bool stats, bool blind, hipStream_t s) {
   if (a.n_tiles == 0) return hipSuccess;
-  if (stats) hipLaunchKernelGGL(k_pixel<true>, dim3(a.n_tiles), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_pixel<false>, dim3(a.n_tiles), dim3(256), 0, s, a);
+  const dim3 g(a.n_tiles), b(256);
+  if (blind) {
+    if (stats) hipLaunchKernelGGL((k_pixel<true, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_pixel<false, true>), g, b, 0, s, a);
+  } else {
+    if (stats) hipLaunchKernelGGL((k_pixel<true, false>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_pixel<false, false>), g, b, 0, s, a);
+  }
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// K0: illumination den_d = sum_{j in d} S_j^T |w_d|^2 (eq. AtA) in FP64, in the
-// fixed order of the subdomain's frame list, and rcp = 1/(eta den + r k + gamma).
+// K0: illumination den_d = sum_{j in d} S_j^T |w|^2 (eq. AtA) in FP64, over the
+// tile's frame list in a fixed order, and rcp = 1/(eta den + r k + gamma).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_illum(IllumArgs a) {
-  const TileDesc td = a.tiles[blockIdx.x];
+  const int tile = blockIdx.x;
+  const TileDesc td = a.tiles[tile];
   const CellDesc* cd = a.cells + td.cell;
   const int tr = threadIdx.x / TILE_COLS, tc = threadIdx.x % TILE_COLS;
   if (!(tr < td.nr && tc < td.nc)) return;
   const int y = td.r0 + tr, x = td.c0 + tc;
-  const int yi = cd->r0 + y, xi = cd->c0 + x;  // image coordinates
+  const int yi = cd->r0 + y, xi = cd->c0 + x;
   const int m = cd->m, p = a.p;
   for (int s = 0; s < m; ++s) {
-    const int d = cd->sub[s];
     const int64_t idx = cd->ubase[s] + (int64_t)y * cd->upitch[s] + x;
     double den;
     if (a.recompute_den) {
-      const float2* w = a.w + (a.w_per_sub ? (size_t)d * p * p : 0);
       den = 0.0;
-      for (int k = a.sub_first[d]; k < a.sub_first[d + 1]; ++k) {
-        const int j = a.order[k];
+      for (int k = a.tf_first[tile * MAXS + s]; k < a.tf_first[tile * MAXS + s + 1]; ++k) {
+        const int j = a.tf_list[k];
         const int dy = yi - a.offsets[2 * j], dx = xi - a.offsets[2 * j + 1];
         if ((unsigned)dy < (unsigned)p && (unsigned)dx < (unsigned)p) {
-          const float2 ww = w[dy * p + dx];
+          const float2 ww = a.w[dy * p + dx];
           den += (double)ww.x * ww.x + (double)ww.y * ww.y;
         }
       }

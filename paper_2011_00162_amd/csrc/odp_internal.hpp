@@ -9,8 +9,8 @@ namespace odp {
 
 constexpr int MAXS = 8;                        // most subdomains over one pixel
 constexpr int MAXP = MAXS * (MAXS - 1) / 2;    // most pairs over one pixel
-constexpr int TILE_ROWS = 4;                   // pixel-update tile: 4 x 64 pixels, 256 threads
-constexpr int TILE_COLS = 64;
+constexpr int TILE_ROWS = 8;                   // pixel-update tile: 8 x 32 pixels, 256 threads
+constexpr int TILE_COLS = 32;
 constexpr int NXCD = 8;                        // MI355X accelerator complex dies
 
 // A cell is a rectangle of image pixels covered by the same set of subdomains
@@ -44,10 +44,10 @@ struct FrameDesc {
 // ---------------------------------------------------------------- launch args
 struct SweepArgs {
   const float2* u;           // u_sub
-  float2* num;               // A_d*(z - Gamma) accumulators, one per u_sub pixel
   const float2* w;           // probe [p][p] (non-blind) or copies [D][p][p] (blind)
+  const float2* w_out;       // the same probe, read again for the output multiply
   int w_per_sub;             // 1: w indexed by subdomain (blind)
-  const float2* tw;          // W_p^m, m < p
+  const float2* tw;          // twiddle table W_p^{i k}, [p/16][16]
   float2* gamma;             // [J][p][p]
   const float* sqrt_f;       // [J][p][p]
   const FrameDesc* frames;
@@ -55,29 +55,32 @@ struct SweepArgs {
   int32_t J, chunk;          // frames, frames per XCD slice
   float eps, eta;
   double* part;              // [J][2] stats partials (L1 misfit, G_eps) or null
-  float2* phi;               // blind: F^{-1}(z - Gamma) per frame, natural layout, or null
+  float2* psi;               // [J][p][p] per-frame output, natural spatial layout:
+                             //   non-blind conj(w) o F^{-1}(z - Gamma), blind F^{-1}(z - Gamma)
+  int blind;
 };
 
 struct PixelArgs {
   float2* u;                 // u_sub (updated in place)
-  float2* num;               // accumulators (read, then cleared)
-  const float* rcp;          // 1 / (eta den + r k + gamma); 0 = held pixel
+  const float* rcp;          // 1 / (eta den + r k + gamma); 0 = held pixel (non-blind)
   float2* lam;
   const CellDesc* cells;
   const TileDesc* tiles;
-  int32_t n_tiles;
+  int32_t n_tiles, p;
+  const float2* psi;         // per-frame outputs of the sweep
+  const int32_t* tf_first;   // [n_tiles*MAXS + 1]: frames of slot s overlapping tile t
+  const int32_t* tf_list;
+  const int32_t* offsets;    // [J][2]
+  const float2* w_sub;       // blind: probe copies (the illumination is formed in the pull)
   float eta, r, gamma;
   double* part;              // [n_tiles][MAXS][2] (|du|^2, |u|^2) or null
 };
 
 struct IllumArgs {           // den and rcp on every subdomain pixel
-  const float2* w;           // probe or probe copies
-  int w_per_sub;
-  const FrameDesc* frames;
-  const int32_t* order;      // frames grouped by subdomain
-  const int32_t* sub_first;  // [D+1] ranges of order per subdomain
+  const float2* w;           // probe
+  const int32_t* tf_first;   // per-tile frame lists (as in PixelArgs)
+  const int32_t* tf_list;
   const int32_t* offsets;    // [J][2]
-  const int32_t* rects;      // [D][4]
   const CellDesc* cells;
   const TileDesc* tiles;
   int32_t n_tiles, p;
@@ -88,7 +91,7 @@ struct IllumArgs {           // den and rcp on every subdomain pixel
 };
 
 hipError_t launch_sweep(int p, const SweepArgs& a, hipStream_t s);
-hipError_t launch_pixel(const PixelArgs& a, bool stats, hipStream_t s);
+hipError_t launch_pixel(const PixelArgs& a, bool stats, bool blind, hipStream_t s);
 hipError_t launch_illum(const IllumArgs& a, hipStream_t s);
 hipError_t launch_forward(int p, const float2* u, int H, int W, const float2* w, const float2* tw,
                           const int32_t* offsets, int J, float2* out, hipStream_t s);
@@ -106,13 +109,13 @@ hipError_t launch_merge(const float2* u_sub, const int32_t* rects, const int64_t
                         int H, int W, float2* out, hipStream_t s);
 hipError_t launch_copy(float2* dst, const float2* src, int64_t n, hipStream_t s);
 
-// blind (Alg. 3) pieces
+// blind (Alg. 3) probe steps
 struct ProbeArgs {
   const float2* u;           // u_sub (iterate n)
   const float2* phi;         // F^{-1}(Z - Gamma) per frame
   const FrameDesc* frames;
-  const int32_t* order;
-  const int32_t* sub_first;
+  const int32_t* order;      // frames grouped by subdomain
+  const int32_t* sub_first;  // [D+1]
   int32_t D, p;
   float2* w;                 // shared probe w (out: w^{n+1})
   float2* w_sub;             // copies [D][p][p] (in W^n, out W^{n+1})
@@ -120,18 +123,8 @@ struct ProbeArgs {
   const float* fmask;        // [p][p] support indicator or null
   const float2* tw;
   double eta, mu;
-  float2* scratch;           // [p][p] work buffer
 };
 hipError_t launch_probe_update(const ProbeArgs& a, hipStream_t s);
-
-struct ScatterArgs {         // num += S_j^T (conj(w_d) o phi_j), per frame
-  const float2* phi;
-  const float2* w_sub;
-  const FrameDesc* frames;
-  int32_t J, p;
-  float2* num;
-};
-hipError_t launch_blind_scatter(const ScatterArgs& a, hipStream_t s);
 
 struct LossArgs {
   const float2* u; int H, W;

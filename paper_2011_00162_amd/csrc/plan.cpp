@@ -16,7 +16,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/odp.h"
+#include "odp.h"
 #include "odp_internal.hpp"
 
 using namespace odp;
@@ -63,12 +63,13 @@ struct odp_plan {
   std::vector<FrameDesc> frames;
   std::vector<int32_t> order, sub_first;
   std::vector<int32_t> re_list, re_first;
+  std::vector<int32_t> tf_first, tf_list;   // per (tile, slot): frames whose window meets the tile
   std::vector<float2> tw;
   int32_t chunk = 0;
   // workspace layout (byte offsets)
   struct {
-    size_t tw, w, frames, order, sub_first, offsets, rects, usub_off, cells, tiles, re_list, re_first, den, rcp,
-        num, fpart, tpart, stat_scratch, misc, phi, fmask, probe_tmp, bytes;
+    size_t tw, w, frames, order, sub_first, offsets, rects, usub_off, cells, tiles, re_list, re_first, tf_first,
+        tf_list, den, rcp, fpart, tpart, stat_scratch, misc, psi, fmask, bytes;
   } ws{};
   struct {
     size_t u_sub, gamma, lam, w, w_sub, delta, bytes;
@@ -232,12 +233,36 @@ int build_geometry(odp_plan* P) {
   for (int j = 0; j < J; ++j) P->sub_first[P->frame_sub[j] + 1]++;
   for (int d = 0; d < D; ++d) P->sub_first[d + 1] += P->sub_first[d];
   P->chunk = (J + NXCD - 1) / NXCD;
-  // twiddles W_p^m = exp(-2 pi i m / p), FP64 on the host
-  P->tw.resize(p);
-  for (int m = 0; m < p; ++m) {
-    const double a = 2.0 * M_PI * (double)m / (double)p;
-    P->tw[m] = make_float2((float)std::cos(a), (float)-std::sin(a));
+  // per (tile, slot) lists of the slot's frames whose window meets the tile,
+  // ascending frame id (the pull order of the pixel update)
+  {
+    std::vector<std::vector<int32_t>> by_sub(D);
+    for (int j = 0; j < J; ++j) by_sub[P->frame_sub[j]].push_back(j);
+    P->tf_first.assign(P->tiles.size() * MAXS + 1, 0);
+    P->tf_list.clear();
+    for (size_t t = 0; t < P->tiles.size(); ++t) {
+      const TileDesc& td = P->tiles[t];
+      const CellDesc& cd = P->cells[td.cell];
+      const int y0 = cd.r0 + td.r0, y1 = y0 + td.nr, x0 = cd.c0 + td.c0, x1 = x0 + td.nc;
+      for (int s = 0; s < MAXS; ++s) {
+        P->tf_first[t * MAXS + s] = (int32_t)P->tf_list.size();
+        if (s >= cd.m) continue;
+        for (int j : by_sub[cd.sub[s]]) {
+          const int r = P->offsets[2 * j], c = P->offsets[2 * j + 1];
+          if (r < y1 && r + p > y0 && c < x1 && c + p > x0) P->tf_list.push_back(j);
+        }
+      }
+    }
+    P->tf_first[P->tiles.size() * MAXS] = (int32_t)P->tf_list.size();
   }
+  // twiddle table tw[i][k] = W_p^{i k} = exp(-2 pi i i k / p), i < p/16, k < 16, FP64 on the host
+  const int n2 = p / 16;
+  P->tw.resize((size_t)n2 * 16);
+  for (int i = 0; i < n2; ++i)
+    for (int k = 0; k < 16; ++k) {
+      const double a = 2.0 * M_PI * (double)(i * k) / (double)p;
+      P->tw[i * 16 + k] = make_float2((float)std::cos(a), (float)-std::sin(a));
+    }
   return ODP_OK;
 }
 
@@ -249,7 +274,7 @@ void layout(odp_plan* P) {
     return at;
   };
   const size_t pp = (size_t)P->p * P->p;
-  P->ws.tw = take(sizeof(float2) * P->p);
+  P->ws.tw = take(sizeof(float2) * P->tw.size());
   P->ws.w = take(sizeof(float2) * pp);
   P->ws.frames = take(sizeof(FrameDesc) * P->J);
   P->ws.order = take(sizeof(int32_t) * P->J);
@@ -261,16 +286,16 @@ void layout(odp_plan* P) {
   P->ws.tiles = take(sizeof(TileDesc) * P->tiles.size());
   P->ws.re_list = take(sizeof(int32_t) * std::max<size_t>(1, P->re_list.size()));
   P->ws.re_first = take(sizeof(int32_t) * (P->D + 1));
+  P->ws.tf_first = take(sizeof(int32_t) * P->tf_first.size());
+  P->ws.tf_list = take(sizeof(int32_t) * std::max<size_t>(1, P->tf_list.size()));
   P->ws.den = take(sizeof(double) * P->p_sub);
   P->ws.rcp = take(sizeof(float) * P->p_sub);
-  P->ws.num = take(sizeof(float2) * P->p_sub);
   P->ws.fpart = take(sizeof(double) * 2 * P->J);
   P->ws.tpart = take(sizeof(double) * 2 * MAXS * std::max<size_t>(1, P->tiles.size()));
   P->ws.stat_scratch = take(sizeof(double) * 2 * (P->D + 1));
   P->ws.misc = take(sizeof(double) * (2 + 2 * 1024 + 8));
-  P->ws.phi = P->blind ? take(sizeof(float2) * pp * P->J) : 0;
+  P->ws.psi = take(sizeof(float2) * pp * P->J);
   P->ws.fmask = take(sizeof(float) * pp);
-  P->ws.probe_tmp = take(sizeof(float2) * pp);
   P->ws.bytes = o;
   size_t s = 0;
   auto stake = [&](size_t bytes) {
@@ -297,15 +322,12 @@ int check_params(double eps, double eta, double r, double mu, double gamma, int 
   return ODP_OK;
 }
 
-IllumArgs illum_args(const odp_plan* P, const float2* w, int per_sub, int recompute) {
+IllumArgs illum_args(const odp_plan* P, const float2* w, int recompute) {
   IllumArgs a;
   a.w = w;
-  a.w_per_sub = per_sub;
-  a.frames = P->W_<FrameDesc>(P->ws.frames);
-  a.order = P->W_<int32_t>(P->ws.order);
-  a.sub_first = P->W_<int32_t>(P->ws.sub_first);
+  a.tf_first = P->W_<int32_t>(P->ws.tf_first);
+  a.tf_list = P->W_<int32_t>(P->ws.tf_list);
   a.offsets = P->W_<int32_t>(P->ws.offsets);
-  a.rects = P->W_<int32_t>(P->ws.rects);
   a.cells = P->W_<CellDesc>(P->ws.cells);
   a.tiles = P->W_<TileDesc>(P->ws.tiles);
   a.n_tiles = (int32_t)P->tiles.size();
@@ -470,9 +492,10 @@ int odp_plan_bind(odp_plan* P, void* dev_ws, const float* dev_sqrt_f, const odp_
   ODP_HIP(up(P->ws.tiles, P->tiles.data(), sizeof(TileDesc) * P->tiles.size()));
   ODP_HIP(up(P->ws.re_list, P->re_list.data(), sizeof(int32_t) * P->re_list.size()));
   ODP_HIP(up(P->ws.re_first, P->re_first.data(), sizeof(int32_t) * P->re_first.size()));
+  ODP_HIP(up(P->ws.tf_first, P->tf_first.data(), sizeof(int32_t) * P->tf_first.size()));
+  ODP_HIP(up(P->ws.tf_list, P->tf_list.data(), sizeof(int32_t) * P->tf_list.size()));
   if (!P->fmask.empty()) ODP_HIP(up(P->ws.fmask, P->fmask.data(), sizeof(float) * pp));
-  ODP_HIP(launch_fill(P->W_<float2>(P->ws.num), P->p_sub, make_float2(0.f, 0.f), s));
-  ODP_HIP(launch_illum(illum_args(P, P->W_<float2>(P->ws.w), 0, 1), s));
+  ODP_HIP(launch_illum(illum_args(P, P->W_<float2>(P->ws.w), 1), s));
   double* misc = P->W_<double>(P->ws.misc);
   ODP_HIP(launch_sum_max(P->W_<double>(P->ws.den), P->p_sub, dev_sqrt_f, (int64_t)P->J * pp, misc, s));
   double host[2] = {0, 0};
@@ -498,7 +521,7 @@ int odp_plan_set_params(odp_plan* P, double eps, double eta, double r, double mu
   P->r = r;
   P->mu = mu;
   P->gamma = gamma;
-  if (P->wsp) ODP_HIP(launch_illum(illum_args(P, P->W_<float2>(P->ws.w), 0, 0), s));
+  if (P->wsp) ODP_HIP(launch_illum(illum_args(P, P->W_<float2>(P->ws.w), 0), s));
   return ODP_OK;
 }
 
@@ -552,8 +575,8 @@ int odp_state_init(const odp_plan* P, void* dev_state, const odp_c32* dev_w0, hi
 static SweepArgs sweep_args(const odp_plan* P, char* b, double* stats) {
   SweepArgs a;
   a.u = reinterpret_cast<const float2*>(b + P->st.u_sub);
-  a.num = P->W_<float2>(P->ws.num);
   a.w = P->blind ? reinterpret_cast<const float2*>(b + P->st.w_sub) : P->W_<float2>(P->ws.w);
+  a.w_out = a.w;
   a.w_per_sub = P->blind;
   a.tw = P->W_<float2>(P->ws.tw);
   a.gamma = reinterpret_cast<float2*>(b + P->st.gamma);
@@ -565,19 +588,25 @@ static SweepArgs sweep_args(const odp_plan* P, char* b, double* stats) {
   a.eps = (float)P->eps;
   a.eta = (float)P->eta;
   a.part = stats ? P->W_<double>(P->ws.fpart) : nullptr;
-  a.phi = P->blind ? P->W_<float2>(P->ws.phi) : nullptr;
+  a.psi = P->W_<float2>(P->ws.psi);
+  a.blind = P->blind;
   return a;
 }
 
 static PixelArgs pixel_args(const odp_plan* P, char* b, double* stats) {
   PixelArgs a;
   a.u = reinterpret_cast<float2*>(b + P->st.u_sub);
-  a.num = P->W_<float2>(P->ws.num);
   a.rcp = P->W_<float>(P->ws.rcp);
   a.lam = reinterpret_cast<float2*>(b + P->st.lam);
   a.cells = P->W_<CellDesc>(P->ws.cells);
   a.tiles = P->W_<TileDesc>(P->ws.tiles);
   a.n_tiles = (int32_t)P->tiles.size();
+  a.p = P->p;
+  a.psi = P->W_<float2>(P->ws.psi);
+  a.tf_first = P->W_<int32_t>(P->ws.tf_first);
+  a.tf_list = P->W_<int32_t>(P->ws.tf_list);
+  a.offsets = P->W_<int32_t>(P->ws.offsets);
+  a.w_sub = P->blind ? reinterpret_cast<const float2*>(b + P->st.w_sub) : nullptr;
   a.eta = (float)P->eta;
   a.r = (float)P->r;
   a.gamma = (float)P->gamma;
@@ -592,52 +621,58 @@ static int finish_stats(const odp_plan* P, double* stats, hipStream_t s) {
   return ODP_OK;
 }
 
+int odp_frame_sweep(odp_plan* P, void* dev_state, double* dev_stats, hipStream_t s) {
+  if (!P || !dev_state) return fail(ODP_EINVAL, "null argument");
+  if (!P->wsp) return fail(ODP_EINVAL, "plan is not bound");
+  ODP_HIP(launch_sweep(P->p, sweep_args(P, static_cast<char*>(dev_state), dev_stats), s));
+  return ODP_OK;
+}
+
+int odp_probe_update(odp_plan* P, void* dev_state, hipStream_t s) {
+  if (!P || !dev_state) return fail(ODP_EINVAL, "null argument");
+  if (!P->wsp) return fail(ODP_EINVAL, "plan is not bound");
+  if (!P->blind) return fail(ODP_EINVAL, "plan is not blind");
+  char* b = static_cast<char*>(dev_state);
+  ProbeArgs a;
+  a.u = reinterpret_cast<const float2*>(b + P->st.u_sub);
+  a.phi = P->W_<float2>(P->ws.psi);
+  a.frames = P->W_<FrameDesc>(P->ws.frames);
+  a.order = P->W_<int32_t>(P->ws.order);
+  a.sub_first = P->W_<int32_t>(P->ws.sub_first);
+  a.D = P->D;
+  a.p = P->p;
+  a.w = reinterpret_cast<float2*>(b + P->st.w);
+  a.w_sub = reinterpret_cast<float2*>(b + P->st.w_sub);
+  a.delta = reinterpret_cast<float2*>(b + P->st.delta);
+  a.fmask = P->fmask.empty() ? nullptr : P->W_<float>(P->ws.fmask);
+  a.tw = P->W_<float2>(P->ws.tw);
+  a.eta = P->eta;
+  a.mu = P->mu;
+  ODP_HIP(launch_probe_update(a, s));
+  return ODP_OK;
+}
+
+int odp_pixel_update(odp_plan* P, void* dev_state, double* dev_stats, hipStream_t s) {
+  if (!P || !dev_state) return fail(ODP_EINVAL, "null argument");
+  if (!P->wsp) return fail(ODP_EINVAL, "plan is not bound");
+  ODP_HIP(launch_pixel(pixel_args(P, static_cast<char*>(dev_state), dev_stats), dev_stats != nullptr,
+                       P->blind != 0, s));
+  if (dev_stats) return finish_stats(P, dev_stats, s);
+  return ODP_OK;
+}
+
 int odp_admm_iterate(odp_plan* P, void* dev_state, int32_t n_iter, double* dev_stats, hipStream_t s) {
   if (!P || !dev_state) return fail(ODP_EINVAL, "null argument");
   if (!P->wsp) return fail(ODP_EINVAL, "plan is not bound");
   if (n_iter < 0) return fail(ODP_EINVAL, "negative iteration count");
-  char* b = static_cast<char*>(dev_state);
   for (int it = 0; it < n_iter; ++it) {
     double* st = dev_stats ? dev_stats + 3 * (size_t)it : nullptr;
-    if (P->blind) {
-      int rc = odp_blind_sweep(P, dev_state, st, s);
-      if (rc) return rc;
-      rc = odp_probe_update(P, dev_state, s);
-      if (rc) return rc;
-      rc = odp_blind_pixel_update(P, dev_state, st, s);
-      if (rc) return rc;
-      continue;
-    }
-    ODP_HIP(launch_sweep(P->p, sweep_args(P, b, st), s));
-    ODP_HIP(launch_pixel(pixel_args(P, b, st), st != nullptr, s));
-    if (st) {
-      int rc = finish_stats(P, st, s);
-      if (rc) return rc;
-    }
+    int rc = odp_frame_sweep(P, dev_state, st, s);
+    if (!rc && P->blind) rc = odp_probe_update(P, dev_state, s);
+    if (!rc) rc = odp_pixel_update(P, dev_state, st, s);
+    if (rc) return rc;
   }
   return ODP_OK;
-}
-
-int odp_blind_sweep(odp_plan* P, void* dev_state, double* dev_stats, hipStream_t s) {
-  if (!P || !dev_state) return fail(ODP_EINVAL, "null argument");
-  if (!P->blind) return fail(ODP_EINVAL, "plan is not blind");
-  (void)dev_stats;
-  return fail(ODP_EUNSUPPORTED, "blind recovery is not built into this library yet");
-}
-
-int odp_probe_update(odp_plan* P, void* dev_state, hipStream_t s) {
-  (void)s;
-  if (!P || !dev_state) return fail(ODP_EINVAL, "null argument");
-  if (!P->blind) return fail(ODP_EINVAL, "plan is not blind");
-  return fail(ODP_EUNSUPPORTED, "blind recovery is not built into this library yet");
-}
-
-int odp_blind_pixel_update(odp_plan* P, void* dev_state, double* dev_stats, hipStream_t s) {
-  (void)s;
-  (void)dev_stats;
-  if (!P || !dev_state) return fail(ODP_EINVAL, "null argument");
-  if (!P->blind) return fail(ODP_EINVAL, "plan is not blind");
-  return fail(ODP_EUNSUPPORTED, "blind recovery is not built into this library yet");
 }
 
 int odp_merge(const odp_plan* P, const void* dev_state, odp_c32* u_out, hipStream_t s) {

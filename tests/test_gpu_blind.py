@@ -1,0 +1,83 @@
+"""GPU parity of OD2BP (Algorithm 3): frame sweep with probe copies, probe update
+(w, w_d, Delta) and the U-step, against the FP64 oracle."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+from oracle import blind
+from tests.gpu_util import dev_c64, gpu_plan, host, rel, rel_list, rounded_inputs
+from tests.oracle_problems import oracle_problem, tiny_spec
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+
+
+def _blind_setup(spec, mu_scale=0.5, gamma=0.0, mask=None):
+    P = oracle_problem(spec)
+    w_true, _, f = rounded_inputs(P)
+    p = spec.p
+    w0 = synthetic.make_probe(p, spec.radius * 0.85, 0.0)
+    w0 = (w0 * np.sqrt(f.sum(axis=(1, 2)).mean() / max(np.sum(np.abs(w0) ** 2), 1e-30)))
+    w0 = w0.astype(np.complex64).astype(np.complex128)
+    g = P["geom"]
+    mu = mu_scale * P["eta"] * max(len(fr) for fr in g.frames_of)
+    plan = gpu_plan(P, blind=True, mu=mu, gamma=gamma, mask=mask)
+    st = plan.new_state(w0=dev_c64(w0))
+    return P, f, g, w0, mu, plan, st
+
+
+def _compare(st, ost, tol):
+    e_u = rel_list([host(t) for t in st.u_sub()], ost.u)
+    e_w = rel(host(st.probe()), ost.w)
+    e_ws = rel(host(st.probe_copies()), np.stack(ost.w_sub))
+    e_g = rel(host(st.gamma()), ost.gamma)
+    dl = np.stack(ost.delta)
+    e_d = rel(host(st.probe_multipliers()), dl) / 50 if np.linalg.norm(dl) > 0 else 0.0  # small differences
+    errs = dict(u=e_u, w=e_w, w_sub=e_ws, gamma=e_g, delta_over_50=e_d)
+    assert max(errs.values()) <= tol, errs
+
+
+@pytest.mark.parametrize("gamma", [0.0, 0.3])
+def test_blind_iterations_parity(gamma):
+    spec = tiny_spec(n=128, p=32, step=8, jitter=1, dy=2, dx=2, radius=12, peak=1e4)
+    say("blind parity gamma", gamma)
+    P, f, g, w0, mu, plan, st = _blind_setup(spec, gamma=gamma)
+    stats = host(plan.iterate(st, 1, stats=True))
+    ost, hist = blind.od2bp_run(g, f, w0, P["eps"], P["eta"], P["r"], mu, 1, gamma_p=gamma)
+    _compare(st, ost, 1e-5)
+    assert abs(stats[0, 0] - hist[0]["RF"]) <= 1e-5 * hist[0]["RF"]
+    plan.iterate(st, 9)
+    ost, _ = blind.od2bp_run(g, f, w0, P["eps"], P["eta"], P["r"], mu, 9, gamma_p=gamma, state=ost)
+    _compare(st, ost, 1e-3)   # K-iteration reconstruction bound
+
+
+def test_blind_with_support_mask():
+    spec = tiny_spec(n=128, p=32, step=8, jitter=0, dy=1, dx=2, radius=12, peak=None)
+    say("blind with support mask")
+    k = np.fft.fftfreq(32) * 32
+    mask = ((k[:, None] ** 2 + k[None, :] ** 2) <= 10 ** 2).astype(np.uint8)
+    P, f, g, w0, mu, plan, st = _blind_setup(spec, mask=mask)
+    plan.iterate(st, 1)
+    ost, _ = blind.od2bp_run(g, f, w0, P["eps"], P["eta"], P["r"], mu, 1, mask=mask)
+    _compare(st, ost, 1e-5)
+    plan.iterate(st, 2)
+    ost, _ = blind.od2bp_run(g, f, w0, P["eps"], P["eta"], P["r"], mu, 2, mask=mask, state=ost)
+    _compare(st, ost, 1e-3)   # K-iteration reconstruction bound
+    # the shared probe's spectrum vanishes off the support
+    spec_w = np.fft.fft2(host(st.probe()), norm="ortho")
+    assert np.abs(spec_w[mask == 0]).max() <= 1e-5 * np.abs(spec_w).max()
+
+
+def test_blind_p64_single_run():
+    spec = tiny_spec(n=192, p=64, step=16, jitter=2, dy=2, dx=2, radius=24, peak=1e4)
+    say("blind p64")
+    P, f, g, w0, mu, plan, st = _blind_setup(spec)
+    plan.iterate(st, 5)
+    ost, _ = blind.od2bp_run(g, f, w0, P["eps"], P["eta"], P["r"], mu, 5)
+    _compare(st, ost, 1e-3)   # K-iteration reconstruction bound
