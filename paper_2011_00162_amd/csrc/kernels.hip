@@ -8,33 +8,13 @@
 
 #include "fft_frame.hpp"
 #include "odp_internal.hpp"
+#include "reduce.hpp"
 
 namespace odp {
 
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Block-wide sum in a fixed order (deterministic); every thread gets the total.
-template <int NT>
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  constexpr int NW = NT / 64;
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  double t = 0.0;
-#pragma unroll
-  for (int i = 0; i < NW; ++i) t += sh[i];
-  return t;
-}
 
 __device__ __forceinline__ void atomic_add_c(float2* p, float2 v) {
   unsafeAtomicAdd(&p->x, v.x);
@@ -59,17 +39,16 @@ __host__ __device__ inline ProxC prox_coeffs(double eps, double lam) {
   return c;
 }
 
+// Branch-free: selects only, so a wavefront never splits on the data.
 __device__ __forceinline__ float2 prox_stagm(float2 y, float sf, const ProxC& c) {
   const float a2 = y.x * y.x + y.y * y.y;
-  if (a2 > 0.0f) {
-    const float inv = __builtin_amdgcn_rsqf(a2);   // 1/|y|, about 1 ulp
-    const float ay = a2 * inv;
-    const float rho = (ay < c.thr * sf) ? fmaxf(0.0f, ay * c.ctr) : fmaf(sf, c.ca, ay * c.cb);
-    const float s = rho * inv;
-    return make_float2(y.x * s, y.y * s);
-  }
+  const bool nz = a2 > 0.0f;
+  const float inv = nz ? __builtin_amdgcn_rsqf(a2) : 0.0f;   // 1/|y|, about 1 ulp
+  const float ay = a2 * inv;                                  // |y| (0 for y = 0)
+  const float rho = (ay < c.thr * sf) ? fmaxf(0.0f, ay * c.ctr) : fmaf(sf, c.ca, ay * c.cb);
+  const float s = rho * inv;
   // y = 0: every phase is a minimiser; sign(0) = +1
-  return make_float2((0.0f < c.thr * sf) ? 0.0f : sf * c.ca, 0.0f);
+  return nz ? make_float2(y.x * s, y.y * s) : make_float2(rho, 0.0f);
 }
 
 // g_eps(x; b) of eq. obj-1 from |x| and sqrt(b), in FP64
@@ -186,6 +165,54 @@ hipError_t launch_sweep(int p, const SweepArgs& a, hipStream_t s) {
 // Pairs (s, t), s < t, of the cell's subdomain list are stored at index
 // t(t-1)/2 + s, so every register index below is a compile-time constant.
 // ---------------------------------------------------------------------------
+// Sum of the covering frames' contributions at image pixel (yi, xi), over the
+// records [k0, k1) in order.  Loads are unconditional (out-of-window lanes read
+// element 0 and discard it) and four records are fetched per step, so several
+// loads are in flight per wavefront.
+template <bool BLIND>
+__device__ __forceinline__ void pull_pixel(const PullEntry* __restrict__ pull, int k0, int k1,
+                                           const float2* __restrict__ psi, const float2* __restrict__ ws,
+                                           int yi, int xi, int p, bool act, float2& num, double& den) {
+  const int64_t pix = (int64_t)yi * p + xi;
+  int k = k0;
+  for (; k + 4 <= k1; k += 4) {
+    PullEntry e[4];
+    bool in[4];
+    float2 ps[4], ww[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      e[q] = pull[k + q];
+      const int dy = yi - e[q].r, dx = xi - e[q].c;
+      in[q] = act && (unsigned)dy < (unsigned)p && (unsigned)dx < (unsigned)p;
+      ps[q] = psi[in[q] ? e[q].base + pix : 0];
+      if (BLIND) ww[q] = ws[in[q] ? dy * p + dx : 0];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (BLIND) {
+        const float2 c = c_mulc(ps[q], ww[q]);
+        num = in[q] ? c_add(num, c) : num;
+        den += in[q] ? (double)ww[q].x * ww[q].x + (double)ww[q].y * ww[q].y : 0.0;
+      } else {
+        num = in[q] ? c_add(num, ps[q]) : num;
+      }
+    }
+  }
+  for (; k < k1; ++k) {
+    const PullEntry e = pull[k];
+    const int dy = yi - e.r, dx = xi - e.c;
+    const bool in = act && (unsigned)dy < (unsigned)p && (unsigned)dx < (unsigned)p;
+    const float2 ps = psi[in ? e.base + pix : 0];
+    if (BLIND) {
+      const float2 ww = ws[in ? dy * p + dx : 0];
+      num = in ? c_add(num, c_mulc(ps, ww)) : num;
+      den += in ? (double)ww.x * ww.x + (double)ww.y * ww.y : 0.0;
+    } else {
+      num = in ? c_add(num, ps) : num;
+    }
+  }
+}
+
 template <bool STATS, bool BLIND>
 __global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
   __shared__ double red[4];
@@ -209,21 +236,8 @@ __global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
       float2 num = make_float2(0.f, 0.f);
       double den = 0.0;
       const float2* ws = BLIND ? a.w_sub + (size_t)cd->sub[s] * p * p : nullptr;
-      const int k1 = a.tf_first[tile * MAXS + s + 1];
-      for (int k = a.tf_first[tile * MAXS + s]; k < k1; ++k) {
-        const int j = a.tf_list[k];
-        const int dy = yi - a.offsets[2 * j], dx = xi - a.offsets[2 * j + 1];
-        if (act && (unsigned)dy < (unsigned)p && (unsigned)dx < (unsigned)p) {
-          const float2 ps = a.psi[(size_t)j * p * p + dy * p + dx];
-          if (BLIND) {
-            const float2 ww = ws[dy * p + dx];
-            num = c_add(num, c_mulc(ps, ww));
-            den += (double)ww.x * ww.x + (double)ww.y * ww.y;
-          } else {
-            num = c_add(num, ps);
-          }
-        }
-      }
+      pull_pixel<BLIND>(a.pull, a.tf_first[tile * MAXS + s], a.tf_first[tile * MAXS + s + 1], a.psi, ws,
+                        yi, xi, p, act, num, den);
       if (act) {
         idx[s] = cd->ubase[s] + (int64_t)y * cd->upitch[s] + x;
         uo[s] = a.u[idx[s]];
@@ -328,8 +342,8 @@ __global__ __launch_bounds__(256) void k_illum(IllumArgs a) {
     if (a.recompute_den) {
       den = 0.0;
       for (int k = a.tf_first[tile * MAXS + s]; k < a.tf_first[tile * MAXS + s + 1]; ++k) {
-        const int j = a.tf_list[k];
-        const int dy = yi - a.offsets[2 * j], dx = xi - a.offsets[2 * j + 1];
+        const PullEntry pe = a.pull[k];
+        const int dy = yi - pe.r, dx = xi - pe.c;
         if ((unsigned)dy < (unsigned)p && (unsigned)dx < (unsigned)p) {
           const float2 ww = a.w[dy * p + dx];
           den += (double)ww.x * ww.x + (double)ww.y * ww.y;

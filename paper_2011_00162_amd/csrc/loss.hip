@@ -1,0 +1,155 @@
+// loss.hip -- amplitude data term and its gradients (the frame model of Sec. 2).
+//
+//   L      = sum_j || |X_j| - sqrt(f_j) ||^2,  X_j = F(w o S_j u)  (F unitary)
+//   g_j    = 2 (1 - sqrt(f_j)/|X_j|) X_j        (0 where X_j = 0)
+//   dL/du  = sum_j S_j^T( conj(w) o F^{-1} g_j )
+//   dL/dw  = sum_j conj(S_j u) o F^{-1} g_j
+// Gradients are dL/dRe + i dL/dIm.  One workgroup per frame recomputes X_j and
+// writes phi_j = F^{-1} g_j; the image gradient is pulled per pixel over the
+// covering frames and the probe gradient is reduced over frames in FP64, both in
+// a fixed order.
+#include <hip/hip_runtime.h>
+
+#include "fft_frame.hpp"
+#include "odp_internal.hpp"
+#include "reduce.hpp"
+
+namespace odp {
+
+template <int P, bool GRAD>
+__global__ __launch_bounds__(Frame<P>::T) void k_loss(LossArgs a) {
+  using F = Frame<P>;
+  __shared__ float2 lds[F::LDS];
+  __shared__ double red[F::T / 64];
+  const int j = blockIdx.x, t = threadIdx.x;
+  const int col = F::a_col(t), r2 = F::a_r2(t);
+  const int64_t base = (int64_t)a.offsets[2 * j] * a.W + a.offsets[2 * j + 1];
+  const float inv_p = 1.0f / (float)P;
+  float2 v[16];
+#pragma unroll
+  for (int r1 = 0; r1 < 16; ++r1) {
+    const int row = F::N2 * r1 + r2;
+    v[r1] = c_mul(a.u[base + (int64_t)row * a.W + col], a.w[row * P + col]);
+  }
+  F::forward(v, lds, a.tw, t);
+  double loss = 0.0;
+  const size_t fbase = (size_t)j * P * P;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    int kr, kc;
+    F::freq(t, e, kr, kc);
+    const float2 X = c_scale(v[e], inv_p);
+    const float sf = a.sqrt_f[fbase + kr * P + kc];
+    const float a2 = X.x * X.x + X.y * X.y;
+    const double ax = sqrt((double)a2);
+    loss += (ax - sf) * (ax - sf);
+    if (GRAD) {
+      const bool nz = a2 > 0.0f;
+      const float inv = nz ? __builtin_amdgcn_rsqf(a2) : 0.0f;
+      const float sc = nz ? 2.0f * (1.0f - sf * inv) : 0.0f;
+      v[e] = c_scale(X, sc * inv_p);
+    }
+  }
+  loss = block_sum<F::T>(loss, red);
+  if (t == 0) a.frame_loss[j] = loss;
+  if (!GRAD) return;
+  __syncthreads();
+  F::inverse(v, lds, a.tw, t);
+#pragma unroll
+  for (int r1 = 0; r1 < 16; ++r1) a.phi[fbase + (F::N2 * r1 + r2) * P + col] = v[r1];
+}
+
+// dL/du on every subdomain tile: pull over all frames covering the pixel (every
+// slot of the tile's cell holds a disjoint set of frames).  Pixels in no
+// subdomain are covered by no frame and stay 0 (cleared by the caller).
+__global__ __launch_bounds__(256) void k_grad_u(LossGradArgs a) {
+  const int tile = blockIdx.x;
+  const TileDesc td = a.tiles[tile];
+  const CellDesc* cd = a.cells + td.cell;
+  const int tr = threadIdx.x / TILE_COLS, tc = threadIdx.x % TILE_COLS;
+  const bool act = tr < td.nr && tc < td.nc;
+  const int yi = cd->r0 + td.r0 + tr, xi = cd->c0 + td.c0 + tc;
+  const int p = a.p;
+  // tiles partition the covered pixels, so each pixel is written by one thread
+  float2 g = make_float2(0.f, 0.f);
+  const int64_t pix = (int64_t)yi * p + xi;
+  for (int s = 0; s < cd->m; ++s) {
+    const int k1 = a.tf_first[tile * MAXS + s + 1];
+    for (int k = a.tf_first[tile * MAXS + s]; k < k1; ++k) {
+      const PullEntry pe = a.pull[k];
+      const int dy = yi - pe.r, dx = xi - pe.c;
+      if (act && (unsigned)dy < (unsigned)p && (unsigned)dx < (unsigned)p)
+        g = c_add(g, c_mulc(a.phi[pe.base + pix], a.w[dy * p + dx]));
+    }
+  }
+  if (act) a.grad_u[(int64_t)yi * a.W + xi] = g;
+}
+
+// dL/dw partial sums over frame chunks (FP64), then a fixed-order final sum.
+__global__ __launch_bounds__(256) void k_grad_w_part(LossGradArgs a) {
+  const int p = a.p, k = blockIdx.x * 256 + threadIdx.x, chunk = blockIdx.y;
+  if (k >= p * p) return;
+  const int ky = k / p, kx = k % p;
+  const int j0 = chunk * a.frames_per_chunk;
+  const int j1 = min(a.J, j0 + a.frames_per_chunk);
+  double gx = 0.0, gy = 0.0;
+  for (int j = j0; j < j1; ++j) {
+    const float2 uu = a.u[((int64_t)a.offsets[2 * j] + ky) * a.W + a.offsets[2 * j + 1] + kx];
+    const float2 ph = a.phi[(size_t)j * p * p + k];
+    gx += (double)uu.x * ph.x + (double)uu.y * ph.y;     // conj(u) * phi
+    gy += (double)uu.x * ph.y - (double)uu.y * ph.x;
+  }
+  a.wpart[2 * ((size_t)chunk * p * p + k)] = gx;
+  a.wpart[2 * ((size_t)chunk * p * p + k) + 1] = gy;
+}
+
+__global__ __launch_bounds__(256) void k_grad_w_final(LossGradArgs a) {
+  const int p = a.p, k = blockIdx.x * 256 + threadIdx.x;
+  if (k < p * p) {
+    double gx = 0.0, gy = 0.0;
+    for (int c = 0; c < a.n_chunks; ++c) {
+      gx += a.wpart[2 * ((size_t)c * p * p + k)];
+      gy += a.wpart[2 * ((size_t)c * p * p + k) + 1];
+    }
+    a.grad_w[k] = make_float2((float)gx, (float)gy);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_loss_total(const double* frame_loss, int J, double* out) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int j = threadIdx.x; j < J; j += 256) s += frame_loss[j];
+  s = block_sum<256>(s, sh);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+hipError_t launch_loss(int p, const LossArgs& a, bool grad, hipStream_t s) {
+#define ODP_LOSS(PP)                                                                                   \
+  if (p == PP) {                                                                                       \
+    if (grad) hipLaunchKernelGGL((k_loss<PP, true>), dim3(a.J), dim3(Frame<PP>::T), 0, s, a);            \
+    else hipLaunchKernelGGL((k_loss<PP, false>), dim3(a.J), dim3(Frame<PP>::T), 0, s, a);                \
+    return hipGetLastError();                                                                          \
+  }
+  ODP_LOSS(32)
+  ODP_LOSS(64)
+  ODP_LOSS(128)
+#undef ODP_LOSS
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_loss_total(const double* frame_loss, int J, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, s, frame_loss, J, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_grads(const LossGradArgs& a, hipStream_t s) {
+  if (a.grad_u && a.n_tiles > 0) hipLaunchKernelGGL(k_grad_u, dim3(a.n_tiles), dim3(256), 0, s, a);
+  if (a.grad_w) {
+    const int nb = (a.p * a.p + 255) / 256;
+    hipLaunchKernelGGL(k_grad_w_part, dim3(nb, a.n_chunks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_grad_w_final, dim3(nb), dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace odp

@@ -35,6 +35,14 @@ struct TileDesc {
   int32_t pad[3];
 };
 
+// One covering frame of a pixel tile: psi index of pixel (y, x) of the image is
+// base + y*p + x (base = j*p*p - row_j*p - col_j); the window is rows
+// [row_j, row_j + p) and columns [col_j, col_j + p).
+struct PullEntry {
+  int64_t base;
+  int32_t r, c;
+};
+
 struct FrameDesc {
   int64_t base;              // u_sub index of the window's top-left inside its subdomain
   int32_t pitch;             // row pitch of that subdomain
@@ -69,8 +77,7 @@ struct PixelArgs {
   int32_t n_tiles, p;
   const float2* psi;         // per-frame outputs of the sweep
   const int32_t* tf_first;   // [n_tiles*MAXS + 1]: frames of slot s overlapping tile t
-  const int32_t* tf_list;
-  const int32_t* offsets;    // [J][2]
+  const PullEntry* pull;     // their records, ascending frame id
   const float2* w_sub;       // blind: probe copies (the illumination is formed in the pull)
   float eta, r, gamma;
   double* part;              // [n_tiles][MAXS][2] (|du|^2, |u|^2) or null
@@ -79,8 +86,7 @@ struct PixelArgs {
 struct IllumArgs {           // den and rcp on every subdomain pixel
   const float2* w;           // probe
   const int32_t* tf_first;   // per-tile frame lists (as in PixelArgs)
-  const int32_t* tf_list;
-  const int32_t* offsets;    // [J][2]
+  const PullEntry* pull;
   const CellDesc* cells;
   const TileDesc* tiles;
   int32_t n_tiles, p;
@@ -127,19 +133,37 @@ struct ProbeArgs {
 hipError_t launch_probe_update(const ProbeArgs& a, hipStream_t s);
 
 struct LossArgs {
-  const float2* u; int H, W;
-  const float2* w;
+  const float2* u;           // image [H][W]
+  int32_t H, W;
+  const float2* w;           // probe [p][p]
   const float2* tw;
-  const float* sqrt_f;
-  const int32_t* offsets;
+  const float* sqrt_f;       // [J][p][p]
+  const int32_t* offsets;    // [J][2]
   int32_t J;
   double* frame_loss;        // [J]
-  float2* grad_u;            // [H][W] or null (atomic accumulation, cleared by the caller)
-  float2* phi;               // [J][p][p] F^{-1} g_j (for the probe gradient) or null
+  float2* phi;               // [J][p][p] F^{-1} g_j, natural spatial layout
 };
-hipError_t launch_loss(int p, const LossArgs& a, hipStream_t s);
-hipError_t launch_probe_grad(const float2* u, int H, int W, const float2* phi, const int32_t* offsets,
-                             int J, int p, double* loss_parts, double* loss_out, float2* grad_w,
-                             hipStream_t s);
+
+struct LossGradArgs {
+  const float2* u;
+  int32_t W;
+  const float2* w;
+  const float2* phi;
+  const int32_t* offsets;
+  int32_t J, p;
+  const CellDesc* cells;
+  const TileDesc* tiles;
+  int32_t n_tiles;
+  const int32_t* tf_first;
+  const PullEntry* pull;
+  float2* grad_u;            // [H][W] or null
+  float2* grad_w;            // [p][p] or null
+  double* wpart;             // [n_chunks][p][p][2]
+  int32_t n_chunks, frames_per_chunk;
+};
+
+hipError_t launch_loss(int p, const LossArgs& a, bool grad, hipStream_t s);
+hipError_t launch_loss_total(const double* frame_loss, int J, double* out, hipStream_t s);
+hipError_t launch_loss_grads(const LossGradArgs& a, hipStream_t s);
 
 }  // namespace odp

@@ -38,6 +38,8 @@ int fail(int code, const std::string& msg) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+constexpr int LOSS_CHUNKS = 32;   // frame chunks of the probe-gradient reduction
+
 struct Pair {
   int32_t a, b, r0, c0, r1, c1;
   int64_t off;  // lam index of Lam_{a,b}; Lam_{b,a} follows after h*w
@@ -63,13 +65,14 @@ struct odp_plan {
   std::vector<FrameDesc> frames;
   std::vector<int32_t> order, sub_first;
   std::vector<int32_t> re_list, re_first;
-  std::vector<int32_t> tf_first, tf_list;   // per (tile, slot): frames whose window meets the tile
+  std::vector<int32_t> tf_first;            // per (tile, slot): range of pull records
+  std::vector<PullEntry> pull;              // frames whose window meets the tile, ascending id
   std::vector<float2> tw;
   int32_t chunk = 0;
   // workspace layout (byte offsets)
   struct {
     size_t tw, w, frames, order, sub_first, offsets, rects, usub_off, cells, tiles, re_list, re_first, tf_first,
-        tf_list, den, rcp, fpart, tpart, stat_scratch, misc, psi, fmask, bytes;
+        pull, den, rcp, fpart, tpart, stat_scratch, misc, psi, fmask, wpart, bytes;
   } ws{};
   struct {
     size_t u_sub, gamma, lam, w, w_sub, delta, bytes;
@@ -239,21 +242,22 @@ int build_geometry(odp_plan* P) {
     std::vector<std::vector<int32_t>> by_sub(D);
     for (int j = 0; j < J; ++j) by_sub[P->frame_sub[j]].push_back(j);
     P->tf_first.assign(P->tiles.size() * MAXS + 1, 0);
-    P->tf_list.clear();
+    P->pull.clear();
     for (size_t t = 0; t < P->tiles.size(); ++t) {
       const TileDesc& td = P->tiles[t];
       const CellDesc& cd = P->cells[td.cell];
       const int y0 = cd.r0 + td.r0, y1 = y0 + td.nr, x0 = cd.c0 + td.c0, x1 = x0 + td.nc;
       for (int s = 0; s < MAXS; ++s) {
-        P->tf_first[t * MAXS + s] = (int32_t)P->tf_list.size();
+        P->tf_first[t * MAXS + s] = (int32_t)P->pull.size();
         if (s >= cd.m) continue;
         for (int j : by_sub[cd.sub[s]]) {
           const int r = P->offsets[2 * j], c = P->offsets[2 * j + 1];
-          if (r < y1 && r + p > y0 && c < x1 && c + p > x0) P->tf_list.push_back(j);
+          if (r < y1 && r + p > y0 && c < x1 && c + p > x0)
+            P->pull.push_back(PullEntry{(int64_t)j * p * p - (int64_t)r * p - c, r, c});
         }
       }
     }
-    P->tf_first[P->tiles.size() * MAXS] = (int32_t)P->tf_list.size();
+    P->tf_first[P->tiles.size() * MAXS] = (int32_t)P->pull.size();
   }
   // twiddle table tw[i][k] = W_p^{i k} = exp(-2 pi i i k / p), i < p/16, k < 16, FP64 on the host
   const int n2 = p / 16;
@@ -287,7 +291,7 @@ void layout(odp_plan* P) {
   P->ws.re_list = take(sizeof(int32_t) * std::max<size_t>(1, P->re_list.size()));
   P->ws.re_first = take(sizeof(int32_t) * (P->D + 1));
   P->ws.tf_first = take(sizeof(int32_t) * P->tf_first.size());
-  P->ws.tf_list = take(sizeof(int32_t) * std::max<size_t>(1, P->tf_list.size()));
+  P->ws.pull = take(sizeof(PullEntry) * std::max<size_t>(1, P->pull.size()));
   P->ws.den = take(sizeof(double) * P->p_sub);
   P->ws.rcp = take(sizeof(float) * P->p_sub);
   P->ws.fpart = take(sizeof(double) * 2 * P->J);
@@ -296,6 +300,7 @@ void layout(odp_plan* P) {
   P->ws.misc = take(sizeof(double) * (2 + 2 * 1024 + 8));
   P->ws.psi = take(sizeof(float2) * pp * P->J);
   P->ws.fmask = take(sizeof(float) * pp);
+  P->ws.wpart = take(sizeof(double) * 2 * pp * LOSS_CHUNKS);
   P->ws.bytes = o;
   size_t s = 0;
   auto stake = [&](size_t bytes) {
@@ -326,8 +331,7 @@ IllumArgs illum_args(const odp_plan* P, const float2* w, int recompute) {
   IllumArgs a;
   a.w = w;
   a.tf_first = P->W_<int32_t>(P->ws.tf_first);
-  a.tf_list = P->W_<int32_t>(P->ws.tf_list);
-  a.offsets = P->W_<int32_t>(P->ws.offsets);
+  a.pull = P->W_<PullEntry>(P->ws.pull);
   a.cells = P->W_<CellDesc>(P->ws.cells);
   a.tiles = P->W_<TileDesc>(P->ws.tiles);
   a.n_tiles = (int32_t)P->tiles.size();
@@ -493,7 +497,7 @@ int odp_plan_bind(odp_plan* P, void* dev_ws, const float* dev_sqrt_f, const odp_
   ODP_HIP(up(P->ws.re_list, P->re_list.data(), sizeof(int32_t) * P->re_list.size()));
   ODP_HIP(up(P->ws.re_first, P->re_first.data(), sizeof(int32_t) * P->re_first.size()));
   ODP_HIP(up(P->ws.tf_first, P->tf_first.data(), sizeof(int32_t) * P->tf_first.size()));
-  ODP_HIP(up(P->ws.tf_list, P->tf_list.data(), sizeof(int32_t) * P->tf_list.size()));
+  ODP_HIP(up(P->ws.pull, P->pull.data(), sizeof(PullEntry) * P->pull.size()));
   if (!P->fmask.empty()) ODP_HIP(up(P->ws.fmask, P->fmask.data(), sizeof(float) * pp));
   ODP_HIP(launch_illum(illum_args(P, P->W_<float2>(P->ws.w), 1), s));
   double* misc = P->W_<double>(P->ws.misc);
@@ -604,8 +608,7 @@ static PixelArgs pixel_args(const odp_plan* P, char* b, double* stats) {
   a.p = P->p;
   a.psi = P->W_<float2>(P->ws.psi);
   a.tf_first = P->W_<int32_t>(P->ws.tf_first);
-  a.tf_list = P->W_<int32_t>(P->ws.tf_list);
-  a.offsets = P->W_<int32_t>(P->ws.offsets);
+  a.pull = P->W_<PullEntry>(P->ws.pull);
   a.w_sub = P->blind ? reinterpret_cast<const float2*>(b + P->st.w_sub) : nullptr;
   a.eta = (float)P->eta;
   a.r = (float)P->r;
@@ -686,11 +689,44 @@ int odp_merge(const odp_plan* P, const void* dev_state, odp_c32* u_out, hipStrea
 
 int odp_amp_loss(const odp_plan* P, const odp_c32* u, const odp_c32* w, double* loss_out, odp_c32* grad_u,
                  odp_c32* grad_w, hipStream_t s) {
-  (void)s;
   if (!P || !u || !w || !loss_out) return fail(ODP_EINVAL, "null argument");
-  (void)grad_u;
-  (void)grad_w;
-  return fail(ODP_EUNSUPPORTED, "amplitude loss is not built into this library yet");
+  if (!P->wsp) return fail(ODP_EINVAL, "plan is not bound");
+  const bool grad = grad_u || grad_w;
+  LossArgs la;
+  la.u = reinterpret_cast<const float2*>(u);
+  la.H = P->H;
+  la.W = P->W;
+  la.w = reinterpret_cast<const float2*>(w);
+  la.tw = P->W_<float2>(P->ws.tw);
+  la.sqrt_f = P->sqrt_f;
+  la.offsets = P->W_<int32_t>(P->ws.offsets);
+  la.J = P->J;
+  la.frame_loss = P->W_<double>(P->ws.fpart);
+  la.phi = P->W_<float2>(P->ws.psi);
+  ODP_HIP(launch_loss(P->p, la, grad, s));
+  ODP_HIP(launch_loss_total(la.frame_loss, P->J, loss_out, s));
+  if (!grad) return ODP_OK;
+  if (grad_u) ODP_HIP(launch_fill(reinterpret_cast<float2*>(grad_u), (int64_t)P->H * P->W, make_float2(0.f, 0.f), s));
+  LossGradArgs ga;
+  ga.u = la.u;
+  ga.W = P->W;
+  ga.w = la.w;
+  ga.phi = la.phi;
+  ga.offsets = la.offsets;
+  ga.J = P->J;
+  ga.p = P->p;
+  ga.cells = P->W_<CellDesc>(P->ws.cells);
+  ga.tiles = P->W_<TileDesc>(P->ws.tiles);
+  ga.n_tiles = (int32_t)P->tiles.size();
+  ga.tf_first = P->W_<int32_t>(P->ws.tf_first);
+  ga.pull = P->W_<PullEntry>(P->ws.pull);
+  ga.grad_u = reinterpret_cast<float2*>(grad_u);
+  ga.grad_w = reinterpret_cast<float2*>(grad_w);
+  ga.wpart = P->W_<double>(P->ws.wpart);
+  ga.frames_per_chunk = (P->J + LOSS_CHUNKS - 1) / LOSS_CHUNKS;
+  ga.n_chunks = (P->J + ga.frames_per_chunk - 1) / ga.frames_per_chunk;
+  ODP_HIP(launch_loss_grads(ga, s));
+  return ODP_OK;
 }
 
 }  // extern "C"

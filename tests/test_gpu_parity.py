@@ -216,8 +216,9 @@ def test_resume_matches_uninterrupted():
     plan.iterate(b, 2)
     c = b.clone()                      # checkpoint = a copy of the state buffer
     plan.iterate(c, 4)
-    # atomics make the accumulation order free: equal to FP32 rounding, not bit for bit
-    assert rel_list([host(t) for t in a.u_sub()], [host(t) for t in c.u_sub()]) <= 1e-6
+    # every reduction runs in a fixed order: resuming from a copy is bit for bit
+    torch.cuda.synchronize()
+    assert torch.equal(a.buf, c.buf)
 
 
 def test_held_pixels_stay_one():
