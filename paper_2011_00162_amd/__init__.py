@@ -5,7 +5,7 @@ include/odp.h); this package is its thin binding.  Importing it does not load
 the library; the first call does, and fails loudly if it was not built.
 """
 from ._lib import (ODP_DFT_SPLIT_BF16, ODP_FFT_F32, EXPORTS, OdpError, lib)  # noqa: F401
-from .api import Geometry, Plan, State, prox_stagm  # noqa: F401
+from .api import Geometry, Graph, Plan, State, prox_stagm  # noqa: F401
 from .autograd import AmplitudeLoss, amplitude_loss  # noqa: F401
 
 __version__ = "0.1.0"

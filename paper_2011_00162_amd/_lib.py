@@ -21,6 +21,8 @@ EXPORTS = [
     "odp_plan_illum_max", "odp_plan_set_params", "odp_forward", "odp_adjoint", "odp_prox_stagm",
     "odp_state_init", "odp_admm_iterate", "odp_frame_sweep", "odp_probe_update",
     "odp_pixel_update", "odp_merge", "odp_amp_loss", "odp_last_error", "odp_version",
+    "odp_batch_plan_create", "odp_batch_get_entry", "odp_batch_set_penalties", "odp_plan_get_tuning",
+    "odp_plan_set_tuning", "odp_plan_autotune", "odp_graph_create", "odp_graph_launch", "odp_graph_destroy",
 ]
 
 
@@ -51,6 +53,16 @@ class PlanInfo(C.Structure):
 
 class StateLayout(C.Structure):
     _fields_ = [(n, C.c_size_t) for n in ("u_sub", "gamma", "lam", "w", "w_sub", "delta", "bytes")]
+
+
+class BatchEntry(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("row0", "col0", "H", "W", "J0", "J", "D0", "D")] + [
+        ("r", C.c_double), ("illum_max", C.c_double)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("transform", "xcd_slice", "tiling", "tile_rows", "tile_cols")] + [
+        ("ms_per_iter", C.c_double), ("n_tried", C.c_int32)]
 
 
 _lib = None
@@ -85,6 +97,15 @@ def lib() -> C.CDLL:
         "odp_pixel_update": (C.c_int, [vp, vp, vp, vp]),
         "odp_merge": (C.c_int, [vp, vp, vp, vp]),
         "odp_amp_loss": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+        "odp_batch_plan_create": (C.c_int, [C.POINTER(Problem), i32, C.POINTER(vp)]),
+        "odp_batch_get_entry": (C.c_int, [vp, i32, C.POINTER(BatchEntry)]),
+        "odp_batch_set_penalties": (C.c_int, [vp, vp, vp]),
+        "odp_plan_get_tuning": (C.c_int, [vp, C.POINTER(Tuning)]),
+        "odp_plan_set_tuning": (C.c_int, [vp, i32, i32, i32, vp]),
+        "odp_plan_autotune": (C.c_int, [vp, vp, i32, vp, C.POINTER(Tuning)]),
+        "odp_graph_create": (C.c_int, [vp, vp, i32, i32, C.POINTER(vp)]),
+        "odp_graph_launch": (C.c_int, [vp, vp]),
+        "odp_graph_destroy": (None, [vp]),
         "odp_last_error": (C.c_char_p, []),
         "odp_version": (C.c_char_p, []),
     }

@@ -9,7 +9,7 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from ._lib import (ODP_FFT_F32, PlanInfo, Problem, StateLayout, check, lib)
+from ._lib import (ODP_FFT_F32, BatchEntry, PlanInfo, Problem, StateLayout, Tuning, check, lib)
 
 
 def _stream(stream=None) -> C.c_void_p:
@@ -107,28 +107,35 @@ class State:
         return State(self.plan, self.buf.clone())
 
 
+def _problem(H, W, p, offsets, frame_sub, D, eps, eta, r, mu, gamma, transform, blind, probe_fmask):
+    """(odp_problem, keep-alive arrays) for one problem."""
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32).reshape(-1, 2))
+    sub = np.ascontiguousarray(np.asarray(frame_sub, dtype=np.int32).reshape(-1))
+    mask = None if probe_fmask is None else np.ascontiguousarray(np.asarray(probe_fmask, dtype=np.uint8))
+    if D is None:
+        D = int(sub.max()) + 1 if len(sub) else 0
+    prob = Problem(H=H, W=W, p=p, J=len(off), offsets=off.ctypes.data_as(C.POINTER(C.c_int32)), D=D,
+                   frame_sub=sub.ctypes.data_as(C.POINTER(C.c_int32)), eps=eps, eta=eta, r=r, mu=mu,
+                   gamma=gamma, transform=transform, blind=1 if blind else 0,
+                   probe_fmask=mask.ctypes.data_as(C.POINTER(C.c_uint8)) if mask is not None else None)
+    return prob, (off, sub, mask)
+
+
 class Plan:
     """A validated problem (odp_plan) plus its device workspace once bound."""
 
     def __init__(self, H: int, W: int, p: int, offsets, frame_sub, D: int | None = None,
                  eps: float = 0.5, eta: float = 0.1, r: float = 0.0, mu: float = 0.0,
                  gamma: float = 0.0, transform: int = ODP_FFT_F32, blind: bool = False,
-                 probe_fmask=None):
+                 probe_fmask=None, _handle=None):
         L = lib()
-        self._off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32).reshape(-1, 2))
-        self._sub = np.ascontiguousarray(np.asarray(frame_sub, dtype=np.int32).reshape(-1))
-        self._mask = None if probe_fmask is None else np.ascontiguousarray(np.asarray(probe_fmask, dtype=np.uint8))
-        if D is None:
-            D = int(self._sub.max()) + 1 if len(self._sub) else 0
-        prob = Problem(H=H, W=W, p=p, J=len(self._off),
-                       offsets=self._off.ctypes.data_as(C.POINTER(C.c_int32)), D=D,
-                       frame_sub=self._sub.ctypes.data_as(C.POINTER(C.c_int32)),
-                       eps=eps, eta=eta, r=r, mu=mu, gamma=gamma, transform=transform,
-                       blind=1 if blind else 0,
-                       probe_fmask=(self._mask.ctypes.data_as(C.POINTER(C.c_uint8))
-                                    if self._mask is not None else None))
-        h = C.c_void_p()
-        check(L.odp_plan_create(C.byref(prob), C.byref(h)))
+        if _handle is None:
+            prob, self._arrays = _problem(H, W, p, offsets, frame_sub, D, eps, eta, r, mu, gamma, transform,
+                                          blind, probe_fmask)
+            h = C.c_void_p()
+            check(L.odp_plan_create(C.byref(prob), C.byref(h)))
+        else:
+            h = _handle
         self._h = h
         self.info = PlanInfo()
         check(L.odp_plan_get_info(self._h, C.byref(self.info)))
@@ -139,6 +146,56 @@ class Plan:
         self._geom = None
         self.workspace = None
         self._keep = ()
+
+    @classmethod
+    def batch(cls, problems: list[dict]) -> "Plan":
+        """One plan over independent problems (dicts with the Plan() keyword arguments)."""
+        arr = (Problem * len(problems))()
+        keep = []
+        for i, pb in enumerate(problems):
+            kw = dict(D=None, eps=0.5, eta=0.1, r=0.0, mu=0.0, gamma=0.0, transform=ODP_FFT_F32, blind=False,
+                      probe_fmask=None)
+            kw.update(pb)
+            prob, k = _problem(kw.pop("H"), kw.pop("W"), kw.pop("p"), kw.pop("offsets"), kw.pop("frame_sub"),
+                               **kw)
+            arr[i] = prob
+            keep.append(k)
+        h = C.c_void_p()
+        check(lib().odp_batch_plan_create(arr, len(problems), C.byref(h)))
+        p0 = problems[0]
+        plan = cls(0, 0, p0["p"], None, None, eps=p0.get("eps", 0.5), eta=p0.get("eta", 0.1),
+                   transform=p0.get("transform", ODP_FFT_F32), _handle=h)
+        plan._arrays = keep
+        return plan
+
+    def n_problems(self) -> int:
+        n = 0
+        e = BatchEntry()
+        while lib().odp_batch_get_entry(self._h, n, C.byref(e)) == 0:
+            n += 1
+        return n
+
+    def entry(self, i: int) -> BatchEntry:
+        e = BatchEntry()
+        check(lib().odp_batch_get_entry(self._h, int(i), C.byref(e)))
+        return e
+
+    def set_penalties(self, r, stream=None) -> None:
+        rr = np.ascontiguousarray(np.asarray(r, dtype=np.float64))
+        check(lib().odp_batch_set_penalties(self._h, rr.ctypes.data, _stream(stream)))
+
+    def tuning(self) -> Tuning:
+        t = Tuning()
+        check(lib().odp_plan_get_tuning(self._h, C.byref(t)))
+        return t
+
+    def set_tuning(self, transform: int, xcd_slice: int, tiling: int, stream=None) -> None:
+        check(lib().odp_plan_set_tuning(self._h, int(transform), int(xcd_slice), int(tiling), _stream(stream)))
+
+    def autotune(self, scratch: "State", iters: int = 5, stream=None) -> Tuning:
+        t = Tuning()
+        check(lib().odp_plan_autotune(self._h, _ptr(scratch.buf), int(iters), _stream(stream), C.byref(t)))
+        return t
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -165,10 +222,14 @@ class Plan:
 
     # ---- device side ----
     def bind(self, sqrt_f: torch.Tensor, w: torch.Tensor, stream=None) -> "Plan":
+        """w: [p, p] probe, or [n, p, p] probes of a batch plan (one per problem)."""
         i = self.info
         if sqrt_f.dtype != torch.float32 or tuple(sqrt_f.shape) != (i.J, i.p, i.p):
             raise ValueError("sqrt_f must be float32 [J, p, p]")
-        _c64(w, (i.p, i.p))
+        if w.dim() == 3:
+            _c64(w, (self.n_problems(), i.p, i.p))
+        else:
+            _c64(w, (i.p, i.p))
         self.workspace = torch.empty(i.workspace_bytes, dtype=torch.uint8, device=sqrt_f.device)
         check(lib().odp_plan_bind(self._h, _ptr(self.workspace), _ptr(sqrt_f), _ptr(w), _stream(stream)))
         self._keep = (sqrt_f, w)
@@ -240,3 +301,25 @@ class Plan:
         gw = torch.empty_like(w) if grad_w else None
         check(lib().odp_amp_loss(self._h, _ptr(u), _ptr(w), _ptr(loss), _ptr(gu), _ptr(gw), _stream(stream)))
         return loss, gu, gw
+
+
+class Graph:
+    """n_iter iterations of several (plan, state) pairs captured into one HIP graph."""
+
+    def __init__(self, plans: list, states: list, n_iter: int):
+        n = len(plans)
+        ph = (C.c_void_p * n)(*[pl._h.value for pl in plans])
+        sh = (C.c_void_p * n)(*[st.buf.data_ptr() for st in states])
+        g = C.c_void_p()
+        check(lib().odp_graph_create(ph, sh, n, int(n_iter), C.byref(g)))
+        self._g = g
+        self._keep = (plans, states)
+
+    def launch(self, stream=None) -> None:
+        check(lib().odp_graph_launch(self._g, _stream(stream)))
+
+    def __del__(self):
+        g = getattr(self, "_g", None)
+        if g is not None and g.value:
+            lib().odp_graph_destroy(g)
+            self._g = None

@@ -2,12 +2,13 @@
 //
 // Frame kernels run one workgroup per scan frame (p*p/16 threads, 16 complex
 // values per thread, frame transform through LDS, see fft_frame.hpp).  Pixel
-// kernels run one 256-thread workgroup per 8 x 32 tile of a cell (a rectangle
+// kernels run one 256-thread workgroup per 256-pixel tile of a cell (a rectangle
 // covered by one fixed set of subdomains), so every descriptor load is uniform.
 #include <hip/hip_runtime.h>
 
 #include "fft_frame.hpp"
 #include "odp_internal.hpp"
+#include "prox.hpp"
 #include "reduce.hpp"
 
 namespace odp {
@@ -21,47 +22,13 @@ __device__ __forceinline__ void atomic_add_c(float2* p, float2 v) {
   unsafeAtomicAdd(&p->y, v.y);
 }
 
-// Closed-form proximal map of the ST-AGM (eq. Prox_sol), with precomputed
-// coefficients: thr = eps - (1-eps)/lam (truncated branch when |y| < thr*sqrt f),
-// ctr = lam/(lam - (1-eps)/eps) (only used when thr > 0), ca = 1/(1+lam),
-// cb = lam/(1+lam).  sign(0) = +1.
-struct ProxC {
-  float thr, ctr, ca, cb;
-};
-
-__host__ __device__ inline ProxC prox_coeffs(double eps, double lam) {
-  const double kappa = (1.0 - eps) / eps;
-  ProxC c;
-  c.thr = (float)(eps - (1.0 - eps) / lam);
-  c.ctr = lam > kappa ? (float)(lam / (lam - kappa)) : 0.0f;
-  c.ca = (float)(1.0 / (1.0 + lam));
-  c.cb = (float)(lam / (1.0 + lam));
-  return c;
-}
-
-// Branch-free: selects only, so a wavefront never splits on the data.
-__device__ __forceinline__ float2 prox_stagm(float2 y, float sf, const ProxC& c) {
-  const float a2 = y.x * y.x + y.y * y.y;
-  const bool nz = a2 > 0.0f;
-  const float inv = nz ? __builtin_amdgcn_rsqf(a2) : 0.0f;   // 1/|y|, about 1 ulp
-  const float ay = a2 * inv;                                  // |y| (0 for y = 0)
-  const float rho = (ay < c.thr * sf) ? fmaxf(0.0f, ay * c.ctr) : fmaf(sf, c.ca, ay * c.cb);
-  const float s = rho * inv;
-  // y = 0: every phase is a minimiser; sign(0) = +1
-  return nz ? make_float2(y.x * s, y.y * s) : make_float2(rho, 0.0f);
-}
-
-// g_eps(x; b) of eq. obj-1 from |x| and sqrt(b), in FP64
-__device__ __forceinline__ double g_eps(double ax, double sb, double eps) {
-  return (ax < eps * sb) ? 0.5 * (1.0 - eps) * (sb * sb - ax * ax / eps) : 0.5 * (ax - sb) * (ax - sb);
-}
-
-__device__ __forceinline__ int sweep_frame(int32_t chunk, int32_t J, const int32_t* order) {
+__device__ __forceinline__ int sweep_frame(int32_t chunk, int32_t J, const int32_t* order, int xcd_slice) {
   // XCD-aware slicing: workgroup b runs on XCD b % 8; each XCD takes a
   // contiguous slice of the subdomain-grouped frame order, so neighbouring
-  // windows (which share image pixels and accumulators) share one L2.
+  // windows (which share image patches) share one L2.  The autotuner may pick
+  // the plain order instead.
   const int b = blockIdx.x;
-  const int pos = (b % NXCD) * chunk + b / NXCD;
+  const int pos = xcd_slice ? (b % NXCD) * chunk + b / NXCD : b;
   return pos < J ? order[pos] : -1;
 }
 
@@ -78,11 +45,11 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
   using F = Frame<P>;
   __shared__ float2 lds[F::LDS];
   __shared__ double red[F::T / 64];
-  const int j = sweep_frame(a.chunk, a.J, a.order);
+  const int j = sweep_frame(a.chunk, a.J, a.order, a.xcd_slice);
   if (j < 0) return;  // uniform over the workgroup
   const int t = threadIdx.x;
   const FrameDesc fd = a.frames[j];
-  const size_t woff = a.w_per_sub ? (size_t)fd.sub * P * P : 0;
+  const size_t woff = (size_t)(a.w_per_sub ? fd.sub : fd.probe) * P * P;
   const float2* w = a.w + woff;
   const int col = F::a_col(t), r2 = F::a_r2(t);
   const float inv_p = 1.0f / (float)P;
@@ -155,7 +122,7 @@ hipError_t launch_sweep(int p, const SweepArgs& a, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // K3: pixel update (Alg. 2 Steps 1 (v), 3 (u) and 4 (Lam); Alg. 3 Step 4 (U)
-// and the Lam half of Step 5) on one 8 x 32 tile of a cell.
+// and the Lam half of Step 5) on one 256-pixel tile of a cell.
 //   num_d   = sum_{j in d, window covers x} psi_j(x - o_j)    (A_d*(z - Gamma), fixed order)
 //   v_{a,b} = (u_a + u_b + Lam_{a,b} + Lam_{b,a}) / 2        from the iterate n
 //   u_d     = (eta num_d + r sum_{e != d} (v_{d,e} - Lam_{d,e}) + gamma u_d) / (eta den_d + r k + gamma)
@@ -220,7 +187,8 @@ __global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
   const TileDesc td = a.tiles[tile];
   const CellDesc* cd = a.cells + td.cell;
   const int m = cd->m, p = a.p;
-  const int tr = threadIdx.x / TILE_COLS, tc = threadIdx.x % TILE_COLS;
+  const float r = cd->r;
+  const int tr = threadIdx.x / a.tile_cols, tc = threadIdx.x % a.tile_cols;
   const bool act = tr < td.nr && tc < td.nc;
   const int y = td.r0 + tr, x = td.c0 + tc;
   const int yi = cd->r0 + y, xi = cd->c0 + x;  // image coordinates
@@ -243,7 +211,7 @@ __global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
         uo[s] = a.u[idx[s]];
         acc[s] = c_add(c_scale(num, a.eta), c_scale(uo[s], a.gamma));
         if (BLIND) {
-          const double q = (double)a.eta * den + (double)a.r * (double)(m - 1) + (double)a.gamma;
+          const double q = (double)a.eta * den + (double)r * (double)(m - 1) + (double)a.gamma;
           rc[s] = q == 0.0 ? 0.0f : (float)(1.0 / q);
         } else {
           rc[s] = a.rcp[idx[s]];
@@ -261,8 +229,8 @@ __global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
           const int64_t li = cd->lbase[q] + (int64_t)y * cd->lpitch[q] + x;
           const float2 lab = a.lam[li], lba = a.lam[li + cd->lstride[q]];
           const float2 v = c_scale(c_add(c_add(uo[s], uo[t]), c_add(lab, lba)), 0.5f);
-          acc[s] = c_add(acc[s], c_scale(c_sub(v, lab), a.r));
-          acc[t] = c_add(acc[t], c_scale(c_sub(v, lba), a.r));
+          acc[s] = c_add(acc[s], c_scale(c_sub(v, lab), r));
+          acc[t] = c_add(acc[t], c_scale(c_sub(v, lba), r));
         }
       }
     }
@@ -331,11 +299,12 @@ __global__ __launch_bounds__(256) void k_illum(IllumArgs a) {
   const int tile = blockIdx.x;
   const TileDesc td = a.tiles[tile];
   const CellDesc* cd = a.cells + td.cell;
-  const int tr = threadIdx.x / TILE_COLS, tc = threadIdx.x % TILE_COLS;
+  const int tr = threadIdx.x / a.tile_cols, tc = threadIdx.x % a.tile_cols;
   if (!(tr < td.nr && tc < td.nc)) return;
   const int y = td.r0 + tr, x = td.c0 + tc;
   const int yi = cd->r0 + y, xi = cd->c0 + x;
   const int m = cd->m, p = a.p;
+  const float2* w = a.w + (size_t)cd->probe * p * p;
   for (int s = 0; s < m; ++s) {
     const int64_t idx = cd->ubase[s] + (int64_t)y * cd->upitch[s] + x;
     double den;
@@ -345,7 +314,7 @@ __global__ __launch_bounds__(256) void k_illum(IllumArgs a) {
         const PullEntry pe = a.pull[k];
         const int dy = yi - pe.r, dx = xi - pe.c;
         if ((unsigned)dy < (unsigned)p && (unsigned)dx < (unsigned)p) {
-          const float2 ww = a.w[dy * p + dx];
+          const float2 ww = w[dy * p + dx];
           den += (double)ww.x * ww.x + (double)ww.y * ww.y;
         }
       }
@@ -353,7 +322,7 @@ __global__ __launch_bounds__(256) void k_illum(IllumArgs a) {
     } else {
       den = a.den[idx];
     }
-    const double q = a.eta * den + a.r * (double)(m - 1) + a.gamma;
+    const double q = a.eta * den + (double)cd->r * (double)(m - 1) + a.gamma;
     a.rcp[idx] = q == 0.0 ? 0.0f : (float)(1.0 / q);
   }
 }

@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void k_grad_u(LossGradArgs a) {
   const int tile = blockIdx.x;
   const TileDesc td = a.tiles[tile];
   const CellDesc* cd = a.cells + td.cell;
-  const int tr = threadIdx.x / TILE_COLS, tc = threadIdx.x % TILE_COLS;
+  const int tr = threadIdx.x / a.tile_cols, tc = threadIdx.x % a.tile_cols;
   const bool act = tr < td.nr && tc < td.nc;
   const int yi = cd->r0 + td.r0 + tr, xi = cd->c0 + td.c0 + tc;
   const int p = a.p;

@@ -9,8 +9,7 @@ namespace odp {
 
 constexpr int MAXS = 8;                        // most subdomains over one pixel
 constexpr int MAXP = MAXS * (MAXS - 1) / 2;    // most pairs over one pixel
-constexpr int TILE_ROWS = 8;                   // pixel-update tile: 8 x 32 pixels, 256 threads
-constexpr int TILE_COLS = 32;
+constexpr int TILE_PIX = 256;                  // pixels (= threads) of a pixel-update tile
 constexpr int NXCD = 8;                        // MI355X accelerator complex dies
 
 // A cell is a rectangle of image pixels covered by the same set of subdomains
@@ -19,6 +18,8 @@ struct CellDesc {
   int32_t m;                 // number of subdomains covering the cell
   int32_t npair;             // m (m - 1) / 2
   int32_t r0, c0;            // top-left pixel in the image
+  float r;                   // overlap penalty of the problem the cell belongs to
+  int32_t probe;             // probe index of that problem
   int32_t sub[MAXS];         // subdomain ids, ascending
   int32_t upitch[MAXS];      // row pitch of each subdomain array
   int64_t ubase[MAXS];       // u_sub index of the cell's top-left in each subdomain
@@ -47,6 +48,8 @@ struct FrameDesc {
   int64_t base;              // u_sub index of the window's top-left inside its subdomain
   int32_t pitch;             // row pitch of that subdomain
   int32_t sub;               // subdomain id
+  int32_t probe;             // probe index (one probe per problem of a batch)
+  int32_t pad;
 };
 
 // ---------------------------------------------------------------- launch args
@@ -61,6 +64,7 @@ struct SweepArgs {
   const FrameDesc* frames;
   const int32_t* order;      // frame processing order (grouped by subdomain)
   int32_t J, chunk;          // frames, frames per XCD slice
+  int32_t xcd_slice;         // 1: workgroup b takes slice b % 8 of the order; 0: order[b]
   float eps, eta;
   double* part;              // [J][2] stats partials (L1 misfit, G_eps) or null
   float2* psi;               // [J][p][p] per-frame output, natural spatial layout:
@@ -74,29 +78,36 @@ struct PixelArgs {
   float2* lam;
   const CellDesc* cells;
   const TileDesc* tiles;
-  int32_t n_tiles, p;
+  int32_t n_tiles, p, tile_cols;
   const float2* psi;         // per-frame outputs of the sweep
   const int32_t* tf_first;   // [n_tiles*MAXS + 1]: frames of slot s overlapping tile t
   const PullEntry* pull;     // their records, ascending frame id
   const float2* w_sub;       // blind: probe copies (the illumination is formed in the pull)
-  float eta, r, gamma;
+  float eta, gamma;          // (r is per cell)
   double* part;              // [n_tiles][MAXS][2] (|du|^2, |u|^2) or null
 };
 
 struct IllumArgs {           // den and rcp on every subdomain pixel
-  const float2* w;           // probe
+  const float2* w;           // probes [n_probes][p][p] (indexed by the cell's probe)
   const int32_t* tf_first;   // per-tile frame lists (as in PixelArgs)
   const PullEntry* pull;
   const CellDesc* cells;
   const TileDesc* tiles;
-  int32_t n_tiles, p;
+  int32_t n_tiles, p, tile_cols;
   double* den;               // [p_sub]
   float* rcp;                // [p_sub]
-  double eta, r, gamma;
+  double eta, gamma;         // (r is per cell)
   int recompute_den;         // 0: reuse den, only rebuild rcp
 };
 
 hipError_t launch_sweep(int p, const SweepArgs& a, hipStream_t s);
+
+// Split-BF16 DFT matrix for the MFMA sweep: planes [re hi, re lo, im hi, im lo] of
+// F[k][n] = exp(-2 pi i k n / p) / sqrt(p), each [p][p] bf16 bit patterns.
+struct DftTable {
+  const uint16_t* f;
+};
+hipError_t launch_sweep_dft(int p, const SweepArgs& a, const DftTable& dt, hipStream_t s);
 hipError_t launch_pixel(const PixelArgs& a, bool stats, bool blind, hipStream_t s);
 hipError_t launch_illum(const IllumArgs& a, hipStream_t s);
 hipError_t launch_forward(int p, const float2* u, int H, int W, const float2* w, const float2* tw,
@@ -153,7 +164,7 @@ struct LossGradArgs {
   int32_t J, p;
   const CellDesc* cells;
   const TileDesc* tiles;
-  int32_t n_tiles;
+  int32_t n_tiles, tile_cols;
   const int32_t* tf_first;
   const PullEntry* pull;
   float2* grad_u;            // [H][W] or null

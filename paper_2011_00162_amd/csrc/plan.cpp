@@ -38,6 +38,21 @@ int fail(int code, const std::string& msg) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// float -> bf16 bit pattern, round to nearest even (finite inputs)
+uint16_t bf16_rne(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+double bf16_value(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return (double)f;
+}
+
 constexpr int LOSS_CHUNKS = 32;   // frame chunks of the probe-gradient reduction
 
 struct Pair {
@@ -60,19 +75,35 @@ struct odp_plan {
   std::vector<Pair> pairs;
   int64_t n_lam = 0;
   std::vector<CellDesc> cells;
-  std::vector<TileDesc> tiles;
   int32_t max_cover = 0;
   std::vector<FrameDesc> frames;
   std::vector<int32_t> order, sub_first;
-  std::vector<int32_t> re_list, re_first;
-  std::vector<int32_t> tf_first;            // per (tile, slot): range of pull records
-  std::vector<PullEntry> pull;              // frames whose window meets the tile, ascending id
+  // pixel-update tilings (the autotuner picks one); the active one is tsets[ts]
+  struct TileSet {
+    int rows = 0, cols = 0;
+    std::vector<TileDesc> tiles;
+    std::vector<int32_t> re_list, re_first;  // (tile, slot) entries per subdomain, for RE
+    std::vector<int32_t> tf_first;           // per (tile, slot): range of pull records
+    std::vector<PullEntry> pull;             // frames whose window meets the tile, ascending id
+  };
+  TileSet tsets[3];
+  int ts = 0;
+  int32_t xcd_slice = 1;
+  // problems of a batch (one entry for a single problem)
+  struct Entry {
+    int32_t row0, col0, H, W, J0, J, D0, D;
+    double r, illum_max;
+  };
+  std::vector<Entry> batch;
+  std::vector<int32_t> sub_problem;        // [D] problem of each subdomain
+  std::vector<int> cuts_r, cuts_c;         // cell cuts
   std::vector<float2> tw;
+  std::vector<uint16_t> dft;               // split-BF16 DFT matrix planes (transform = DFT)
   int32_t chunk = 0;
   // workspace layout (byte offsets)
   struct {
     size_t tw, w, frames, order, sub_first, offsets, rects, usub_off, cells, tiles, re_list, re_first, tf_first,
-        pull, den, rcp, fpart, tpart, stat_scratch, misc, psi, fmask, wpart, bytes;
+        pull, den, rcp, fpart, tpart, stat_scratch, misc, pmax, psi, fmask, wpart, dft, bytes;
   } ws{};
   struct {
     size_t u_sub, gamma, lam, w, w_sub, delta, bytes;
@@ -84,9 +115,67 @@ struct odp_plan {
 
   template <class T>
   T* W_(size_t off) const { return reinterpret_cast<T*>(wsp + off); }
+  const TileSet& tset() const { return tsets[ts]; }
+  int n_probes() const { return (int)batch.size(); }
 };
 
 namespace {
+
+// Cut every cell into rows x cols tiles (rows * cols = 256) and list, per (tile,
+// subdomain slot), the slot's frames whose window meets the tile (ascending id).
+void build_tiles(const odp_plan* P, int rows, int cols, odp_plan::TileSet& T) {
+  const int p = P->p, D = P->D;
+  T.rows = rows;
+  T.cols = cols;
+  T.tiles.clear();
+  for (size_t c = 0; c < P->cells.size(); ++c) {
+    const CellDesc& cd = P->cells[c];
+    const int r1 = *std::upper_bound(P->cuts_r.begin(), P->cuts_r.end(), cd.r0);
+    const int c1 = *std::upper_bound(P->cuts_c.begin(), P->cuts_c.end(), cd.c0);
+    for (int ty = 0; ty < r1 - cd.r0; ty += rows)
+      for (int tx = 0; tx < c1 - cd.c0; tx += cols) {
+        TileDesc td;
+        std::memset(&td, 0, sizeof(td));
+        td.cell = (int32_t)c;
+        td.r0 = ty;
+        td.c0 = tx;
+        td.nr = std::min(rows, r1 - cd.r0 - ty);
+        td.nc = std::min(cols, c1 - cd.c0 - tx);
+        T.tiles.push_back(td);
+      }
+  }
+  std::vector<std::vector<int32_t>> per(D);
+  for (size_t t = 0; t < T.tiles.size(); ++t) {
+    const CellDesc& cd = P->cells[T.tiles[t].cell];
+    for (int s = 0; s < cd.m; ++s) per[cd.sub[s]].push_back((int32_t)(t * MAXS + s));
+  }
+  T.re_first.assign(D + 1, 0);
+  T.re_list.clear();
+  for (int d = 0; d < D; ++d) {
+    T.re_first[d] = (int32_t)T.re_list.size();
+    T.re_list.insert(T.re_list.end(), per[d].begin(), per[d].end());
+  }
+  T.re_first[D] = (int32_t)T.re_list.size();
+  std::vector<std::vector<int32_t>> by_sub(D);
+  for (int j = 0; j < P->J; ++j) by_sub[P->frame_sub[j]].push_back(j);
+  T.tf_first.assign(T.tiles.size() * MAXS + 1, 0);
+  T.pull.clear();
+  for (size_t t = 0; t < T.tiles.size(); ++t) {
+    const TileDesc& td = T.tiles[t];
+    const CellDesc& cd = P->cells[td.cell];
+    const int y0 = cd.r0 + td.r0, y1 = y0 + td.nr, x0 = cd.c0 + td.c0, x1 = x0 + td.nc;
+    for (int s = 0; s < MAXS; ++s) {
+      T.tf_first[t * MAXS + s] = (int32_t)T.pull.size();
+      if (s >= cd.m) continue;
+      for (int j : by_sub[cd.sub[s]]) {
+        const int r = P->offsets[2 * j], c = P->offsets[2 * j + 1];
+        if (r < y1 && r + p > y0 && c < x1 && c + p > x0)
+          T.pull.push_back(PullEntry{(int64_t)j * p * p - (int64_t)r * p - c, r, c});
+      }
+    }
+  }
+  T.tf_first[T.tiles.size() * MAXS] = (int32_t)T.pull.size();
+}
 
 int build_geometry(odp_plan* P) {
   const int J = P->J, D = P->D, p = P->p, H = P->H, W = P->W;
@@ -144,13 +233,14 @@ int build_geometry(odp_plan* P) {
   rc.erase(std::unique(rc.begin(), rc.end()), rc.end());
   std::sort(cc.begin(), cc.end());
   cc.erase(std::unique(cc.begin(), cc.end()), cc.end());
+  P->cuts_r = rc;
+  P->cuts_c = cc;
   // pair lookup
   std::vector<int> pair_of((size_t)D * D, -1);
   for (size_t q = 0; q < P->pairs.size(); ++q) {
     pair_of[(size_t)P->pairs[q].a * D + P->pairs[q].b] = (int)q;
   }
   P->cells.clear();
-  P->tiles.clear();
   P->max_cover = 0;
   for (size_t yi = 0; yi + 1 < rc.size(); ++yi)
     for (size_t xi = 0; xi + 1 < cc.size(); ++xi) {
@@ -190,33 +280,10 @@ int build_geometry(odp_plan* P) {
           cd.pa[q] = (int8_t)s;
           cd.pb[q] = (int8_t)t;
         }
-      const int cell = (int)P->cells.size();
+      cd.r = (float)P->batch[P->sub_problem[S[0]]].r;
+      cd.probe = P->sub_problem[S[0]];
       P->cells.push_back(cd);
-      for (int ty = 0; ty < r1 - r0; ty += TILE_ROWS)
-        for (int tx = 0; tx < c1 - c0; tx += TILE_COLS) {
-          TileDesc td;
-          std::memset(&td, 0, sizeof(td));
-          td.cell = cell;
-          td.r0 = ty;
-          td.c0 = tx;
-          td.nr = std::min(TILE_ROWS, r1 - r0 - ty);
-          td.nc = std::min(TILE_COLS, c1 - c0 - tx);
-          P->tiles.push_back(td);
-        }
     }
-  // RE reduction lists: (tile, slot) entries per subdomain, tile order
-  std::vector<std::vector<int32_t>> per(D);
-  for (size_t t = 0; t < P->tiles.size(); ++t) {
-    const CellDesc& cd = P->cells[P->tiles[t].cell];
-    for (int s = 0; s < cd.m; ++s) per[cd.sub[s]].push_back((int32_t)(t * MAXS + s));
-  }
-  P->re_first.assign(D + 1, 0);
-  P->re_list.clear();
-  for (int d = 0; d < D; ++d) {
-    P->re_first[d] = (int32_t)P->re_list.size();
-    P->re_list.insert(P->re_list.end(), per[d].begin(), per[d].end());
-  }
-  P->re_first[D] = (int32_t)P->re_list.size();
   // frames: base index inside the owning subdomain; processing order grouped by subdomain
   P->frames.resize(J);
   for (int j = 0; j < J; ++j) {
@@ -226,6 +293,8 @@ int build_geometry(odp_plan* P) {
     fd.pitch = R[3] - R[1];
     fd.base = P->usub_off[d] + (int64_t)(P->offsets[2 * j] - R[0]) * fd.pitch + (P->offsets[2 * j + 1] - R[1]);
     fd.sub = d;
+    fd.probe = P->sub_problem[d];
+    fd.pad = 0;
     P->frames[j] = fd;
   }
   P->order.resize(J);
@@ -236,29 +305,9 @@ int build_geometry(odp_plan* P) {
   for (int j = 0; j < J; ++j) P->sub_first[P->frame_sub[j] + 1]++;
   for (int d = 0; d < D; ++d) P->sub_first[d + 1] += P->sub_first[d];
   P->chunk = (J + NXCD - 1) / NXCD;
-  // per (tile, slot) lists of the slot's frames whose window meets the tile,
-  // ascending frame id (the pull order of the pixel update)
-  {
-    std::vector<std::vector<int32_t>> by_sub(D);
-    for (int j = 0; j < J; ++j) by_sub[P->frame_sub[j]].push_back(j);
-    P->tf_first.assign(P->tiles.size() * MAXS + 1, 0);
-    P->pull.clear();
-    for (size_t t = 0; t < P->tiles.size(); ++t) {
-      const TileDesc& td = P->tiles[t];
-      const CellDesc& cd = P->cells[td.cell];
-      const int y0 = cd.r0 + td.r0, y1 = y0 + td.nr, x0 = cd.c0 + td.c0, x1 = x0 + td.nc;
-      for (int s = 0; s < MAXS; ++s) {
-        P->tf_first[t * MAXS + s] = (int32_t)P->pull.size();
-        if (s >= cd.m) continue;
-        for (int j : by_sub[cd.sub[s]]) {
-          const int r = P->offsets[2 * j], c = P->offsets[2 * j + 1];
-          if (r < y1 && r + p > y0 && c < x1 && c + p > x0)
-            P->pull.push_back(PullEntry{(int64_t)j * p * p - (int64_t)r * p - c, r, c});
-        }
-      }
-    }
-    P->tf_first[P->tiles.size() * MAXS] = (int32_t)P->pull.size();
-  }
+  static const int shapes[3][2] = {{8, 32}, {4, 64}, {16, 16}};
+  for (int k = 0; k < 3; ++k) build_tiles(P, shapes[k][0], shapes[k][1], P->tsets[k]);
+  P->ts = 0;
   // twiddle table tw[i][k] = W_p^{i k} = exp(-2 pi i i k / p), i < p/16, k < 16, FP64 on the host
   const int n2 = p / 16;
   P->tw.resize((size_t)n2 * 16);
@@ -267,6 +316,24 @@ int build_geometry(odp_plan* P) {
       const double a = 2.0 * M_PI * (double)(i * k) / (double)p;
       P->tw[i * 16 + k] = make_float2((float)std::cos(a), (float)-std::sin(a));
     }
+  // split-BF16 DFT matrix F[k][n] = exp(-2 pi i k n / p) / sqrt(p), FP64 on the host:
+  // hi = bf16(F), lo = bf16(F - hi)
+  if (p == 64) {  // the autotuner may switch a p = 64 plan between the two transforms
+    const size_t pp = (size_t)p * p;
+    P->dft.assign(4 * pp, 0);
+    const double s = 1.0 / std::sqrt((double)p);
+    for (int k = 0; k < p; ++k)
+      for (int n = 0; n < p; ++n) {
+        const double a = 2.0 * M_PI * (double)((k * n) % p) / (double)p;
+        const double re = s * std::cos(a), im = -s * std::sin(a);
+        const size_t o = (size_t)k * p + n;
+        const uint16_t rh = bf16_rne((float)re), ih = bf16_rne((float)im);
+        P->dft[o] = rh;
+        P->dft[pp + o] = bf16_rne((float)(re - bf16_value(rh)));
+        P->dft[2 * pp + o] = ih;
+        P->dft[3 * pp + o] = bf16_rne((float)(im - bf16_value(ih)));
+      }
+  }
   return ODP_OK;
 }
 
@@ -279,7 +346,7 @@ void layout(odp_plan* P) {
   };
   const size_t pp = (size_t)P->p * P->p;
   P->ws.tw = take(sizeof(float2) * P->tw.size());
-  P->ws.w = take(sizeof(float2) * pp);
+  P->ws.w = take(sizeof(float2) * pp * P->n_probes());
   P->ws.frames = take(sizeof(FrameDesc) * P->J);
   P->ws.order = take(sizeof(int32_t) * P->J);
   P->ws.sub_first = take(sizeof(int32_t) * (P->D + 1));
@@ -287,20 +354,29 @@ void layout(odp_plan* P) {
   P->ws.rects = take(sizeof(int32_t) * 4 * P->D);
   P->ws.usub_off = take(sizeof(int64_t) * P->D);
   P->ws.cells = take(sizeof(CellDesc) * P->cells.size());
-  P->ws.tiles = take(sizeof(TileDesc) * P->tiles.size());
-  P->ws.re_list = take(sizeof(int32_t) * std::max<size_t>(1, P->re_list.size()));
+  size_t n_tiles = 1, n_re = 1, n_tf = 1, n_pull = 1;
+  for (const auto& T : P->tsets) {
+    n_tiles = std::max(n_tiles, T.tiles.size());
+    n_re = std::max(n_re, T.re_list.size());
+    n_tf = std::max(n_tf, T.tf_first.size());
+    n_pull = std::max(n_pull, T.pull.size());
+  }
+  P->ws.tiles = take(sizeof(TileDesc) * n_tiles);
+  P->ws.re_list = take(sizeof(int32_t) * n_re);
   P->ws.re_first = take(sizeof(int32_t) * (P->D + 1));
-  P->ws.tf_first = take(sizeof(int32_t) * P->tf_first.size());
-  P->ws.pull = take(sizeof(PullEntry) * std::max<size_t>(1, P->pull.size()));
+  P->ws.tf_first = take(sizeof(int32_t) * n_tf);
+  P->ws.pull = take(sizeof(PullEntry) * n_pull);
   P->ws.den = take(sizeof(double) * P->p_sub);
   P->ws.rcp = take(sizeof(float) * P->p_sub);
   P->ws.fpart = take(sizeof(double) * 2 * P->J);
-  P->ws.tpart = take(sizeof(double) * 2 * MAXS * std::max<size_t>(1, P->tiles.size()));
+  P->ws.tpart = take(sizeof(double) * 2 * MAXS * n_tiles);
   P->ws.stat_scratch = take(sizeof(double) * 2 * (P->D + 1));
   P->ws.misc = take(sizeof(double) * (2 + 2 * 1024 + 8));
+  P->ws.pmax = take(sizeof(double) * (2 + 2 * 1024) * P->n_probes());
   P->ws.psi = take(sizeof(float2) * pp * P->J);
   P->ws.fmask = take(sizeof(float) * pp);
   P->ws.wpart = take(sizeof(double) * 2 * pp * LOSS_CHUNKS);
+  P->ws.dft = take(sizeof(uint16_t) * P->dft.size() + 16);
   P->ws.bytes = o;
   size_t s = 0;
   auto stake = [&](size_t bytes) {
@@ -334,15 +410,43 @@ IllumArgs illum_args(const odp_plan* P, const float2* w, int recompute) {
   a.pull = P->W_<PullEntry>(P->ws.pull);
   a.cells = P->W_<CellDesc>(P->ws.cells);
   a.tiles = P->W_<TileDesc>(P->ws.tiles);
-  a.n_tiles = (int32_t)P->tiles.size();
+  a.n_tiles = (int32_t)P->tset().tiles.size();
   a.p = P->p;
+  a.tile_cols = P->tset().cols;
   a.den = P->W_<double>(P->ws.den);
   a.rcp = P->W_<float>(P->ws.rcp);
   a.eta = P->eta;
-  a.r = P->r;
   a.gamma = P->gamma;
   a.recompute_den = recompute;
   return a;
+}
+
+int upload_tiles(odp_plan* P, hipStream_t s) {
+  const odp_plan::TileSet& T = P->tset();
+  auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(P->wsp + off, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  ODP_HIP(up(P->ws.tiles, T.tiles.data(), sizeof(TileDesc) * T.tiles.size()));
+  ODP_HIP(up(P->ws.re_list, T.re_list.data(), sizeof(int32_t) * T.re_list.size()));
+  ODP_HIP(up(P->ws.re_first, T.re_first.data(), sizeof(int32_t) * T.re_first.size()));
+  ODP_HIP(up(P->ws.tf_first, T.tf_first.data(), sizeof(int32_t) * T.tf_first.size()));
+  ODP_HIP(up(P->ws.pull, T.pull.data(), sizeof(PullEntry) * T.pull.size()));
+  // pageable host sources: finish before the vectors may change
+  ODP_HIP(hipStreamSynchronize(s));
+  return ODP_OK;
+}
+
+// per-problem overlap penalties: cell descriptors carry r; reciprocals rebuilt
+int set_penalties(odp_plan* P, const double* r, hipStream_t s) {
+  for (int i = 0; i < P->n_probes(); ++i) P->batch[i].r = r[i];
+  for (CellDesc& cd : P->cells) cd.r = (float)P->batch[cd.probe].r;
+  if (!P->wsp) return ODP_OK;
+  ODP_HIP(hipMemcpyAsync(P->wsp + P->ws.cells, P->cells.data(), sizeof(CellDesc) * P->cells.size(),
+                         hipMemcpyHostToDevice, s));
+  ODP_HIP(launch_illum(illum_args(P, P->W_<float2>(P->ws.w), 0), s));
+  ODP_HIP(hipStreamSynchronize(s));
+  return ODP_OK;
 }
 
 }  // namespace
@@ -355,9 +459,7 @@ extern "C" {
 const char* odp_last_error(void) { return g_err.c_str(); }
 const char* odp_version(void) { return "odp 0.1 (gfx950)"; }
 
-int odp_plan_create(const odp_problem* prob, odp_plan** out) {
-  if (!prob || !out) return fail(ODP_EINVAL, "null argument");
-  *out = nullptr;
+static int validate_problem(const odp_problem* prob) {
   if (prob->p != 32 && prob->p != 64 && prob->p != 128)
     return fail(ODP_EUNSUPPORTED, "p must be 32, 64 or 128");
   if (prob->H < prob->p || prob->W < prob->p) return fail(ODP_EINVAL, "image smaller than the probe");
@@ -365,8 +467,8 @@ int odp_plan_create(const odp_problem* prob, odp_plan** out) {
   if (prob->D < 1) return fail(ODP_EINVAL, "D must be >= 1");
   if (prob->transform != ODP_FFT_F32 && prob->transform != ODP_DFT_SPLIT_BF16)
     return fail(ODP_EINVAL, "unknown transform");
-  if (prob->transform == ODP_DFT_SPLIT_BF16)
-    return fail(ODP_EUNSUPPORTED, "split-BF16 DFT transform is not built into this library");
+  if (prob->transform == ODP_DFT_SPLIT_BF16 && prob->p != 64)
+    return fail(ODP_EUNSUPPORTED, "the split-BF16 DFT transform is built for p = 64");
   int rc = check_params(prob->eps, prob->eta, prob->r, prob->mu, prob->gamma, prob->D, prob->blind);
   if (rc) return rc;
   if ((int64_t)prob->H * prob->W >= (int64_t)1 << 31) return fail(ODP_EUNSUPPORTED, "image too large");
@@ -377,6 +479,13 @@ int odp_plan_create(const odp_problem* prob, odp_plan** out) {
     if (prob->frame_sub[j] < 0 || prob->frame_sub[j] >= prob->D)
       return fail(ODP_EGEOM, "frame_sub out of range at frame " + std::to_string(j));
   }
+  return ODP_OK;
+}
+
+// Build a plan from a validated problem; `batch` describes the independent
+// problems it packs (one entry for a single problem).
+static int create_impl(const odp_problem* prob, std::vector<odp_plan::Entry> batch,
+                       std::vector<int32_t> sub_problem, odp_plan** out) {
   odp_plan* P = new (std::nothrow) odp_plan();
   if (!P) return fail(ODP_ENOMEM, "host allocation failed");
   P->H = prob->H;
@@ -391,12 +500,15 @@ int odp_plan_create(const odp_problem* prob, odp_plan** out) {
   P->gamma = prob->gamma;
   P->transform = prob->transform;
   P->blind = prob->blind ? 1 : 0;
+  P->batch = std::move(batch);
+  P->sub_problem = std::move(sub_problem);
   P->offsets.assign(prob->offsets, prob->offsets + 2 * (size_t)prob->J);
   P->frame_sub.assign(prob->frame_sub, prob->frame_sub + prob->J);
   if (prob->probe_fmask) {
     P->fmask.resize((size_t)prob->p * prob->p);
     for (size_t i = 0; i < P->fmask.size(); ++i) P->fmask[i] = prob->probe_fmask[i] ? 1.0f : 0.0f;
   }
+  int rc;
   try {
     rc = build_geometry(P);
   } catch (const std::bad_alloc&) {
@@ -408,6 +520,80 @@ int odp_plan_create(const odp_problem* prob, odp_plan** out) {
   }
   layout(P);
   *out = P;
+  return ODP_OK;
+}
+
+int odp_plan_create(const odp_problem* prob, odp_plan** out) {
+  if (!prob || !out) return fail(ODP_EINVAL, "null argument");
+  *out = nullptr;
+  int rc = validate_problem(prob);
+  if (rc) return rc;
+  std::vector<odp_plan::Entry> batch{{0, 0, prob->H, prob->W, 0, prob->J, 0, prob->D, prob->r, 0.0}};
+  return create_impl(prob, std::move(batch), std::vector<int32_t>(prob->D, 0), out);
+}
+
+int odp_batch_plan_create(const odp_problem* probs, int32_t n, odp_plan** out) {
+  if (!probs || !out || n < 1) return fail(ODP_EINVAL, "null argument or empty batch");
+  *out = nullptr;
+  const int p = probs[0].p;
+  int64_t Wt = 0, Jt = 0, Dt = 0;
+  int32_t Ht = 0;
+  for (int i = 0; i < n; ++i) {
+    const odp_problem& q = probs[i];
+    int rc = validate_problem(&q);
+    if (rc) return fail(rc, "problem " + std::to_string(i) + ": " + g_err);
+    if (q.p != p || q.transform != probs[0].transform || q.eps != probs[0].eps || q.eta != probs[0].eta ||
+        q.gamma != probs[0].gamma)
+      return fail(ODP_EINVAL, "batched problems must share p, transform, eps, eta and gamma");
+    if (q.blind) return fail(ODP_EUNSUPPORTED, "batches hold known-probe problems");
+    if (q.probe_fmask) return fail(ODP_EINVAL, "batches take no probe mask");
+    Ht = std::max(Ht, q.H);
+    Wt += q.W + (i ? 1 : 0);   // one blank column between problems: their subdomains never meet
+    Jt += q.J;
+    Dt += q.D;
+  }
+  if ((int64_t)Ht * Wt >= (int64_t)1 << 31 || Jt >= (int64_t)1 << 31) return fail(ODP_EUNSUPPORTED, "batch too large");
+  std::vector<int32_t> off((size_t)2 * Jt), sub((size_t)Jt), sub_problem((size_t)Dt);
+  std::vector<odp_plan::Entry> batch;
+  int32_t col = 0, J0 = 0, D0 = 0;
+  for (int i = 0; i < n; ++i) {
+    const odp_problem& q = probs[i];
+    for (int j = 0; j < q.J; ++j) {
+      off[2 * (size_t)(J0 + j)] = q.offsets[2 * j];
+      off[2 * (size_t)(J0 + j) + 1] = q.offsets[2 * j + 1] + col;
+      sub[J0 + j] = q.frame_sub[j] + D0;
+    }
+    for (int d = 0; d < q.D; ++d) sub_problem[D0 + d] = i;
+    batch.push_back(odp_plan::Entry{0, col, q.H, q.W, J0, q.J, D0, q.D, q.r, 0.0});
+    col += q.W + 1;
+    J0 += q.J;
+    D0 += q.D;
+  }
+  odp_problem all = probs[0];
+  all.H = Ht;
+  all.W = (int32_t)Wt;
+  all.J = (int32_t)Jt;
+  all.D = (int32_t)Dt;
+  all.offsets = off.data();
+  all.frame_sub = sub.data();
+  all.r = 1.0;  // per problem (cells carry their own r)
+  return create_impl(&all, std::move(batch), std::move(sub_problem), out);
+}
+
+int odp_batch_get_entry(const odp_plan* P, int32_t i, odp_batch_entry* o) {
+  if (!P || !o) return fail(ODP_EINVAL, "null argument");
+  if (i < 0 || i >= P->n_probes()) return fail(ODP_EINVAL, "batch index out of range");
+  const odp_plan::Entry& e = P->batch[i];
+  o->row0 = e.row0;
+  o->col0 = e.col0;
+  o->H = e.H;
+  o->W = e.W;
+  o->J0 = e.J0;
+  o->J = e.J;
+  o->D0 = e.D0;
+  o->D = e.D;
+  o->r = e.r;
+  o->illum_max = e.illum_max;
   return ODP_OK;
 }
 
@@ -423,7 +609,7 @@ int odp_plan_get_info(const odp_plan* P, odp_plan_info* o) {
   o->n_pairs = (int32_t)P->pairs.size();
   o->max_cover = P->max_cover;
   o->n_cells = (int32_t)P->cells.size();
-  o->n_tiles = (int32_t)P->tiles.size();
+  o->n_tiles = (int32_t)P->tset().tiles.size();
   o->p_sub = P->p_sub;
   o->n_lam = P->n_lam;
   o->workspace_bytes = P->ws.bytes;
@@ -464,8 +650,7 @@ int odp_plan_get_pairs(const odp_plan* P, int32_t* pairs, int64_t* lam_off) {
 int odp_plan_get_cover(const odp_plan* P, int32_t* cover) {
   if (!P || !cover) return fail(ODP_EINVAL, "null argument");
   std::fill(cover, cover + (size_t)P->H * P->W, 0);
-  for (const CellDesc& cd : P->cells) (void)cd;
-  for (const TileDesc& td : P->tiles) {
+  for (const TileDesc& td : P->tset().tiles) {
     const CellDesc& cd = P->cells[td.cell];
     for (int y = 0; y < td.nr; ++y)
       for (int x = 0; x < td.nc; ++x)
@@ -485,7 +670,7 @@ int odp_plan_bind(odp_plan* P, void* dev_ws, const float* dev_sqrt_f, const odp_
     return hipMemcpyAsync(P->wsp + off, src, bytes, hipMemcpyHostToDevice, s);
   };
   ODP_HIP(up(P->ws.tw, P->tw.data(), sizeof(float2) * P->tw.size()));
-  ODP_HIP(hipMemcpyAsync(P->wsp + P->ws.w, dev_w, sizeof(float2) * pp, hipMemcpyDeviceToDevice, s));
+  ODP_HIP(hipMemcpyAsync(P->wsp + P->ws.w, dev_w, sizeof(float2) * pp * P->n_probes(), hipMemcpyDeviceToDevice, s));
   ODP_HIP(up(P->ws.frames, P->frames.data(), sizeof(FrameDesc) * P->frames.size()));
   ODP_HIP(up(P->ws.order, P->order.data(), sizeof(int32_t) * P->order.size()));
   ODP_HIP(up(P->ws.sub_first, P->sub_first.data(), sizeof(int32_t) * P->sub_first.size()));
@@ -493,19 +678,29 @@ int odp_plan_bind(odp_plan* P, void* dev_ws, const float* dev_sqrt_f, const odp_
   ODP_HIP(up(P->ws.rects, P->rects.data(), sizeof(int32_t) * P->rects.size()));
   ODP_HIP(up(P->ws.usub_off, P->usub_off.data(), sizeof(int64_t) * P->usub_off.size()));
   ODP_HIP(up(P->ws.cells, P->cells.data(), sizeof(CellDesc) * P->cells.size()));
-  ODP_HIP(up(P->ws.tiles, P->tiles.data(), sizeof(TileDesc) * P->tiles.size()));
-  ODP_HIP(up(P->ws.re_list, P->re_list.data(), sizeof(int32_t) * P->re_list.size()));
-  ODP_HIP(up(P->ws.re_first, P->re_first.data(), sizeof(int32_t) * P->re_first.size()));
-  ODP_HIP(up(P->ws.tf_first, P->tf_first.data(), sizeof(int32_t) * P->tf_first.size()));
-  ODP_HIP(up(P->ws.pull, P->pull.data(), sizeof(PullEntry) * P->pull.size()));
+  int rc = upload_tiles(P, s);
+  if (rc) return rc;
   if (!P->fmask.empty()) ODP_HIP(up(P->ws.fmask, P->fmask.data(), sizeof(float) * pp));
+  if (!P->dft.empty()) ODP_HIP(up(P->ws.dft, P->dft.data(), sizeof(uint16_t) * P->dft.size()));
   ODP_HIP(launch_illum(illum_args(P, P->W_<float2>(P->ws.w), 1), s));
   double* misc = P->W_<double>(P->ws.misc);
   ODP_HIP(launch_sum_max(P->W_<double>(P->ws.den), P->p_sub, dev_sqrt_f, (int64_t)P->J * pp, misc, s));
+  // the largest illumination of each problem (penalty scales are chosen from it)
+  const int nb = P->n_probes();
+  double* pm = P->W_<double>(P->ws.pmax);
+  for (int i = 0; i < nb; ++i) {
+    const odp_plan::Entry& e = P->batch[i];
+    const int64_t u0 = P->usub_off[e.D0];
+    const int64_t u1 = e.D0 + e.D < P->D ? P->usub_off[e.D0 + e.D] : P->p_sub;
+    ODP_HIP(launch_sum_max(P->W_<double>(P->ws.den) + u0, u1 - u0, dev_sqrt_f, 0, pm + (size_t)i * (2 + 2048), s));
+  }
   double host[2] = {0, 0};
+  std::vector<double> hp((size_t)nb * (2 + 2048));
   ODP_HIP(hipMemcpyAsync(host, misc, sizeof(host), hipMemcpyDeviceToHost, s));
+  ODP_HIP(hipMemcpyAsync(hp.data(), pm, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, s));
   ODP_HIP(hipStreamSynchronize(s));
   P->illum_max = host[0];
+  for (int i = 0; i < nb; ++i) P->batch[i].illum_max = hp[(size_t)i * (2 + 2048)];
   return ODP_OK;
 }
 
@@ -525,8 +720,15 @@ int odp_plan_set_params(odp_plan* P, double eps, double eta, double r, double mu
   P->r = r;
   P->mu = mu;
   P->gamma = gamma;
-  if (P->wsp) ODP_HIP(launch_illum(illum_args(P, P->W_<float2>(P->ws.w), 0), s));
-  return ODP_OK;
+  std::vector<double> rs(P->n_probes(), r);
+  return set_penalties(P, rs.data(), s);
+}
+
+int odp_batch_set_penalties(odp_plan* P, const double* r, hipStream_t s) {
+  if (!P || !r) return fail(ODP_EINVAL, "null argument");
+  for (int i = 0; i < P->n_probes(); ++i)
+    if (!(r[i] > 0.0) && P->batch[i].D > 1) return fail(ODP_EINVAL, "r must be positive when D > 1");
+  return set_penalties(P, r, s);
 }
 
 int odp_forward(const odp_plan* P, const odp_c32* u, const odp_c32* w, odp_c32* out, hipStream_t s) {
@@ -589,6 +791,7 @@ static SweepArgs sweep_args(const odp_plan* P, char* b, double* stats) {
   a.order = P->W_<int32_t>(P->ws.order);
   a.J = P->J;
   a.chunk = P->chunk;
+  a.xcd_slice = P->xcd_slice;
   a.eps = (float)P->eps;
   a.eta = (float)P->eta;
   a.part = stats ? P->W_<double>(P->ws.fpart) : nullptr;
@@ -604,14 +807,14 @@ static PixelArgs pixel_args(const odp_plan* P, char* b, double* stats) {
   a.lam = reinterpret_cast<float2*>(b + P->st.lam);
   a.cells = P->W_<CellDesc>(P->ws.cells);
   a.tiles = P->W_<TileDesc>(P->ws.tiles);
-  a.n_tiles = (int32_t)P->tiles.size();
+  a.n_tiles = (int32_t)P->tset().tiles.size();
   a.p = P->p;
+  a.tile_cols = P->tset().cols;
   a.psi = P->W_<float2>(P->ws.psi);
   a.tf_first = P->W_<int32_t>(P->ws.tf_first);
   a.pull = P->W_<PullEntry>(P->ws.pull);
   a.w_sub = P->blind ? reinterpret_cast<const float2*>(b + P->st.w_sub) : nullptr;
   a.eta = (float)P->eta;
-  a.r = (float)P->r;
   a.gamma = (float)P->gamma;
   a.part = stats ? P->W_<double>(P->ws.tpart) : nullptr;
   return a;
@@ -627,7 +830,12 @@ static int finish_stats(const odp_plan* P, double* stats, hipStream_t s) {
 int odp_frame_sweep(odp_plan* P, void* dev_state, double* dev_stats, hipStream_t s) {
   if (!P || !dev_state) return fail(ODP_EINVAL, "null argument");
   if (!P->wsp) return fail(ODP_EINVAL, "plan is not bound");
-  ODP_HIP(launch_sweep(P->p, sweep_args(P, static_cast<char*>(dev_state), dev_stats), s));
+  const SweepArgs a = sweep_args(P, static_cast<char*>(dev_state), dev_stats);
+  if (P->transform == ODP_DFT_SPLIT_BF16) {
+    ODP_HIP(launch_sweep_dft(P->p, a, DftTable{P->W_<uint16_t>(P->ws.dft)}, s));
+  } else {
+    ODP_HIP(launch_sweep(P->p, a, s));
+  }
   return ODP_OK;
 }
 
@@ -717,7 +925,8 @@ int odp_amp_loss(const odp_plan* P, const odp_c32* u, const odp_c32* w, double* 
   ga.p = P->p;
   ga.cells = P->W_<CellDesc>(P->ws.cells);
   ga.tiles = P->W_<TileDesc>(P->ws.tiles);
-  ga.n_tiles = (int32_t)P->tiles.size();
+  ga.n_tiles = (int32_t)P->tset().tiles.size();
+  ga.tile_cols = P->tset().cols;
   ga.tf_first = P->W_<int32_t>(P->ws.tf_first);
   ga.pull = P->W_<PullEntry>(P->ws.pull);
   ga.grad_u = reinterpret_cast<float2*>(grad_u);
@@ -727,6 +936,149 @@ int odp_amp_loss(const odp_plan* P, const odp_c32* u, const odp_c32* w, double* 
   ga.n_chunks = (P->J + ga.frames_per_chunk - 1) / ga.frames_per_chunk;
   ODP_HIP(launch_loss_grads(ga, s));
   return ODP_OK;
+}
+
+// ---- tuning -----------------------------------------------------------------
+
+int odp_plan_get_tuning(const odp_plan* P, odp_tuning* o) {
+  if (!P || !o) return fail(ODP_EINVAL, "null argument");
+  o->transform = P->transform;
+  o->xcd_slice = P->xcd_slice;
+  o->tiling = P->ts;
+  o->tile_rows = P->tset().rows;
+  o->tile_cols = P->tset().cols;
+  o->ms_per_iter = 0.0;
+  o->n_tried = 0;
+  return ODP_OK;
+}
+
+int odp_plan_set_tuning(odp_plan* P, int32_t transform, int32_t xcd_slice, int32_t tiling, hipStream_t s) {
+  if (!P) return fail(ODP_EINVAL, "null argument");
+  if (transform != ODP_FFT_F32 && transform != ODP_DFT_SPLIT_BF16) return fail(ODP_EINVAL, "unknown transform");
+  if (transform == ODP_DFT_SPLIT_BF16 && P->p != 64)
+    return fail(ODP_EUNSUPPORTED, "the split-BF16 DFT transform is built for p = 64");
+  if (tiling < 0 || tiling > 2) return fail(ODP_EINVAL, "tiling must be 0, 1 or 2");
+  P->transform = transform;
+  P->xcd_slice = xcd_slice ? 1 : 0;
+  if (tiling != P->ts) {
+    P->ts = tiling;
+    if (P->wsp) return upload_tiles(P, s);
+  }
+  return ODP_OK;
+}
+
+int odp_plan_autotune(odp_plan* P, void* dev_scratch_state, int32_t iters, hipStream_t s, odp_tuning* best) {
+  if (!P || !dev_scratch_state) return fail(ODP_EINVAL, "null argument");
+  if (!P->wsp) return fail(ODP_EINVAL, "plan is not bound");
+  if (iters < 1) iters = 1;
+  std::vector<int> transforms = {P->transform};
+  if (P->p == 64) transforms = {ODP_FFT_F32, ODP_DFT_SPLIT_BF16};
+  hipEvent_t e0, e1;
+  ODP_HIP(hipEventCreate(&e0));
+  ODP_HIP(hipEventCreate(&e1));
+  double best_ms = 1e300;
+  int bt = P->transform, bx = P->xcd_slice, bs = P->ts, tried = 0;
+  int rc = ODP_OK;
+  for (int tr : transforms) {
+    for (int xs = 1; xs >= 0 && !rc; --xs) {
+      for (int ts = 0; ts < 3 && !rc; ++ts) {
+        rc = odp_plan_set_tuning(P, tr, xs, ts, s);
+        if (!rc) rc = odp_admm_iterate(P, dev_scratch_state, 2, nullptr, s);  // warm-up
+        if (rc) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(ODP_EHIP, "hipEventRecord"); break; }
+        rc = odp_admm_iterate(P, dev_scratch_state, iters, nullptr, s);
+        if (rc) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          rc = fail(ODP_EHIP, "event timing failed");
+          break;
+        }
+        ++tried;
+        const double per = (double)ms / iters;
+        if (per < best_ms) {
+          best_ms = per;
+          bt = tr;
+          bx = xs;
+          bs = ts;
+        }
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  rc = odp_plan_set_tuning(P, bt, bx, bs, s);
+  if (rc) return rc;
+  if (best) {
+    odp_plan_get_tuning(P, best);
+    best->ms_per_iter = best_ms;
+    best->n_tried = tried;
+  }
+  return ODP_OK;
+}
+
+// ---- graphs -------------------------------------------------------------------
+
+}  // extern "C"
+
+struct odp_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+int odp_graph_create(odp_plan* const* plans, void* const* states, int32_t n, int32_t n_iter, odp_graph** out) {
+  if (!plans || !states || !out || n < 1 || n_iter < 1) return fail(ODP_EINVAL, "bad graph arguments");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i)
+    if (!plans[i] || !states[i] || !plans[i]->wsp) return fail(ODP_EINVAL, "unbound plan or null state");
+  hipStream_t cs;
+  ODP_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  int rc = ODP_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    hipStreamDestroy(cs);
+    return fail(ODP_EHIP, "hipStreamBeginCapture failed");
+  }
+  for (int it = 0; it < n_iter && !rc; ++it)
+    for (int i = 0; i < n && !rc; ++i) rc = odp_admm_iterate(plans[i], states[i], 1, nullptr, cs);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(cs, &g);
+  hipStreamDestroy(cs);
+  if (rc) {
+    if (g) hipGraphDestroy(g);
+    return rc;
+  }
+  if (ec != hipSuccess || !g) return fail(ODP_EHIP, "hipStreamEndCapture failed");
+  hipGraphExec_t ex = nullptr;
+  if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+    hipGraphDestroy(g);
+    return fail(ODP_EHIP, "hipGraphInstantiate failed");
+  }
+  odp_graph* G = new (std::nothrow) odp_graph();
+  if (!G) {
+    hipGraphExecDestroy(ex);
+    hipGraphDestroy(g);
+    return fail(ODP_ENOMEM, "host allocation failed");
+  }
+  G->graph = g;
+  G->exec = ex;
+  *out = G;
+  return ODP_OK;
+}
+
+int odp_graph_launch(odp_graph* G, hipStream_t s) {
+  if (!G) return fail(ODP_EINVAL, "null graph");
+  ODP_HIP(hipGraphLaunch(G->exec, s));
+  return ODP_OK;
+}
+
+void odp_graph_destroy(odp_graph* G) {
+  if (!G) return;
+  if (G->exec) hipGraphExecDestroy(G->exec);
+  if (G->graph) hipGraphDestroy(G->graph);
+  delete G;
 }
 
 }  // extern "C"

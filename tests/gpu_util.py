@@ -71,3 +71,20 @@ def rel(a, b) -> float:
 
 def rel_list(a: list, b: list) -> float:
     return max(rel(x, y) for x, y in zip(a, b))
+
+
+def same_state(a: "odp.State", b: "odp.State") -> bool:
+    """Bit-for-bit equality of the state variables (u_d, Gamma, Lam and, when blind,
+    w, w_d, Delta); the alignment gaps between them carry no data."""
+    torch.cuda.synchronize()
+    if not all(torch.equal(x, y) for x, y in zip(a.u_sub(), b.u_sub())):
+        return False
+    if not torch.equal(a.gamma(), b.gamma()):
+        return False
+    la, lb = a.lam(), b.lam()
+    if not all(torch.equal(la[k], lb[k]) for k in la):
+        return False
+    if a.plan.blind:
+        return (torch.equal(a.probe(), b.probe()) and torch.equal(a.probe_copies(), b.probe_copies())
+                and torch.equal(a.probe_multipliers(), b.probe_multipliers()))
+    return True

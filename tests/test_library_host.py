@@ -108,3 +108,42 @@ def test_one_subdomain_needs_no_overlap_penalty():
     a = _plan_args(r=0.0, frame_sub=np.zeros(len(_plan_args()["offsets"]), np.int32))
     plan = odp.Plan(**a)
     assert plan.info.D == 1 and plan.info.n_pairs == 0 and plan.info.n_lam == 0
+
+
+def _batch_problems(n=5):
+    out = []
+    for s in synthetic.batch_specs(64)[:n]:
+        pr = synthetic.draw_problem(s)
+        out.append((s, pr))
+    return out
+
+
+def test_batch_plan_packs_independent_problems():
+    items = [(s, pr) for (s, pr) in _batch_problems(8) if s.p == 64]
+    probs = [dict(H=s.n, W=s.n, p=s.p, offsets=pr["offsets"], frame_sub=pr["frame_sub"], r=1.0 + i)
+             for i, (s, pr) in enumerate(items)]
+    batch = odp.Plan.batch(probs)
+    g = batch.geometry()
+    assert batch.n_problems() == len(items)
+    pair_rows = []
+    for i, (s, pr) in enumerate(items):
+        e = batch.entry(i)
+        single = odp.Plan(s.n, s.n, s.p, pr["offsets"], pr["frame_sub"], r=1.0)
+        sg = single.geometry()
+        # rectangles shifted by the problem's column origin
+        want = sg.rects + np.array([0, e.col0, 0, e.col0], dtype=np.int32)
+        np.testing.assert_array_equal(g.rects[e.D0:e.D0 + e.D], want)
+        for q in sg.pairs:
+            pair_rows.append((q[0] + e.D0, q[1] + e.D0, q[2], q[3] + e.col0, q[4], q[5] + e.col0))
+        assert e.r == 1.0 + i and e.J == len(pr["offsets"])
+    # no pair crosses problems
+    np.testing.assert_array_equal(g.pairs, np.array(sorted(pair_rows), dtype=np.int32).reshape(-1, 6))
+
+
+def test_batch_rejects_mixed_probe_sizes():
+    items = _batch_problems(12)
+    ps = {s.p for s, _ in items}
+    assert ps == {64, 128}
+    probs = [dict(H=s.n, W=s.n, p=s.p, offsets=pr["offsets"], frame_sub=pr["frame_sub"], r=1.0) for s, pr in items]
+    with pytest.raises(OdpError):
+        odp.Plan.batch(probs)
