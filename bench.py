@@ -60,23 +60,31 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def gpu_leg(args, torch, odp, synthetic):
+def synth_intensities(torch, odp, synthetic, spec, pr, u_true_np, w_np):
+    """Measured intensities: the library's own forward operator, then seeded Poisson counts."""
+    n, p = spec.n, spec.p
+    J = len(pr["offsets"])
+    u_true = torch.from_numpy(u_true_np.astype("complex64")).cuda()
+    w = torch.from_numpy(w_np.astype("complex64")).cuda()
+    synth = odp.Plan(u_true_np.shape[0], u_true_np.shape[1], p, pr["offsets"], pr["frame_sub"], r=1.0)
+    synth.bind(torch.ones((J, p, p), dtype=torch.float32, device="cuda"), w)
+    f = (synth.forward(u_true, w).abs() ** 2).double().cpu().numpy()
+    del synth
+    return f
+
+
+def gpu_leg(args, torch, odp, synthetic, transform=0):
     spec = synthetic.CONFIGS["c2"]
     pr = synthetic.draw_problem(spec)
     n, p = spec.n, spec.p
     dev = "cuda"
-    u_true = torch.from_numpy(pr["u_true"].astype("complex64")).to(dev)
     w = torch.from_numpy(pr["w"].astype("complex64")).to(dev)
     J = len(pr["offsets"])
-    # measured intensities: the library's own forward operator, then seeded Poisson counts
-    synth = odp.Plan(n, n, p, pr["offsets"], pr["frame_sub"], r=1.0)
-    synth.bind(torch.ones((J, p, p), dtype=torch.float32, device=dev), w)
-    f = (synth.forward(u_true, w).abs() ** 2).double().cpu().numpy()
-    del synth
+    f = synth_intensities(torch, odp, synthetic, spec, pr, pr["u_true"], pr["w"])
     f = synthetic.poisson_counts(f, spec.peak, pr["rng_poisson"])
     sqrt_f = torch.from_numpy(f ** 0.5).float().to(dev)
     eps, eta = 0.5, 0.1
-    plan = odp.Plan(n, n, p, pr["offsets"], pr["frame_sub"], eps=eps, eta=eta, r=1.0)
+    plan = odp.Plan(n, n, p, pr["offsets"], pr["frame_sub"], eps=eps, eta=eta, r=1.0, transform=transform)
     plan.bind(sqrt_f, w)
     r = 0.5 * eta * plan.illum_max()
     plan.set_params(r=r)
@@ -134,26 +142,175 @@ def cpu_leg(args, torch, odp, synthetic):
         st, _ = od2pm_run(g, w, f, eps, eta, r, K)
         dt = time.perf_counter() - t
     u_or = merge(g, st.u)
-    # the GPU path on the identical data and iteration count
-    plan = odp.Plan(spec.n, spec.n, spec.p, pr["offsets"], pr["frame_sub"], eps=eps, eta=eta, r=r)
-    plan.bind(torch.from_numpy(sf32).cuda(), torch.from_numpy(w.astype(np.complex64)).cuda())
-    state = plan.new_state()
-    plan.iterate(state, K)
-    u_gpu = plan.merge(state).cpu().numpy().astype(np.complex128)
-    rel_err = float(np.linalg.norm(u_gpu - u_or) / np.linalg.norm(u_or))
+    # the GPU path on the identical data and iteration count, both transforms
+    errs = {}
+    for name, tr in (("fft_f32", odp.ODP_FFT_F32), ("dft_split_bf16", odp.ODP_DFT_SPLIT_BF16)):
+        plan = odp.Plan(spec.n, spec.n, spec.p, pr["offsets"], pr["frame_sub"], eps=eps, eta=eta, r=r,
+                        transform=tr)
+        plan.bind(torch.from_numpy(sf32).cuda(), torch.from_numpy(w.astype(np.complex64)).cuda())
+        state = plan.new_state()
+        plan.iterate(state, K)
+        u_gpu = plan.merge(state).cpu().numpy().astype(np.complex128)
+        errs[name] = float(np.linalg.norm(u_gpu - u_or) / np.linalg.norm(u_or))
     return dict(value=g.J * K / dt, unit="frame-iters/s", cores=1, kind="oracle",
                 sample=f"{K} OD2Pm iterations of the full 512x512 / 841-frame workload (FP64 NumPy, "
                        f"single thread) in {dt:.1f} s on {cpu_model()} ({os.cpu_count()} logical CPUs)",
-                rel_err_gpu_vs_oracle=rel_err, rel_err_iters=K)
+                rel_err_gpu_vs_oracle=errs, rel_err_iters=K)
 
+
+
+# ---------------------------------------------------------------------------
+# other workloads (not the metric's line; run with --workload)
+# ---------------------------------------------------------------------------
+
+def _timed(torch, fn, steps):
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def _sweep_ms(torch, plan, state, steps, probe=False):
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        plan.frame_sweep(state)
+        b.record()
+        if probe:
+            plan.probe_update(state)
+        plan.pixel_update(state)
+    torch.cuda.synchronize()
+    return sum(a.elapsed_time(b) for a, b in ev) / steps
+
+
+def run_c3(args, torch, odp, synthetic):
+    """Amplitude loss and its gradients (forward + hand-written backward), 1024^2, p=128, 841 frames."""
+    import numpy as np
+    spec = synthetic.CONFIGS["c3"]
+    pr = synthetic.draw_problem(spec)
+    f = synth_intensities(torch, odp, synthetic, spec, pr, pr["u_true"], pr["w"])
+    plan = odp.Plan(spec.n, spec.n, spec.p, pr["offsets"], pr["frame_sub"], r=1.0)
+    w = torch.from_numpy(pr["w"].astype("complex64")).cuda()
+    plan.bind(torch.from_numpy(np.sqrt(f)).float().cuda(), w)
+    rng = np.random.default_rng(0)
+    u = torch.from_numpy((pr["u_true"] * (1 + 0.1 * (rng.standard_normal((spec.n, spec.n))
+                                                       + 1j * rng.standard_normal((spec.n, spec.n))))).astype("complex64")).cuda()
+    J = plan.info.J
+    for _ in range(args.warmup):
+        plan.amp_loss(u, w)
+    ms = _timed(torch, lambda: plan.amp_loss(u, w), args.steps)
+    ms_fwd = _timed(torch, lambda: plan.amp_loss(u, w, grad_u=False, grad_w=False), args.steps)
+    # algorithmic bytes: sqrt f read twice-free (once), u and grad_u image, phi handoff counted as traffic
+    alg = 4.0 * J * spec.p ** 2 + 16.0 * spec.n ** 2
+    return {"metric": "amplitude-loss frame evaluations/s (forward + backward)", "value": J / (ms / 1e3),
+            "unit": "frame-evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "1024x1024 image, 128x128 probe, step 32, 841 frames, loss + dL/du + dL/dw"},
+            "forward_only": {"value": J / (ms_fwd / 1e3), "ms": ms_fwd},
+            "roofline": {"bound": "hbm", "achieved": alg / (ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}}
+
+
+def run_c4(args, torch, odp, synthetic):
+    """64 independent uneven problems, two batch plans (p=64, p=128), autotuned, graph-replayed."""
+    import numpy as np
+    specs = synthetic.batch_specs(64)
+    groups = {}
+    for s in specs:
+        groups.setdefault(s.p, []).append(s)
+    eta = 0.1
+    plans, states, info = [], [], {}
+    total_frames = 0
+    for p, group in sorted(groups.items()):
+        probs, sfs, ws = [], [], []
+        for s in group:
+            pr = synthetic.draw_problem(s)
+            f = synth_intensities(torch, odp, synthetic, s, pr, pr["u_true"], pr["w"])
+            f = synthetic.poisson_counts(f, s.peak, pr["rng_poisson"])
+            sfs.append(np.sqrt(f).astype(np.float32))
+            ws.append(pr["w"].astype(np.complex64))
+            probs.append(dict(H=s.n, W=s.n, p=p, offsets=pr["offsets"], frame_sub=pr["frame_sub"], eps=0.5,
+                              eta=eta, r=1.0))
+        plan = odp.Plan.batch(probs)
+        plan.bind(torch.from_numpy(np.concatenate(sfs)).cuda(), torch.from_numpy(np.stack(ws)).cuda())
+        plan.set_penalties([0.5 * eta * plan.entry(i).illum_max for i in range(len(group))])
+        scratch = plan.new_state()
+        t = plan.autotune(scratch, iters=3)
+        del scratch
+        plans.append(plan)
+        states.append(plan.new_state())
+        total_frames += plan.info.J
+        info[f"p{p}"] = {"problems": len(group), "frames": plan.info.J, "subdomains": plan.info.D,
+                         "tuning": {"transform": t.transform, "xcd_slice": t.xcd_slice,
+                                    "tile": [t.tile_rows, t.tile_cols], "ms_per_iter": t.ms_per_iter}}
+    K = 100
+    g = odp.Graph(plans, states, K)
+    g.launch()                          # warm-up replay
+    ms = _timed(torch, g.launch, 3) / K
+    return {"metric": "ADMM frame-iters/s, 64 uneven problems in one graph", "value": total_frames / (ms / 1e3),
+            "unit": "frame-iters/s", "n_gpus": 1, "steps": 3 * K, "warmup": K, "ms_per_step": ms,
+            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "64 non-blind problems: image 256..1024, probe 64 or 128, step p*U(0.25,0.5), "
+                                   "2x2..6x6 subdomains, Poisson 1e3..1e5; 100 iterations per graph replay",
+                       "frames": total_frames, "groups": info}}
+
+
+def run_c5(args, torch, odp, synthetic):
+    """2048^2, p=128, 6561 frames, 8x8 subdomains: blind (Alg. 3) and non-blind sweeps."""
+    import math
+    import numpy as np
+    spec = synthetic.CONFIGS["c5"]
+    pr = synthetic.draw_problem(spec)
+    f = synth_intensities(torch, odp, synthetic, spec, pr, pr["u_true"], pr["w"])
+    f = synthetic.poisson_counts(f, spec.peak, pr["rng_poisson"])
+    sqrt_f = torch.from_numpy(np.sqrt(f)).float().cuda()
+    mean_energy = float(f.sum(axis=(1, 2)).mean())
+    del f
+    w0 = synthetic.make_probe(spec.p, spec.init_radius, 0.0) * synthetic.problems.blind_init_amplitude(
+        mean_energy, spec.init_radius)
+    w0 = torch.from_numpy(w0.astype("complex64")).cuda()
+    w_true = torch.from_numpy(pr["w"].astype("complex64")).cuda()
+    eta = 0.1
+    out = {}
+    J = len(pr["offsets"])
+    for mode in ("nonblind", "blind"):
+        blind = mode == "blind"
+        plan = odp.Plan(spec.n, spec.n, spec.p, pr["offsets"], pr["frame_sub"], eps=0.5, eta=eta, r=1.0,
+                        mu=1.0, blind=blind)
+        plan.bind(sqrt_f, w0 if blind else w_true)
+        mu = 0.5 * eta * max(int(np.sum(pr["frame_sub"] == d)) for d in range(plan.info.D))
+        plan.set_params(r=0.5 * eta * plan.illum_max(), mu=mu)
+        st = plan.new_state(w0=w0 if blind else None)
+        plan.iterate(st, args.warmup)
+        ms = _timed(torch, lambda: plan.iterate(st, 1), args.steps)
+        sweep = _sweep_ms(torch, plan, st, min(args.steps, 20), probe=blind)
+        alg = 20.0 * J * spec.p ** 2 + 16.0 * plan.info.p_sub
+        out[mode] = {"value": J / (ms / 1e3), "ms_per_step": ms, "sweep_ms": sweep,
+                     "sweep_roofline": {"bound": "hbm", "achieved": alg / (sweep / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
+                                        "unit": "GB/s", "frac": alg / (sweep / 1e3) / 1e9 / HBM_PEAK_GBS}}
+        del plan, st
+    return {"metric": "ADMM frame-iters/s, 2048^2 / 6561 frames of 128^2, 8x8 subdomains",
+            "value": out["blind"]["value"], "unit": "frame-iters/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": out["blind"]["ms_per_step"], "higher_is_better": True,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "blind OD2BP, 2048x2048, probe 128 (init disk R=40), step 24, 8x8 subdomains, "
+                                   "Poisson 1e4"},
+            "modes": out}
 
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--cpu-iters", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+                    help="c2 (default, the metric's workload); c3 loss+gradient; c4 64-problem batch; c5 blind")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (scales the HBM counters)")
     args = ap.parse_args()
@@ -181,7 +338,12 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload != "c2":
+        run = {"c3": run_c3, "c4": run_c4, "c5": run_c5}[args.workload]
+        print(json.dumps(run(args, torch, odp, synthetic)), flush=True)
+        return 0
     g = gpu_leg(args, torch, odp, synthetic)
+    gd = gpu_leg(args, torch, odp, synthetic, transform=odp.ODP_DFT_SPLIT_BF16)
     ms_per_step = g["total_ms"] / args.steps
     value = g["J"] * args.steps / (g["total_ms"] / 1e3)
     achieved = g["alg_bytes"] / (g["sweep_avg_ms"] / 1e3) / 1e9
@@ -205,6 +367,12 @@ def main() -> int:
                         "r=0.5*eta*max(diag A*A)",
             "transform": "fft_f32",
             "frames": g["J"], "probe": g["p"], "image": g["n"], "subdomains": g["D"], "pairs": g["n_pairs"],
+        },
+        "transforms": {
+            "fft_f32": {"value": value, "ms_per_step": ms_per_step, "sweep_ms": g["sweep_avg_ms"]},
+            "dft_split_bf16": {"value": gd["J"] * args.steps / (gd["total_ms"] / 1e3),
+                               "ms_per_step": gd["total_ms"] / args.steps, "sweep_ms": gd["sweep_avg_ms"],
+                               "sweep_mfma_tflops": 96.0 * 64 ** 3 * gd["J"] / (gd["sweep_avg_ms"] / 1e3) / 1e12},
         },
         "roofline": {
             "bound": "hbm",

@@ -140,6 +140,12 @@ struct Frame {
   // v: the 16 spatial values of this thread's stage-A line (already multiplied
   // by the probe).  On return v holds 16 frequencies, see freq().
   __device__ static void forward(float2* v, float2* lds, const float2* __restrict__ tw, int t) {
+    forward_a(v, lds, tw, t);
+    forward_bc(v, lds, tw, t);
+  }
+
+  // the two halves of forward(): stage A into LDS, then stages B and C back to v
+  __device__ static __forceinline__ void forward_a(float2* v, float2* lds, const float2* __restrict__ tw, int t) {
     const int col = a_col(t), r2 = a_r2(t);
     const float2* ta = tw + 16 * uniform_r2(t);
     dft16<false>(v);
@@ -148,6 +154,9 @@ struct Frame {
       const float2 x = k == 0 ? v[k] : c_mul(v[k], ta[k]);
       lds[(N2 * k + r2) * LP + col] = x;
     }
+  }
+
+  __device__ static __forceinline__ void forward_bc(float2* v, float2* lds, const float2* __restrict__ tw, int t) {
     __syncthreads();
     stage_b<false>(lds, tw, t);
     __syncthreads();

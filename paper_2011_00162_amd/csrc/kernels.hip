@@ -60,18 +60,32 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
     const int row = F::N2 * r1 + r2;
     v[r1] = c_mul(a.u[fd.base + (int64_t)row * fd.pitch + col], w[row * P + col]);
   }
-  F::forward(v, lds, a.tw, t);
+  F::forward_a(v, lds, a.tw, t);
+  // The thread's amplitudes (and, for P <= 64, multipliers) are fetched now, while
+  // stages B and C run: between stages A and C the thread holds no frame data in
+  // registers.  At P = 128 (1024 threads, 128 VGPRs) only the amplitudes fit.
+  constexpr int PRE = 1;
+  const size_t fbase = (size_t)j * P * P;
+  float2 gpre[16];
+  float spre[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    int kr, kc;
+    F::freq(t, e, kr, kc);
+    if (PRE >= 1) spre[e] = a.sqrt_f[fbase + kr * P + kc];
+    if (PRE >= 2) gpre[e] = a.gamma[fbase + kr * P + kc];
+  }
+  F::forward_bc(v, lds, a.tw, t);
 
   double mis = 0.0, gsum = 0.0;
-  const size_t fbase = (size_t)j * P * P;
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     int kr, kc;
     F::freq(t, e, kr, kc);
     const size_t idx = fbase + kr * P + kc;
     const float2 X = c_scale(v[e], inv_p);
-    const float sf = a.sqrt_f[idx];
-    const float2 y = c_add(a.gamma[idx], X);
+    const float sf = PRE >= 1 ? spre[e] : a.sqrt_f[idx];
+    const float2 y = c_add(PRE >= 2 ? gpre[e] : a.gamma[idx], X);
     const float2 z = prox_stagm(y, sf, pc);
     const float2 g = c_sub(y, z);
     a.gamma[idx] = g;
@@ -142,12 +156,13 @@ __device__ __forceinline__ void pull_pixel(const PullEntry* __restrict__ pull, i
                                            int yi, int xi, int p, bool act, float2& num, double& den) {
   const int64_t pix = (int64_t)yi * p + xi;
   int k = k0;
-  for (; k + 4 <= k1; k += 4) {
-    PullEntry e[4];
-    bool in[4];
-    float2 ps[4], ww[4];
+  constexpr int B = 4;
+  for (; k + B <= k1; k += B) {
+    PullEntry e[B];
+    bool in[B];
+    float2 ps[B], ww[B];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < B; ++q) {
       e[q] = pull[k + q];
       const int dy = yi - e[q].r, dx = xi - e[q].c;
       in[q] = act && (unsigned)dy < (unsigned)p && (unsigned)dx < (unsigned)p;
@@ -155,7 +170,7 @@ __device__ __forceinline__ void pull_pixel(const PullEntry* __restrict__ pull, i
       if (BLIND) ww[q] = ws[in[q] ? dy * p + dx : 0];
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < B; ++q) {
       if (BLIND) {
         const float2 c = c_mulc(ps[q], ww[q]);
         num = in[q] ? c_add(num, c) : num;

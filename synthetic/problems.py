@@ -219,8 +219,11 @@ def batch_specs(count: int = 64, seed: int = 4) -> list[ProblemSpec]:
         g = int(rng.integers(2, 7))
         peak = float(10.0 ** rng.uniform(3.0, 5.0))
         radius, quad = (24.0, 0.02) if p == 64 else (48.0, 0.01)
+        # each block spans at least ceil(p/step) scan positions per axis, so that only
+        # neighbouring subdomains overlap (at most 4 copies of a pixel), as in the
+        # paper's stripe and two-subdomain decompositions
         k = len(raster_positions(n, p, step))
-        g = min(g, k)
+        g = max(1, min(g, k // -(-p // step)))
         specs.append(ProblemSpec(f"c4_{i:02d}", n=n, sigma=8.0, p=p, radius=radius, quad=quad,
                                  step=step, jitter=0, dy=g, dx=g, peak=peak, iters=100,
                                  seed=child))
