@@ -136,36 +136,57 @@ hipError_t launch_sweep(int p, const SweepArgs& a, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // K3: pixel update (Alg. 2 Steps 1 (v), 3 (u) and 4 (Lam); Alg. 3 Step 4 (U)
-// and the Lam half of Step 5) on one 256-pixel tile of a cell.
+// and the Lam half of Step 5) on one tile of a cell.
 //   num_d   = sum_{j in d, window covers x} psi_j(x - o_j)    (A_d*(z - Gamma), fixed order)
 //   v_{a,b} = (u_a + u_b + Lam_{a,b} + Lam_{b,a}) / 2        from the iterate n
 //   u_d     = (eta num_d + r sum_{e != d} (v_{d,e} - Lam_{d,e}) + gamma u_d) / (eta den_d + r k + gamma)
 //   Lam_{d,e} += u_d^{new} - v_{d,e}
 // Blind: num_d and the FP64 illumination den_d = sum |w_d|^2 both use the new
 // probe copy w_d, in the same pull.  Non-blind: the reciprocal comes from bind.
-// Pairs (s, t), s < t, of the cell's subdomain list are stored at index
-// t(t-1)/2 + s, so every register index below is a compile-time constant.
+//
+// Every thread owns one (pixel, subdomain copy): a cell with m copies per pixel
+// has tiles of 256 / m' pixels (m' = m rounded up to a power of two) and thread t
+// takes copy s = t / (256 / m') of tile pixel t % (256 / m'), so every copy does
+// one pull and all copies of a pixel sit in one workgroup.  u_d and Lam_{d,e} of
+// a pixel are written only by the thread of copy d, after a barrier that follows
+// every thread's reads of the iterate n, so each thread sees u^n and Lam^n of the
+// other copies.  Pairs (a, b), a < b, of the cell's subdomain list are stored at
+// index b(b-1)/2 + a.
 // ---------------------------------------------------------------------------
+// one 16-byte load per record, so the frame base is fetched with the window corner
+__device__ __forceinline__ PullEntry load_entry(const PullEntry* e) {
+  const int4 v = *reinterpret_cast<const int4*>(e);
+  PullEntry o;
+  o.base = (int64_t)(((uint64_t)(uint32_t)v.y << 32) | (uint32_t)v.x);
+  o.r = v.z;
+  o.c = v.w;
+  return o;
+}
+
 // Sum of the covering frames' contributions at image pixel (yi, xi), over the
-// records [k0, k1) in order.  Loads are unconditional (out-of-window lanes read
-// element 0 and discard it) and four records are fetched per step, so several
-// loads are in flight per wavefront.
+// records [k0, k1) in order.  The records are the same for a whole copy group
+// (scalar loads when the group spans whole wavefronts) and are taken B at a time,
+// the last group padded with repeats of record k1 - 1 that count as outside every
+// window.  The psi loads are unconditional (lanes outside a window read element 0
+// and discard it; lanes outside the tile compute a sum nobody stores, from
+// addresses that the window test keeps inside frame j), so all B loads of a group
+// are in flight together.
 template <bool BLIND>
 __device__ __forceinline__ void pull_pixel(const PullEntry* __restrict__ pull, int k0, int k1,
                                            const float2* __restrict__ psi, const float2* __restrict__ ws,
-                                           int yi, int xi, int p, bool act, float2& num, double& den) {
+                                           int yi, int xi, int p, float2& num, double& den) {
   const int64_t pix = (int64_t)yi * p + xi;
-  int k = k0;
-  constexpr int B = 4;
-  for (; k + B <= k1; k += B) {
+  constexpr int B = 8;
+  for (int k = k0; k < k1; k += B) {
     PullEntry e[B];
     bool in[B];
     float2 ps[B], ww[B];
 #pragma unroll
+    for (int q = 0; q < B; ++q) e[q] = load_entry(pull + min(k + q, k1 - 1));
+#pragma unroll
     for (int q = 0; q < B; ++q) {
-      e[q] = pull[k + q];
       const int dy = yi - e[q].r, dx = xi - e[q].c;
-      in[q] = act && (unsigned)dy < (unsigned)p && (unsigned)dx < (unsigned)p;
+      in[q] = k + q < k1 && (unsigned)dy < (unsigned)p && (unsigned)dx < (unsigned)p;
       ps[q] = psi[in[q] ? e[q].base + pix : 0];
       if (BLIND) ww[q] = ws[in[q] ? dy * p + dx : 0];
     }
@@ -180,129 +201,142 @@ __device__ __forceinline__ void pull_pixel(const PullEntry* __restrict__ pull, i
       }
     }
   }
-  for (; k < k1; ++k) {
-    const PullEntry e = pull[k];
-    const int dy = yi - e.r, dx = xi - e.c;
-    const bool in = act && (unsigned)dy < (unsigned)p && (unsigned)dx < (unsigned)p;
-    const float2 ps = psi[in ? e.base + pix : 0];
-    if (BLIND) {
-      const float2 ww = ws[in ? dy * p + dx : 0];
-      num = in ? c_add(num, c_mulc(ps, ww)) : num;
-      den += in ? (double)ww.x * ww.x + (double)ww.y * ww.y : 0.0;
-    } else {
-      num = in ? c_add(num, ps) : num;
-    }
-  }
 }
 
-template <bool STATS, bool BLIND>
-__global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
-  __shared__ double red[4];
-  const int tile = blockIdx.x;
-  const TileDesc td = a.tiles[tile];
-  const CellDesc* cd = a.cells + td.cell;
-  const int m = cd->m, p = a.p;
+// log2 of the copy groups of a cell with m copies (m rounded up to a power of two)
+__device__ __forceinline__ int copy_groups_log2(int m) { return m <= 1 ? 0 : m <= 2 ? 1 : m <= 4 ? 2 : 3; }
+
+// UNI: every wavefront lies inside one copy group (m <= 4), so the copy index and
+// everything indexed by it are wavefront-uniform (scalar loads).
+template <bool STATS, bool BLIND, bool UNI>
+__device__ __forceinline__ void pixel_tile(const PixelArgs& a, int tile, const TileDesc& td, const CellDesc* cd,
+                                           int m, int lg, double (*red)[8]) {
+  const int p = a.p;
   const float r = cd->r;
-  const int tr = threadIdx.x / a.tile_cols, tc = threadIdx.x % a.tile_cols;
-  const bool act = tr < td.nr && tc < td.nc;
+  const int ppt = 256 >> lg;                     // tile pixels = threads per copy group
+  const int cw = min(a.tile_cols, ppt);          // tile width
+  const int q = threadIdx.x & (ppt - 1);
+  int s = threadIdx.x >> (8 - lg);
+  if (UNI) s = __builtin_amdgcn_readfirstlane(s);
+  const int tr = q / cw, tc = q % cw;
+  const bool act = s < m && tr < td.nr && tc < td.nc;
   const int y = td.r0 + tr, x = td.c0 + tc;
   const int yi = cd->r0 + y, xi = cd->c0 + x;  // image coordinates
+  const int sc = min(s, m - 1);                  // idle groups (s >= m) read slot m - 1's descriptors
 
-  float2 uo[MAXS], un[MAXS];
-  float2 acc[MAXS];
-  float rc[MAXS];
-  int64_t idx[MAXS];
+  // reads of the iterate n (own u, partners' u and both Lam of each pair), issued
+  // before the pull so their latency overlaps it
+  constexpr int NT = UNI ? 4 : MAXS;             // copies a cell can have on this path
+  const int64_t idx = cd->ubase[sc] + (int64_t)y * cd->upitch[sc] + x;
+  int64_t own[NT];
+  float2 uo = make_float2(0.f, 0.f);
+  float2 lo_[NT], lt_[NT], ut_[NT];
+  float rc = 0.0f;
 #pragma unroll
-  for (int s = 0; s < MAXS; ++s) {
-    if (s < m) {
-      // A_d*(z - Gamma) at this pixel: the covering frames of subdomain sub[s]
-      float2 num = make_float2(0.f, 0.f);
-      double den = 0.0;
-      const float2* ws = BLIND ? a.w_sub + (size_t)cd->sub[s] * p * p : nullptr;
-      pull_pixel<BLIND>(a.pull, a.tf_first[tile * MAXS + s], a.tf_first[tile * MAXS + s + 1], a.psi, ws,
-                        yi, xi, p, act, num, den);
-      if (act) {
-        idx[s] = cd->ubase[s] + (int64_t)y * cd->upitch[s] + x;
-        uo[s] = a.u[idx[s]];
-        acc[s] = c_add(c_scale(num, a.eta), c_scale(uo[s], a.gamma));
-        if (BLIND) {
-          const double q = (double)a.eta * den + (double)r * (double)(m - 1) + (double)a.gamma;
-          rc[s] = q == 0.0 ? 0.0f : (float)(1.0 / q);
-        } else {
-          rc[s] = a.rcp[idx[s]];
-        }
-      }
+  for (int t = 0; t < NT; ++t) {
+    const int lo = min(s, t), hi = max(s, t);
+    const int pq = hi > lo ? hi * (hi - 1) / 2 + lo : 0;
+    const int64_t li = cd->lbase[pq] + (int64_t)y * cd->lpitch[pq] + x, lj = li + cd->lstride[pq];
+    own[t] = s < t ? li : lj;
+    if (act && t < m && t != s) {
+      lo_[t] = a.lam[own[t]];
+      lt_[t] = a.lam[s < t ? lj : li];
+      ut_[t] = a.u[cd->ubase[t] + (int64_t)y * cd->upitch[t] + x];
     }
   }
   if (act) {
-#pragma unroll
-    for (int t = 1; t < MAXS; ++t) {
-#pragma unroll
-      for (int s = 0; s < t; ++s) {
-        if (t < m) {
-          const int q = t * (t - 1) / 2 + s;
-          const int64_t li = cd->lbase[q] + (int64_t)y * cd->lpitch[q] + x;
-          const float2 lab = a.lam[li], lba = a.lam[li + cd->lstride[q]];
-          const float2 v = c_scale(c_add(c_add(uo[s], uo[t]), c_add(lab, lba)), 0.5f);
-          acc[s] = c_add(acc[s], c_scale(c_sub(v, lab), r));
-          acc[t] = c_add(acc[t], c_scale(c_sub(v, lba), r));
-        }
-      }
+    uo = a.u[idx];
+    if (!BLIND) rc = a.rcp[idx];
+  }
+
+  // A_d*(z - Gamma) at this pixel: the covering frames of subdomain sub[s]
+  float2 num = make_float2(0.f, 0.f);
+  double den = 0.0;
+  const float2* ws = BLIND ? a.w_sub + (size_t)cd->sub[sc] * p * p : nullptr;
+  const int k0 = a.tf_first[tile * MAXS + s], k1 = a.tf_first[tile * MAXS + s + 1];
+  pull_pixel<BLIND>(a.pull, k0, k1, a.psi, ws, yi, xi, p, num, den);
+
+  float2 acc = uo, dv[NT];                       // dv = v_{s,t} - Lam_{s,t}
+  if (act) {
+    acc = c_add(c_scale(num, a.eta), c_scale(uo, a.gamma));
+    if (BLIND) {
+      const double qd = (double)a.eta * den + (double)r * (double)(m - 1) + (double)a.gamma;
+      rc = qd == 0.0 ? 0.0f : (float)(1.0 / qd);
     }
 #pragma unroll
-    for (int s = 0; s < MAXS; ++s) {
-      if (s < m) {
-        un[s] = rc[s] == 0.0f ? uo[s] : c_scale(acc[s], rc[s]);
-        a.u[idx[s]] = un[s];
-      }
-    }
-#pragma unroll
-    for (int t = 1; t < MAXS; ++t) {
-#pragma unroll
-      for (int s = 0; s < t; ++s) {
-        if (t < m) {
-          const int q = t * (t - 1) / 2 + s;
-          const int64_t li = cd->lbase[q] + (int64_t)y * cd->lpitch[q] + x;
-          const int64_t lj = li + cd->lstride[q];
-          const float2 lab = a.lam[li], lba = a.lam[lj];
-          const float2 v = c_scale(c_add(c_add(uo[s], uo[t]), c_add(lab, lba)), 0.5f);
-          a.lam[li] = c_add(lab, c_sub(un[s], v));
-          a.lam[lj] = c_add(lba, c_sub(un[t], v));
-        }
+    for (int t = 0; t < NT; ++t) {
+      dv[t] = make_float2(0.f, 0.f);
+      if (t < m && t != s) {
+        const float2 v = c_scale(c_add(c_add(uo, ut_[t]), c_add(lo_[t], lt_[t])), 0.5f);
+        dv[t] = c_sub(v, lo_[t]);
+        acc = c_add(acc, c_scale(dv[t], r));
       }
     }
   }
-  if (STATS) {
+  __syncthreads();  // every copy's reads of u^n and Lam^n precede the writes below
+  float2 un = uo;
+  if (act) {
+    un = rc == 0.0f ? uo : c_scale(acc, rc);
+    a.u[idx] = un;
 #pragma unroll
-    for (int s = 0; s < MAXS; ++s) {
-      if (s < m) {  // m is uniform: every thread takes part in the reductions
-        double du = 0.0, uu = 0.0;
-        if (act) {
-          const double dx = (double)un[s].x - uo[s].x, dy = (double)un[s].y - uo[s].y;
-          du = dx * dx + dy * dy;
-          uu = (double)un[s].x * un[s].x + (double)un[s].y * un[s].y;
-        }
-        du = block_sum<256>(du, red);
-        uu = block_sum<256>(uu, red);
-        if (threadIdx.x == 0) {
-          a.part[((size_t)tile * MAXS + s) * 2] = du;
-          a.part[((size_t)tile * MAXS + s) * 2 + 1] = uu;
-        }
+    for (int t = 0; t < NT; ++t)
+      if (t < m && t != s) a.lam[own[t]] = c_sub(un, dv[t]);   // Lam + u^{n+1} - v
+  }
+  if (STATS) {
+    // per copy group: (|du|^2, |u|^2), reduced in a fixed order
+    double du = 0.0, uu = 0.0;
+    if (act) {
+      const double ex = (double)un.x - uo.x, ey = (double)un.y - uo.y;
+      du = ex * ex + ey * ey;
+      uu = (double)un.x * un.x + (double)un.y * un.y;
+    }
+    const int g = min(ppt, 64);                  // lanes of one group inside a wavefront
+    for (int o = g >> 1; o > 0; o >>= 1) {
+      du += __shfl_xor(du, o, 64);
+      uu += __shfl_xor(uu, o, 64);
+    }
+    const int chunk = threadIdx.x / g;           // 256 / g <= 8 chunks, ppt / g per group
+    if ((threadIdx.x & (g - 1)) == 0) {
+      red[0][chunk] = du;
+      red[1][chunk] = uu;
+    }
+    __syncthreads();
+    if (threadIdx.x < MAXS && (int)threadIdx.x < m) {
+      const int per = ppt / g;
+      double a0 = 0.0, a1 = 0.0;
+      for (int c = threadIdx.x * per; c < (int)(threadIdx.x + 1) * per; ++c) {
+        a0 += red[0][c];
+        a1 += red[1][c];
       }
+      a.part[((size_t)tile * MAXS + threadIdx.x) * 2] = a0;
+      a.part[((size_t)tile * MAXS + threadIdx.x) * 2 + 1] = a1;
     }
   }
 }
 
+// UNI: tiles [0, n_uni) (at most four copies per pixel); otherwise the rest
+template <bool STATS, bool BLIND, bool UNI>
+__global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
+  __shared__ double red[2][8];
+  const int tile = UNI ? blockIdx.x : a.n_uni + blockIdx.x;
+  const TileDesc td = a.tiles[tile];
+  const CellDesc* cd = a.cells + td.cell;
+  pixel_tile<STATS, BLIND, UNI>(a, tile, td, cd, cd->m, copy_groups_log2(cd->m), red);
+}
+
 hipError_t launch_pixel(const PixelArgs& a, bool stats, bool blind, hipStream_t s) {
-  if (a.n_tiles == 0) return hipSuccess;
-  const dim3 g(a.n_tiles), b(256);
+  const dim3 b(256);
+#define ODP_PIXEL(ST, BL)                                                                            \
+  if (a.n_uni > 0) hipLaunchKernelGGL((k_pixel<ST, BL, true>), dim3(a.n_uni), b, 0, s, a);          \
+  if (a.n_tiles > a.n_uni) hipLaunchKernelGGL((k_pixel<ST, BL, false>), dim3(a.n_tiles - a.n_uni), b, 0, s, a);
   if (blind) {
-    if (stats) hipLaunchKernelGGL((k_pixel<true, true>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_pixel<false, true>), g, b, 0, s, a);
+    if (stats) { ODP_PIXEL(true, true) }
+    else { ODP_PIXEL(false, true) }
   } else {
-    if (stats) hipLaunchKernelGGL((k_pixel<true, false>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_pixel<false, false>), g, b, 0, s, a);
+    if (stats) { ODP_PIXEL(true, false) }
+    else { ODP_PIXEL(false, false) }
   }
+#undef ODP_PIXEL
   return hipGetLastError();
 }
 

@@ -79,6 +79,7 @@ struct PixelArgs {
   const CellDesc* cells;
   const TileDesc* tiles;
   int32_t n_tiles, p, tile_cols;
+  int32_t n_uni;             // tiles [0, n_uni) belong to cells with at most 4 copies
   const float2* psi;         // per-frame outputs of the sweep
   const int32_t* tf_first;   // [n_tiles*MAXS + 1]: frames of slot s overlapping tile t
   const PullEntry* pull;     // their records, ascending frame id

@@ -81,7 +81,8 @@ struct odp_plan {
   // pixel-update tilings (the autotuner picks one); the active one is tsets[ts]
   struct TileSet {
     int rows = 0, cols = 0;
-    std::vector<TileDesc> tiles;
+    std::vector<TileDesc> tiles;             // cells with m <= 4 first: tiles [0, n_uni)
+    int32_t n_uni = 0;
     std::vector<int32_t> re_list, re_first;  // (tile, slot) entries per subdomain, for RE
     std::vector<int32_t> tf_first;           // per (tile, slot): range of pull records
     std::vector<PullEntry> pull;             // frames whose window meets the tile, ascending id
@@ -121,28 +122,40 @@ struct odp_plan {
 
 namespace {
 
-// Cut every cell into rows x cols tiles (rows * cols = 256) and list, per (tile,
-// subdomain slot), the slot's frames whose window meets the tile (ascending id).
+// Cut every cell into tiles and list, per (tile, subdomain slot), the slot's frames
+// whose window meets the tile (ascending id).  A cell with m copies per pixel gets
+// tiles of 256 / m' pixels (m' = m rounded up to a power of two), so one workgroup
+// of 256 threads holds every copy of its pixels: width min(cols, 256 / m'), height
+// the rest (rows x cols = 256 is the shape for m = 1).
 void build_tiles(const odp_plan* P, int rows, int cols, odp_plan::TileSet& T) {
   const int p = P->p, D = P->D;
   T.rows = rows;
   T.cols = cols;
   T.tiles.clear();
-  for (size_t c = 0; c < P->cells.size(); ++c) {
-    const CellDesc& cd = P->cells[c];
-    const int r1 = *std::upper_bound(P->cuts_r.begin(), P->cuts_r.end(), cd.r0);
-    const int c1 = *std::upper_bound(P->cuts_c.begin(), P->cuts_c.end(), cd.c0);
-    for (int ty = 0; ty < r1 - cd.r0; ty += rows)
-      for (int tx = 0; tx < c1 - cd.c0; tx += cols) {
-        TileDesc td;
-        std::memset(&td, 0, sizeof(td));
-        td.cell = (int32_t)c;
-        td.r0 = ty;
-        td.c0 = tx;
-        td.nr = std::min(rows, r1 - cd.r0 - ty);
-        td.nc = std::min(cols, c1 - cd.c0 - tx);
-        T.tiles.push_back(td);
-      }
+  // cells with up to four copies first (their pixel kernel runs with wavefront-uniform
+  // copy indices), then the rest
+  for (int pass = 0; pass < 2; ++pass) {
+    for (size_t c = 0; c < P->cells.size(); ++c) {
+      const CellDesc& cd = P->cells[c];
+      if ((cd.m > 4) != (pass == 1)) continue;
+      int groups = 1;
+      while (groups < cd.m) groups *= 2;
+      const int ppt = rows * cols / groups, tw = std::min(cols, ppt), th = ppt / tw;
+      const int r1 = *std::upper_bound(P->cuts_r.begin(), P->cuts_r.end(), cd.r0);
+      const int c1 = *std::upper_bound(P->cuts_c.begin(), P->cuts_c.end(), cd.c0);
+      for (int ty = 0; ty < r1 - cd.r0; ty += th)
+        for (int tx = 0; tx < c1 - cd.c0; tx += tw) {
+          TileDesc td;
+          std::memset(&td, 0, sizeof(td));
+          td.cell = (int32_t)c;
+          td.r0 = ty;
+          td.c0 = tx;
+          td.nr = std::min(th, r1 - cd.r0 - ty);
+          td.nc = std::min(tw, c1 - cd.c0 - tx);
+          T.tiles.push_back(td);
+        }
+    }
+    if (pass == 0) T.n_uni = (int32_t)T.tiles.size();
   }
   std::vector<std::vector<int32_t>> per(D);
   for (size_t t = 0; t < T.tiles.size(); ++t) {
@@ -808,6 +821,7 @@ static PixelArgs pixel_args(const odp_plan* P, char* b, double* stats) {
   a.cells = P->W_<CellDesc>(P->ws.cells);
   a.tiles = P->W_<TileDesc>(P->ws.tiles);
   a.n_tiles = (int32_t)P->tset().tiles.size();
+  a.n_uni = P->tset().n_uni;
   a.p = P->p;
   a.tile_cols = P->tset().cols;
   a.psi = P->W_<float2>(P->ws.psi);

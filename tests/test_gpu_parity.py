@@ -14,6 +14,7 @@ import torch
 import synthetic
 import paper_2011_00162_amd as odp
 from oracle import operators as ops, stagm
+from oracle.geometry import build_geometry
 from oracle.od2p import init_state, merge, od2pm_run, od2pm_step, subdomain_illumination
 from tests.gpu_util import (dev_c64, dev_f32, gpu_plan, host, oracle_to_state, rel, rel_list,
                             rounded_inputs, state_to_oracle)
@@ -149,6 +150,44 @@ def test_one_iteration_from_random_state(name, spec, eta):
     assert abs(s[0] - ostats["RF"]) <= 1e-5 * ostats["RF"]
     assert abs(s[1] - ostats["RE"]) <= 1e-4 * ostats["RE"]
     assert abs(s[2] - ostats["G"]) <= 1e-5 * ostats["G"]
+
+
+def _interleaved(P, D, eta):
+    """Frame j goes to subdomain j mod D: every subdomain spans the image, so a pixel
+    lies in up to D subdomains (D = 3 leaves an idle copy group of four, D > 4 takes
+    the path for five to eight copies)."""
+    pr = P["pr"]
+    spec = pr["spec"]
+    pr["frame_sub"] = (np.arange(len(pr["offsets"])) % D).astype(np.int32)
+    g = build_geometry(spec.n, spec.n, spec.p, pr["offsets"], pr["frame_sub"])
+    P["geom"] = g
+    P["den"] = [subdomain_illumination(g, pr["w"], d) for d in range(g.D)]
+    P["r"] = 0.5 * eta * max(float(a.max()) for a in P["den"])
+    return P
+
+
+@pytest.mark.parametrize("D", [3, 5, 8])
+def test_one_iteration_many_copies(D):
+    say("one iteration, interleaved subdomains", D)
+    eta = 0.3
+    P = _interleaved(oracle_problem(tiny_spec(n=96, p=32, step=8, jitter=1, radius=12, peak=1e4), eta=eta), D, eta)
+    g = P["geom"]
+    w, _, f = rounded_inputs(P)
+    plan = gpu_plan(P)
+    assert plan.info.max_cover == D
+    st = plan.new_state()
+    rng = np.random.default_rng(D)
+    ost = init_state(g)
+    ost.u = [(1 + 0.3 * (rng.standard_normal(a.shape) + 1j * rng.standard_normal(a.shape))).astype(np.complex64).astype(np.complex128) for a in ost.u]
+    ost.lam = {k: (0.1 * (rng.standard_normal(v.shape) + 1j * rng.standard_normal(v.shape))).astype(np.complex64).astype(np.complex128) for k, v in ost.lam.items()}
+    oracle_to_state(ost, st)
+    stats = host(plan.iterate(st, 2, stats=True))
+    new, h = od2pm_run(g, w, f, P["eps"], eta, P["r"], 2, state=ost)
+    got = state_to_oracle(st)
+    e = dict(u=rel_list(got.u, new.u), gamma=rel(got.gamma, new.gamma),
+             lam=max(rel(got.lam[k], new.lam[k]) for k in new.lam))
+    assert max(e.values()) <= 1e-5, e
+    np.testing.assert_allclose(stats[:, 1], [x["RE"] for x in h], rtol=1e-4)
 
 
 # ---------------------------------------------------------------------------
