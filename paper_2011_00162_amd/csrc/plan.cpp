@@ -330,7 +330,8 @@ int build_geometry(odp_plan* P) {
       P->tw[i * 16 + k] = make_float2((float)std::cos(a), (float)-std::sin(a));
     }
   // split-BF16 DFT matrix F[k][n] = exp(-2 pi i k n / p) / sqrt(p), FP64 on the host:
-  // hi = bf16(F), lo = bf16(F - hi)
+  // hi = bf16(F), lo = bf16(F - hi).  Columns are stored in the MFMA kernel's
+  // contraction order: n = 16t + 4g + i sits at 32(t/2) + 8g + 4(t%2) + i.
   if (p == 64) {  // the autotuner may switch a p = 64 plan between the two transforms
     const size_t pp = (size_t)p * p;
     P->dft.assign(4 * pp, 0);
@@ -339,7 +340,8 @@ int build_geometry(odp_plan* P) {
       for (int n = 0; n < p; ++n) {
         const double a = 2.0 * M_PI * (double)((k * n) % p) / (double)p;
         const double re = s * std::cos(a), im = -s * std::sin(a);
-        const size_t o = (size_t)k * p + n;
+        const int nt = n >> 4, ng = (n >> 2) & 3, ni = n & 3;
+        const size_t o = (size_t)k * p + 32 * (nt >> 1) + 8 * ng + 4 * (nt & 1) + ni;
         const uint16_t rh = bf16_rne((float)re), ih = bf16_rne((float)im);
         P->dft[o] = rh;
         P->dft[pp + o] = bf16_rne((float)(re - bf16_value(rh)));
