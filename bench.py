@@ -26,8 +26,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ADMM frame-iters/s (FP32 FFT vs split-BF16 MFMA DFT) at fixed rel. error"
 HBM_PEAK_GBS = 8000.0
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+DFT_FLOPS_PER_FRAME = 4 * 4 * 3 * 2 * 64 ** 3     # per frame-iteration of the split-BF16 DFT sweep
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_sweep_c2_pmc.md")
-KERNEL_SOURCES = ["paper_2011_00162_amd/csrc/kernels.hip", "paper_2011_00162_amd/csrc/fft_frame.hpp"]
+KERNEL_SOURCES = ["paper_2011_00162_amd/csrc/kernels.hip", "paper_2011_00162_amd/csrc/fft_frame.hpp",
+                  "paper_2011_00162_amd/csrc/prox.hpp", "paper_2011_00162_amd/csrc/odp_internal.hpp"]
 
 
 def kernel_hash() -> str:
@@ -92,23 +95,24 @@ def gpu_leg(args, torch, odp, synthetic, transform=0):
     info = plan.info
 
     plan.iterate(state, args.warmup)
+    # event pairs recorded by the sweep kernel itself at its start and end
+    # (hipExtLaunchKernelGGL on the launch stream) on every stride-th iteration of the
+    # timed region (each recording costs a few microseconds of serialisation, so about 20
+    # samples are taken); record() once here only creates the events
+    stride = max(1, args.steps // 20)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps // stride)]
+    for a, b in ev:
+        a.record()
+        b.record()
     torch.cuda.synchronize()
+    plan.set_sweep_events(ev, stride)
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0.record()
-    plan.iterate(state, args.steps)
+    plan.iterate(state, args.steps)     # the timed region: K iterations (sweep, pixel update)
     t1.record()
     torch.cuda.synchronize()
     total_ms = t0.elapsed_time(t1)
-
-    # per-kernel timing of the frame sweep, events on the launch stream
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    for a, b in ev:
-        a.record()
-        plan.frame_sweep(state)
-        b.record()
-        plan.pixel_update(state)
-    torch.cuda.synchronize()
     sweep_ms = sorted(a.elapsed_time(b) for a, b in ev)
     sweep_avg_ms = sum(sweep_ms) / len(sweep_ms)
     alg_bytes = 20.0 * J * p * p + 16.0 * info.p_sub
@@ -241,13 +245,23 @@ def run_c4(args, torch, odp, synthetic):
         plan.set_penalties([0.5 * eta * plan.entry(i).illum_max for i in range(len(group))])
         scratch = plan.new_state()
         t = plan.autotune(scratch, iters=3)
+        # both frame transforms at the tuned order and tiling (the DFT path exists for p = 64)
+        per_transform = {}
+        for name, tr in (("fft_f32", odp.ODP_FFT_F32), ("dft_split_bf16", odp.ODP_DFT_SPLIT_BF16)):
+            if tr == odp.ODP_DFT_SPLIT_BF16 and p != 64:
+                continue
+            plan.set_tuning(tr, t.xcd_slice, t.tiling)
+            plan.iterate(scratch, 2)
+            per_transform[name] = _timed(torch, lambda: plan.iterate(scratch, 1), 10)
+        plan.set_tuning(t.transform, t.xcd_slice, t.tiling)
         del scratch
         plans.append(plan)
         states.append(plan.new_state())
         total_frames += plan.info.J
         info[f"p{p}"] = {"problems": len(group), "frames": plan.info.J, "subdomains": plan.info.D,
                          "tuning": {"transform": t.transform, "xcd_slice": t.xcd_slice,
-                                    "tile": [t.tile_rows, t.tile_cols], "ms_per_iter": t.ms_per_iter}}
+                                    "tile": [t.tile_rows, t.tile_cols], "ms_per_iter": t.ms_per_iter},
+                         "ms_per_iter_by_transform": per_transform}
     K = 100
     g = odp.Graph(plans, states, K)
     g.launch()                          # warm-up replay
@@ -370,9 +384,14 @@ def main() -> int:
         },
         "transforms": {
             "fft_f32": {"value": value, "ms_per_step": ms_per_step, "sweep_ms": g["sweep_avg_ms"]},
-            "dft_split_bf16": {"value": gd["J"] * args.steps / (gd["total_ms"] / 1e3),
-                               "ms_per_step": gd["total_ms"] / args.steps, "sweep_ms": gd["sweep_avg_ms"],
-                               "sweep_mfma_tflops": 96.0 * 64 ** 3 * gd["J"] / (gd["sweep_avg_ms"] / 1e3) / 1e12},
+            "dft_split_bf16": {
+                "value": gd["J"] * args.steps / (gd["total_ms"] / 1e3),
+                "ms_per_step": gd["total_ms"] / args.steps, "sweep_ms": gd["sweep_avg_ms"],
+                # 4 complex 64^3 products per frame, each 4 real products in 3 split terms
+                "sweep_roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": BF16_MFMA_PEAK_TFLOPS,
+                                   "achieved": DFT_FLOPS_PER_FRAME * gd["J"] / (gd["sweep_avg_ms"] / 1e3) / 1e12,
+                                   "frac": DFT_FLOPS_PER_FRAME * gd["J"] / (gd["sweep_avg_ms"] / 1e3) / 1e12
+                                   / BF16_MFMA_PEAK_TFLOPS}},
         },
         "roofline": {
             "bound": "hbm",

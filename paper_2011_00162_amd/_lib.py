@@ -23,6 +23,7 @@ EXPORTS = [
     "odp_pixel_update", "odp_merge", "odp_amp_loss", "odp_last_error", "odp_version",
     "odp_batch_plan_create", "odp_batch_get_entry", "odp_batch_set_penalties", "odp_plan_get_tuning",
     "odp_plan_set_tuning", "odp_plan_autotune", "odp_graph_create", "odp_graph_launch", "odp_graph_destroy",
+    "odp_plan_set_sweep_events",
 ]
 
 
@@ -93,6 +94,7 @@ def lib() -> C.CDLL:
         "odp_state_init": (C.c_int, [vp, vp, vp, vp]),
         "odp_admm_iterate": (C.c_int, [vp, vp, i32, vp, vp]),
         "odp_frame_sweep": (C.c_int, [vp, vp, vp, vp]),
+        "odp_plan_set_sweep_events": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), i32, i32]),
         "odp_probe_update": (C.c_int, [vp, vp, vp]),
         "odp_pixel_update": (C.c_int, [vp, vp, vp, vp]),
         "odp_merge": (C.c_int, [vp, vp, vp, vp]),

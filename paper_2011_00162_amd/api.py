@@ -276,6 +276,16 @@ class Plan:
         check(lib().odp_admm_iterate(self._h, _ptr(state.buf), int(n_iter), _ptr(st), _stream(stream)))
         return st
 
+    def set_sweep_events(self, events, stride: int = 1) -> None:
+        """events: list of (start, stop) torch.cuda.Event(enable_timing=True), each recorded
+        once beforehand (which creates it); of the next len(events)*stride sweeps, sweep
+        i*stride records pair i at its kernel's own start and end, so elapsed_time gives
+        the kernel time."""
+        n = len(events)
+        s = (C.c_void_p * max(n, 1))(*[e[0].cuda_event for e in events])
+        t = (C.c_void_p * max(n, 1))(*[e[1].cuda_event for e in events])
+        check(lib().odp_plan_set_sweep_events(self._h, s, t, n, int(stride)))
+
     def frame_sweep(self, state: State, stats: torch.Tensor | None = None, stream=None) -> None:
         check(lib().odp_frame_sweep(self._h, _ptr(state.buf), _ptr(stats), _stream(stream)))
 

@@ -35,6 +35,7 @@
 //   psi_j = conj(w) o x
 // Both exchanges use 8- or 16-byte LDS accesses.  The F table (32 KB of split
 // planes, columns in the pi order) is copied into LDS once per workgroup.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -372,7 +373,8 @@ __global__ __launch_bounds__(256, WGS_PER_CU) void k_sweep_dft64(SweepArgs a, Df
   }
 }
 
-hipError_t launch_sweep_dft(int p, const SweepArgs& a, const DftTable& dt, hipStream_t s) {
+hipError_t launch_sweep_dft(int p, const SweepArgs& a, const DftTable& dt, hipStream_t s, hipEvent_t ev0,
+                            hipEvent_t ev1) {
   if (p != DP) return hipErrorInvalidValue;
   if (a.J == 0) return hipSuccess;
   const ProxC pc = prox_coeffs(a.eps, a.eta);
@@ -381,10 +383,10 @@ hipError_t launch_sweep_dft(int p, const SweepArgs& a, const DftTable& dt, hipSt
   const int G = a.xcd_slice ? NXCD * std::min(MAXG / NXCD, (int)a.chunk) : std::min(MAXG, (int)a.J);
   const dim3 grid(G), blk(256);
   const bool st = a.part != nullptr, bl = a.blind != 0;
-  if (bl && st) hipLaunchKernelGGL((k_sweep_dft64<true, true>), grid, blk, 0, s, a, dt, pc);
-  else if (bl) hipLaunchKernelGGL((k_sweep_dft64<true, false>), grid, blk, 0, s, a, dt, pc);
-  else if (st) hipLaunchKernelGGL((k_sweep_dft64<false, true>), grid, blk, 0, s, a, dt, pc);
-  else hipLaunchKernelGGL((k_sweep_dft64<false, false>), grid, blk, 0, s, a, dt, pc);
+  if (bl && st) hipExtLaunchKernelGGL((k_sweep_dft64<true, true>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
+  else if (bl) hipExtLaunchKernelGGL((k_sweep_dft64<true, false>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
+  else if (st) hipExtLaunchKernelGGL((k_sweep_dft64<false, true>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
+  else hipExtLaunchKernelGGL((k_sweep_dft64<false, false>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
   return hipGetLastError();
 }
 

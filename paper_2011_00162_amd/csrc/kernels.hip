@@ -5,6 +5,7 @@
 // kernels run one 256-thread workgroup per 256-pixel tile of a cell (a rectangle
 // covered by one fixed set of subdomains), so every descriptor load is uniform.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include "fft_frame.hpp"
 #include "odp_internal.hpp"
@@ -54,11 +55,17 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
   const int col = F::a_col(t), r2 = F::a_r2(t);
   const float inv_p = 1.0f / (float)P;
 
-  float2 v[16];
+  // The inverse transform returns each thread's 16 points to the positions it
+  // gathered, so at P = 32 the probe values stay in registers for the output
+  // multiply (for larger P the 32 registers would cost occupancy; they are read again).
+  constexpr bool KEEPW = !BLIND && P <= 32;
+  float2 v[16], wk[16];
 #pragma unroll
   for (int r1 = 0; r1 < 16; ++r1) {
     const int row = F::N2 * r1 + r2;
-    v[r1] = c_mul(a.u[fd.base + (int64_t)row * fd.pitch + col], w[row * P + col]);
+    const float2 wr = w[row * P + col];
+    if (KEEPW) wk[r1] = wr;
+    v[r1] = c_mul(a.u[fd.base + (int64_t)row * fd.pitch + col], wr);
   }
   F::forward_a(v, lds, a.tw, t);
   // The thread's amplitudes (and, for P <= 64, multipliers) are fetched now, while
@@ -110,27 +117,29 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
 #pragma unroll
   for (int r1 = 0; r1 < 16; ++r1) {
     const int row = F::N2 * r1 + r2;
-    a.psi[fbase + row * P + col] = BLIND ? v[r1] : c_mulc(v[r1], wo[row * P + col]);
+    a.psi[fbase + row * P + col] = BLIND ? v[r1] : c_mulc(v[r1], KEEPW ? wk[r1] : wo[row * P + col]);
   }
 }
 
-hipError_t launch_sweep(int p, const SweepArgs& a, hipStream_t s) {
+hipError_t launch_sweep(int p, const SweepArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const ProxC pc = prox_coeffs(a.eps, a.eta);
   const dim3 grid(NXCD * a.chunk);
   const bool st = a.part != nullptr, bl = a.blind != 0;
+#define ODP_SWEEP_GO(K, T) hipExtLaunchKernelGGL(K, grid, dim3(T), 0, s, ev0, ev1, 0, a, pc)
 #define ODP_SWEEP(PP)                                                                        \
   if (p == PP) {                                                                             \
     constexpr int T = Frame<PP>::T;                                                          \
-    if (bl && st) hipLaunchKernelGGL((k_sweep<PP, true, true>), grid, dim3(T), 0, s, a, pc);   \
-    else if (bl) hipLaunchKernelGGL((k_sweep<PP, true, false>), grid, dim3(T), 0, s, a, pc);   \
-    else if (st) hipLaunchKernelGGL((k_sweep<PP, false, true>), grid, dim3(T), 0, s, a, pc);   \
-    else hipLaunchKernelGGL((k_sweep<PP, false, false>), grid, dim3(T), 0, s, a, pc);          \
+    if (bl && st) ODP_SWEEP_GO((k_sweep<PP, true, true>), T);                                \
+    else if (bl) ODP_SWEEP_GO((k_sweep<PP, true, false>), T);                                \
+    else if (st) ODP_SWEEP_GO((k_sweep<PP, false, true>), T);                                \
+    else ODP_SWEEP_GO((k_sweep<PP, false, false>), T);                                       \
     return hipGetLastError();                                                                \
   }
   ODP_SWEEP(32)
   ODP_SWEEP(64)
   ODP_SWEEP(128)
 #undef ODP_SWEEP
+#undef ODP_SWEEP_GO
   return hipErrorInvalidValue;
 }
 

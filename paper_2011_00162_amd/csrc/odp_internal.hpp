@@ -101,14 +101,16 @@ struct IllumArgs {           // den and rcp on every subdomain pixel
   int recompute_den;         // 0: reuse den, only rebuild rcp
 };
 
-hipError_t launch_sweep(int p, const SweepArgs& a, hipStream_t s);
+hipError_t launch_sweep(int p, const SweepArgs& a, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Split-BF16 DFT matrix for the MFMA sweep: planes [re hi, re lo, im hi, im lo] of
 // F[k][n] = exp(-2 pi i k n / p) / sqrt(p), each [p][p] bf16 bit patterns.
 struct DftTable {
   const uint16_t* f;
 };
-hipError_t launch_sweep_dft(int p, const SweepArgs& a, const DftTable& dt, hipStream_t s);
+// ev0/ev1: if non-null, recorded at the kernel's start and end (hipExtLaunchKernelGGL)
+hipError_t launch_sweep_dft(int p, const SweepArgs& a, const DftTable& dt, hipStream_t s, hipEvent_t ev0 = nullptr,
+                            hipEvent_t ev1 = nullptr);
 hipError_t launch_pixel(const PixelArgs& a, bool stats, bool blind, hipStream_t s);
 hipError_t launch_illum(const IllumArgs& a, hipStream_t s);
 hipError_t launch_forward(int p, const float2* u, int H, int W, const float2* w, const float2* tw,

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "odp.h"
@@ -90,6 +91,8 @@ struct odp_plan {
   TileSet tsets[3];
   int ts = 0;
   int32_t xcd_slice = 1;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> sweep_ev;   // kernel timing of the next sweeps
+  size_t sweep_ev_next = 0, sweep_ev_stride = 1;
   // problems of a batch (one entry for a single problem)
   struct Entry {
     int32_t row0, col0, H, W, J0, J, D0, D;
@@ -847,11 +850,38 @@ int odp_frame_sweep(odp_plan* P, void* dev_state, double* dev_stats, hipStream_t
   if (!P || !dev_state) return fail(ODP_EINVAL, "null argument");
   if (!P->wsp) return fail(ODP_EINVAL, "plan is not bound");
   const SweepArgs a = sweep_args(P, static_cast<char*>(dev_state), dev_stats);
-  if (P->transform == ODP_DFT_SPLIT_BF16) {
-    ODP_HIP(launch_sweep_dft(P->p, a, DftTable{P->W_<uint16_t>(P->ws.dft)}, s));
-  } else {
-    ODP_HIP(launch_sweep(P->p, a, s));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!P->sweep_ev.empty()) {
+    const size_t c = P->sweep_ev_next++;
+    if (c % P->sweep_ev_stride == 0) {
+      e0 = P->sweep_ev[c / P->sweep_ev_stride].first;
+      e1 = P->sweep_ev[c / P->sweep_ev_stride].second;
+    }
+    if (P->sweep_ev_next == P->sweep_ev.size() * P->sweep_ev_stride) {
+      P->sweep_ev.clear();
+      P->sweep_ev_next = 0;
+    }
   }
+  if (P->transform == ODP_DFT_SPLIT_BF16) {
+    ODP_HIP(launch_sweep_dft(P->p, a, DftTable{P->W_<uint16_t>(P->ws.dft)}, s, e0, e1));
+  } else {
+    ODP_HIP(launch_sweep(P->p, a, s, e0, e1));
+  }
+  return ODP_OK;
+}
+
+int odp_plan_set_sweep_events(odp_plan* P, const hipEvent_t* start, const hipEvent_t* stop, int32_t n,
+                              int32_t stride) {
+  if (!P) return fail(ODP_EINVAL, "null argument");
+  if (n < 0) return fail(ODP_EINVAL, "negative event count");
+  if (stride < 1) return fail(ODP_EINVAL, "stride must be at least 1");
+  if (n > 0 && (!start || !stop)) return fail(ODP_EINVAL, "null event array");
+  for (int32_t i = 0; i < n; ++i)
+    if (!start[i] || !stop[i]) return fail(ODP_EINVAL, "null event");
+  P->sweep_ev.clear();
+  for (int32_t i = 0; i < n; ++i) P->sweep_ev.emplace_back(start[i], stop[i]);
+  P->sweep_ev_next = 0;
+  P->sweep_ev_stride = (size_t)stride;
   return ODP_OK;
 }
 
@@ -1050,18 +1080,57 @@ int odp_graph_create(odp_plan* const* plans, void* const* states, int32_t n, int
   *out = nullptr;
   for (int i = 0; i < n; ++i)
     if (!plans[i] || !states[i] || !plans[i]->wsp) return fail(ODP_EINVAL, "unbound plan or null state");
-  hipStream_t cs;
-  ODP_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  // One capture stream forks into one stream per distinct plan (pairs of one plan share
+  // its workspace and stay on one branch, in the given order): distinct plans touch
+  // disjoint memory, so the graph holds independent chains of n_iter iterations that the
+  // runtime may run side by side, joined at the end.
+  std::vector<int> branch(n);
+  int nb = 0;
+  for (int i = 0; i < n; ++i) {
+    branch[i] = -1;
+    for (int k = 0; k < i; ++k) {
+      if (plans[k] == plans[i]) branch[i] = branch[k];
+      else if (states[k] == states[i]) return fail(ODP_EINVAL, "two plans share one state");
+      if (states[k] == states[i] && plans[k] == plans[i]) return fail(ODP_EINVAL, "repeated (plan, state) pair");
+    }
+    if (branch[i] < 0) branch[i] = nb++;
+  }
+  std::vector<hipStream_t> ss(nb + 1, nullptr);
+  std::vector<hipEvent_t> ev(nb + 1, nullptr);
+  auto cleanup = [&]() {
+    for (hipEvent_t e : ev)
+      if (e) hipEventDestroy(e);
+    for (hipStream_t q : ss)
+      if (q) hipStreamDestroy(q);
+  };
+  for (int b = 0; b <= nb; ++b) {
+    if (hipStreamCreateWithFlags(&ss[b], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ev[b], hipEventDisableTiming) != hipSuccess) {
+      cleanup();
+      return fail(ODP_EHIP, "stream or event creation failed");
+    }
+  }
+  hipStream_t cs = ss[nb];
   int rc = ODP_OK;
   if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-    hipStreamDestroy(cs);
+    cleanup();
     return fail(ODP_EHIP, "hipStreamBeginCapture failed");
   }
-  for (int it = 0; it < n_iter && !rc; ++it)
-    for (int i = 0; i < n && !rc; ++i) rc = odp_admm_iterate(plans[i], states[i], 1, nullptr, cs);
+  if (hipEventRecord(ev[nb], cs) != hipSuccess) rc = fail(ODP_EHIP, "fork event failed");
+  for (int b = 0; b < nb && !rc; ++b) {
+    if (hipStreamWaitEvent(ss[b], ev[nb], 0) != hipSuccess) {
+      rc = fail(ODP_EHIP, "fork wait failed");
+      break;
+    }
+    for (int it = 0; it < n_iter && !rc; ++it)
+      for (int i = 0; i < n && !rc; ++i)
+        if (branch[i] == b) rc = odp_admm_iterate(plans[i], states[i], 1, nullptr, ss[b]);
+    if (!rc && (hipEventRecord(ev[b], ss[b]) != hipSuccess || hipStreamWaitEvent(cs, ev[b], 0) != hipSuccess))
+      rc = fail(ODP_EHIP, "join failed");
+  }
   hipGraph_t g = nullptr;
   const hipError_t ec = hipStreamEndCapture(cs, &g);
-  hipStreamDestroy(cs);
+  cleanup();
   if (rc) {
     if (g) hipGraphDestroy(g);
     return rc;

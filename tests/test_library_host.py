@@ -147,3 +147,17 @@ def test_batch_rejects_mixed_probe_sizes():
     probs = [dict(H=s.n, W=s.n, p=s.p, offsets=pr["offsets"], frame_sub=pr["frame_sub"], r=1.0) for s, pr in items]
     with pytest.raises(OdpError):
         odp.Plan.batch(probs)
+
+
+def test_sweep_event_arguments_are_checked():
+    import ctypes as C
+    plan = odp.Plan(**_plan_args())
+    L = odp.lib()
+    one = (C.c_void_p * 1)(C.c_void_p(0x1000))
+    nul = (C.c_void_p * 1)(None)
+    assert L.odp_plan_set_sweep_events(plan._h, None, None, 0, 1) == 0          # cancel
+    assert L.odp_plan_set_sweep_events(plan._h, None, None, -1, 1) == ODP_EINVAL
+    assert L.odp_plan_set_sweep_events(plan._h, one, one, 1, 0) == ODP_EINVAL   # stride < 1
+    assert L.odp_plan_set_sweep_events(plan._h, None, one, 1, 1) == ODP_EINVAL  # null array
+    assert L.odp_plan_set_sweep_events(plan._h, nul, one, 1, 1) == ODP_EINVAL   # null event
+    assert L.odp_plan_set_sweep_events(plan._h, None, None, 0, 1) == 0
