@@ -6,7 +6,8 @@
 //  Delta_d^{n+1} = Delta_d^n + w_d^{n+1} - w^{n+1}                     (eq. admm_Delta)
 // with phi_j = F^{-1}(Z_j - Gamma_j) from the frame sweep and P_O = F^{-1} M F the
 // projection onto probes whose spectrum vanishes off the support mask M.
-// The frame sums run in FP64 over each subdomain's frames in ascending order.
+// The frame sums run in FP64 in a fixed order (four interleaved ascending partial
+// sums per subdomain, added in order), so repeated runs agree bit for bit.
 #include <hip/hip_runtime.h>
 
 #include "fft_frame.hpp"
@@ -14,56 +15,76 @@
 
 namespace odp {
 
-template <int P, bool MASK>
-__global__ __launch_bounds__(Frame<P>::T) void k_probe_mean(ProbeArgs a) {
+// (1/D) sum_d (w_d + Delta_d) per probe pixel, FP64 over d in ascending order
+__global__ __launch_bounds__(256) void k_probe_avg(ProbeArgs a) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= a.p * a.p) return;
+  const size_t pp = (size_t)a.p * a.p;
+  double sx = 0.0, sy = 0.0;
+  for (int d = 0; d < a.D; ++d) {
+    const float2 ws = a.w_sub[d * pp + k], dl = a.delta[d * pp + k];
+    sx += (double)ws.x + dl.x;
+    sy += (double)ws.y + dl.y;
+  }
+  const double invD = 1.0 / (double)a.D;
+  a.w[k] = make_float2((float)(sx * invD), (float)(sy * invD));
+}
+
+// P_O = F^{-1} M F on the averaged probe, in place (one workgroup: every thread reads
+// its 16 values before any is written)
+template <int P>
+__global__ __launch_bounds__(Frame<P>::T) void k_probe_project(ProbeArgs a) {
   using F = Frame<P>;
-  __shared__ float2 lds[MASK ? F::LDS : 1];
+  __shared__ float2 lds[F::LDS];
   const int t = threadIdx.x;
   const int col = F::a_col(t), r2 = F::a_r2(t);
-  const double invD = 1.0 / (double)a.D;
   float2 v[16];
 #pragma unroll
-  for (int r1 = 0; r1 < 16; ++r1) {
-    const int k = (F::N2 * r1 + r2) * P + col;
-    double sx = 0.0, sy = 0.0;
-    for (int d = 0; d < a.D; ++d) {
-      const float2 ws = a.w_sub[(size_t)d * P * P + k], dl = a.delta[(size_t)d * P * P + k];
-      sx += (double)ws.x + dl.x;
-      sy += (double)ws.y + dl.y;
-    }
-    v[r1] = make_float2((float)(sx * invD), (float)(sy * invD));
-  }
-  if (MASK) {
-    F::forward(v, lds, a.tw, t);
-    const float s = 1.0f / (float)(P * P);   // both unitary factors
+  for (int r1 = 0; r1 < 16; ++r1) v[r1] = a.w[(F::N2 * r1 + r2) * P + col];
+  F::forward(v, lds, a.tw, t);
+  const float s = 1.0f / (float)(P * P);   // both unitary factors
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      int kr, kc;
-      F::freq(t, e, kr, kc);
-      v[e] = c_scale(v[e], s * a.fmask[kr * P + kc]);
-    }
-    __syncthreads();
-    F::inverse(v, lds, a.tw, t);
+  for (int e = 0; e < 16; ++e) {
+    int kr, kc;
+    F::freq(t, e, kr, kc);
+    v[e] = c_scale(v[e], s * a.fmask[kr * P + kc]);
   }
+  __syncthreads();
+  F::inverse(v, lds, a.tw, t);
 #pragma unroll
   for (int r1 = 0; r1 < 16; ++r1) a.w[(F::N2 * r1 + r2) * P + col] = v[r1];
 }
 
+// w_d and Delta_d for 64 probe pixels of subdomain d: the four wavefronts take every
+// fourth frame of the subdomain (frame order ascending within each), and their FP64
+// partial sums are added in wavefront order.
 __global__ __launch_bounds__(256) void k_probe_copies(ProbeArgs a) {
-  const int p = a.p, d = blockIdx.y;
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= p * p) return;
-  const int ky = k / p, kx = k % p;
+  __shared__ double part[3][4][64];
+  const int p = a.p, d = blockIdx.y, lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int k = blockIdx.x * 64 + lane;
+  const bool ok = k < p * p;
+  const int kk = ok ? k : 0;
+  const int ky = kk / p, kx = kk % p;
   double nr = 0.0, ni = 0.0, den = 0.0;
-  for (int q = a.sub_first[d]; q < a.sub_first[d + 1]; ++q) {
+  const int q1 = a.sub_first[d + 1];
+#pragma unroll 2
+  for (int q = a.sub_first[d] + grp; q < q1; q += 4) {
     const int j = a.order[q];
     const FrameDesc fd = a.frames[j];
     const float2 pu = a.u[fd.base + (int64_t)ky * fd.pitch + kx];
-    const float2 ph = a.phi[(size_t)j * p * p + k];
+    const float2 ph = a.phi[(size_t)j * p * p + kk];
     nr += (double)pu.x * ph.x + (double)pu.y * ph.y;   // conj(S_j u) o phi
     ni += (double)pu.x * ph.y - (double)pu.y * ph.x;
     den += (double)pu.x * pu.x + (double)pu.y * pu.y;
   }
+  part[0][grp][lane] = nr;
+  part[1][grp][lane] = ni;
+  part[2][grp][lane] = den;
+  __syncthreads();
+  if (grp != 0 || !ok) return;
+  nr = ((part[0][0][lane] + part[0][1][lane]) + part[0][2][lane]) + part[0][3][lane];
+  ni = ((part[1][0][lane] + part[1][1][lane]) + part[1][2][lane]) + part[1][3][lane];
+  den = ((part[2][0][lane] + part[2][1][lane]) + part[2][2][lane]) + part[2][3][lane];
   const size_t o = (size_t)d * p * p + k;
   const float2 w = a.w[k], dl = a.delta[o];
   const double q = a.eta * den + a.mu;
@@ -74,17 +95,17 @@ __global__ __launch_bounds__(256) void k_probe_copies(ProbeArgs a) {
 }
 
 hipError_t launch_probe_update(const ProbeArgs& a, hipStream_t s) {
-  const bool mask = a.fmask != nullptr;
-#define ODP_MEAN(PP)                                                                             \
-  if (a.p == PP) {                                                                               \
-    if (mask) hipLaunchKernelGGL((k_probe_mean<PP, true>), dim3(1), dim3(Frame<PP>::T), 0, s, a);  \
-    else hipLaunchKernelGGL((k_probe_mean<PP, false>), dim3(1), dim3(Frame<PP>::T), 0, s, a);      \
+  const int pp = a.p * a.p;
+  hipLaunchKernelGGL(k_probe_avg, dim3((pp + 255) / 256), dim3(256), 0, s, a);
+  if (a.fmask) {
+#define ODP_PROJ(PP) \
+  if (a.p == PP) hipLaunchKernelGGL((k_probe_project<PP>), dim3(1), dim3(Frame<PP>::T), 0, s, a);
+    ODP_PROJ(32)
+    ODP_PROJ(64)
+    ODP_PROJ(128)
+#undef ODP_PROJ
   }
-  ODP_MEAN(32)
-  ODP_MEAN(64)
-  ODP_MEAN(128)
-#undef ODP_MEAN
-  hipLaunchKernelGGL(k_probe_copies, dim3((a.p * a.p + 255) / 256, a.D), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_probe_copies, dim3((pp + 63) / 64, a.D), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
