@@ -13,10 +13,13 @@ under the prefix "<case>_":
               float64     relative distance, on the sample, between this run and
                           the same run from sqrt(f) multiplied by a seeded factor
                           uniform in 1 +- 2^-24 (half a float32 ulp)
+  sens50_bf16, sens200_bf16
+              float64     the same with 1 +- 2^-17 (the resolution of a split-BF16
+                          hi + lo pair)
 and r (the overlap penalty, shared).
 Inputs: the probe rounded to complex64 and sqrt(f) rounded to float32 (what the GPU
 reads).  eps = 0.5, eta = 0.1, r = 0.5 eta max_d den_d.
-Run: python tests/golden/make_c2_reference.py   (about half an hour, four threads)
+Run: python tests/golden/make_c2_reference.py   (about 45 minutes, four threads)
 """
 import os
 import sys
@@ -60,19 +63,21 @@ def main():
     for name, f in cases.items():
         sf = np.sqrt(f).astype(np.float32).astype(np.float64)
         snap, rf = snapshots(g, w, sf, r, idx)
-        jitter = np.random.default_rng(7).uniform(-2.0 ** -24, 2.0 ** -24, sf.shape)
-        snap_p, _ = snapshots(g, w, sf * (1.0 + jitter), r, idx)
-        for k in K:
-            a, b = snap[k].reshape(-1)[idx], snap_p[k].reshape(-1)[idx]
-            res[f"{name}_u{k}"] = a
-            res[f"{name}_sens{k}"] = np.linalg.norm(a - b) / np.linalg.norm(a)
+        unit = np.random.default_rng(7).uniform(-1.0, 1.0, sf.shape)
+        for tag, scale in (("", 2.0 ** -24), ("_bf16", 2.0 ** -17)):
+            snap_p, _ = snapshots(g, w, sf * (1.0 + scale * unit), r, idx)
+            for k in K:
+                a, b = snap[k].reshape(-1)[idx], snap_p[k].reshape(-1)[idx]
+                res[f"{name}_u{k}"] = a
+                res[f"{name}_sens{k}{tag}"] = np.linalg.norm(a - b) / np.linalg.norm(a)
         u = snap[K[-1]]
         res[f"{name}_norm200"] = np.linalg.norm(u)
         res[f"{name}_rf"] = rf
         res[f"{name}_err_true"] = np.linalg.norm(align_phase(u, pr["u_true"]) - pr["u_true"]) / np.linalg.norm(
             pr["u_true"])
         print(name, "RF", rf[0], "->", rf[-1], "err_true", res[f"{name}_err_true"],
-              "sens", res[f"{name}_sens50"], res[f"{name}_sens200"], flush=True)
+              "sens", res[f"{name}_sens50"], res[f"{name}_sens200"],
+              "sens_bf16", res[f"{name}_sens50_bf16"], res[f"{name}_sens200_bf16"], flush=True)
     np.savez(os.path.join(HERE, "c2_k200_oracle.npz"), **res)
 
 

@@ -6,13 +6,14 @@ recipes), for both frame transforms and two data cases.
 Bound on the merged image (8192 seeded pixel samples, relative norm):
     max(1e-3, 2 * s_K)
 where s_K is the oracle's own distance after K iterations between runs whose sqrt(f)
-differ by half a float32 ulp.  On noise-free data the iteration contracts (s_K is
-1e-5 or less) and the bound is the plain 1e-3.  On Poisson data the iteration
-amplifies rounding-sized differences (s_50 = 3.0e-3, s_200 = 3.5e-3), so no
-float32 run, and no float64 run in another summation order, can stay within 1e-3
-of one particular float64 trajectory; the bound then asks for agreement to the
-oracle's own resolution.  The RF curve (Sec. 4) and the error against the true
-image are compared as well.
+differ by the transform's resolution: half a float32 ulp (1 +- 2^-24) for the FP32
+FFT, 1 +- 2^-17 for the split-BF16 DFT.  On noise-free data the iteration contracts
+(s_K is 1e-4 or less) and the bound is the plain 1e-3.  On Poisson data the iteration
+amplifies rounding-sized differences (s_50 = 3.0e-3 and 4.8e-3, s_200 = 3.5e-3 and
+4.3e-3), so no float32 run, and no float64 run in another summation order, can stay
+within 1e-3 of one particular float64 trajectory; the bound then asks for agreement
+to the oracle's own resolution.  The RF curve (Sec. 4), the norm and the error
+against the true image are compared to 1e-3 as well.
 """
 from __future__ import annotations
 
@@ -61,8 +62,9 @@ def test_c2_reconstruction_matches_oracle(golden, case, transform):
         done = k
         u = host(plan.merge(st))
         want = golden[f"{case}_u{k}"]
+        tag = "_bf16" if transform == odp.ODP_DFT_SPLIT_BF16 else ""
         errs[k] = (float(np.linalg.norm(u.reshape(-1)[idx] - want) / np.linalg.norm(want)),
-                   max(1e-3, 2.0 * float(golden[f"{case}_sens{k}"])))
+                   max(1e-3, 2.0 * float(golden[f"{case}_sens{k}{tag}"])))
     rf = np.concatenate(rf)
     rf_diff = float(np.max(np.abs(rf - golden[f"{case}_rf"]) / golden[f"{case}_rf"]))
     norm_diff = float(np.linalg.norm(u) / golden[f"{case}_norm200"] - 1.0)
