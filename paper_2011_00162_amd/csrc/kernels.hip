@@ -45,27 +45,24 @@ template <int P, bool BLIND, bool STATS>
 __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
   using F = Frame<P>;
   __shared__ float2 lds[F::LDS];
+  __shared__ float2 twl[F::N2 * 16];   // stage-B twiddles, read from LDS so that no
+                                       // wait on them also waits on the prefetches
   __shared__ double red[F::T / 64];
   const int j = sweep_frame(a.chunk, a.J, a.order, a.xcd_slice);
   if (j < 0) return;  // uniform over the workgroup
   const int t = threadIdx.x;
+  if (t < F::N2 * 16) twl[t] = a.tw[t];   // visible after the first barrier of forward_bc
   const FrameDesc fd = a.frames[j];
   const size_t woff = (size_t)(a.w_per_sub ? fd.sub : fd.probe) * P * P;
   const float2* w = a.w + woff;
   const int col = F::a_col(t), r2 = F::a_r2(t);
   const float inv_p = 1.0f / (float)P;
 
-  // The inverse transform returns each thread's 16 points to the positions it
-  // gathered, so at P = 32 the probe values stay in registers for the output
-  // multiply (for larger P the 32 registers would cost occupancy; they are read again).
-  constexpr bool KEEPW = !BLIND && P <= 32;
-  float2 v[16], wk[16];
+  float2 v[16];
 #pragma unroll
   for (int r1 = 0; r1 < 16; ++r1) {
     const int row = F::N2 * r1 + r2;
-    const float2 wr = w[row * P + col];
-    if (KEEPW) wk[r1] = wr;
-    v[r1] = c_mul(a.u[fd.base + (int64_t)row * fd.pitch + col], wr);
+    v[r1] = c_mul(a.u[fd.base + (int64_t)row * fd.pitch + col], w[row * P + col]);
   }
   F::forward_a(v, lds, a.tw, t);
   // The thread's amplitudes (and, for P <= 64, multipliers) are fetched now, while
@@ -82,8 +79,18 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
     if (PRE >= 1) spre[e] = a.sqrt_f[fbase + kr * P + kc];
     if (PRE >= 2) gpre[e] = a.gamma[fbase + kr * P + kc];
   }
-  F::forward_bc(v, lds, a.tw, t);
+  F::forward_bc(v, lds, twl, t);
 
+  // all 16 multipliers are read before any is written back, so the loads are in
+  // flight together (the stores could otherwise alias later loads for the compiler)
+  if (PRE < 2) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      int kr, kc;
+      F::freq(t, e, kr, kc);
+      gpre[e] = a.gamma[fbase + kr * P + kc];
+    }
+  }
   double mis = 0.0, gsum = 0.0;
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
@@ -92,16 +99,22 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
     const size_t idx = fbase + kr * P + kc;
     const float2 X = c_scale(v[e], inv_p);
     const float sf = PRE >= 1 ? spre[e] : a.sqrt_f[idx];
-    const float2 y = c_add(PRE >= 2 ? gpre[e] : a.gamma[idx], X);
+    const float2 y = c_add(gpre[e], X);
     const float2 z = prox_stagm(y, sf, pc);
     const float2 g = c_sub(y, z);
-    a.gamma[idx] = g;
+    gpre[e] = g;
     v[e] = c_scale(c_sub(z, g), inv_p);   // both 1/p factors of the unitary pair applied here
     if (STATS) {
       const double ax = sqrt((double)X.x * X.x + (double)X.y * X.y);
       mis += fabs(ax - (double)sf);
       gsum += g_eps(ax, (double)sf, (double)a.eps);
     }
+  }
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    int kr, kc;
+    F::freq(t, e, kr, kc);
+    a.gamma[fbase + kr * P + kc] = gpre[e];
   }
   if (STATS) {
     mis = block_sum<F::T>(mis, red);
@@ -112,13 +125,19 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
     }
   }
   __syncthreads();  // stage-C reads of all threads done before inverse writes reuse LDS
-  F::inverse(v, lds, a.tw, t);
-  const float2* wo = a.w_out + woff;
+  F::inverse(v, lds, twl, t);
+  // the inverse returns each thread's 16 points to the positions it gathered; the 16
+  // probe values are read before any output is written, so they are in flight together
+  if (!BLIND) {
+    const float2* wo = a.w_out + woff;
+    float2 wk[16];
 #pragma unroll
-  for (int r1 = 0; r1 < 16; ++r1) {
-    const int row = F::N2 * r1 + r2;
-    a.psi[fbase + row * P + col] = BLIND ? v[r1] : c_mulc(v[r1], KEEPW ? wk[r1] : wo[row * P + col]);
+    for (int r1 = 0; r1 < 16; ++r1) wk[r1] = wo[(F::N2 * r1 + r2) * P + col];
+#pragma unroll
+    for (int r1 = 0; r1 < 16; ++r1) v[r1] = c_mulc(v[r1], wk[r1]);
   }
+#pragma unroll
+  for (int r1 = 0; r1 < 16; ++r1) a.psi[fbase + (F::N2 * r1 + r2) * P + col] = v[r1];
 }
 
 hipError_t launch_sweep(int p, const SweepArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
