@@ -51,7 +51,6 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
   const int j = sweep_frame(a.chunk, a.J, a.order, a.xcd_slice);
   if (j < 0) return;  // uniform over the workgroup
   const int t = threadIdx.x;
-  if (t < F::N2 * 16) twl[t] = a.tw[t];   // visible after the first barrier of forward_bc
   const FrameDesc fd = a.frames[j];
   const size_t woff = (size_t)(a.w_per_sub ? fd.sub : fd.probe) * P * P;
   const float2* w = a.w + woff;
@@ -64,6 +63,9 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
     const int row = F::N2 * r1 + r2;
     v[r1] = c_mul(a.u[fd.base + (int64_t)row * fd.pitch + col], w[row * P + col]);
   }
+  // the stage-B twiddles go to LDS after the gather's loads are issued, so waiting for
+  // this copy overlaps their latency; visible after the first barrier of forward_bc
+  if (t < F::N2 * 16) twl[t] = a.tw[t];
   F::forward_a(v, lds, a.tw, t);
   // The thread's amplitudes (and, for P <= 64, multipliers) are fetched now, while
   // stages B and C run: between stages A and C the thread holds no frame data in
