@@ -71,23 +71,25 @@ __global__ __launch_bounds__(256) void k_grad_u(LossGradArgs a) {
   const int tile = blockIdx.x;
   const TileDesc td = a.tiles[tile];
   const CellDesc* cd = a.cells + td.cell;
-  const int tr = threadIdx.x / a.tile_cols, tc = threadIdx.x % a.tile_cols;
-  const bool act = tr < td.nr && tc < td.nc;
-  const int yi = cd->r0 + td.r0 + tr, xi = cd->c0 + td.c0 + tc;
   const int p = a.p;
   // tiles partition the covered pixels, so each pixel is written by one thread
-  float2 g = make_float2(0.f, 0.f);
-  const int64_t pix = (int64_t)yi * p + xi;
-  for (int s = 0; s < cd->m; ++s) {
-    const int k1 = a.tf_first[tile * MAXS + s + 1];
-    for (int k = a.tf_first[tile * MAXS + s]; k < k1; ++k) {
-      const PullEntry pe = a.pull[k];
-      const int dy = yi - pe.r, dx = xi - pe.c;
-      if (act && (unsigned)dy < (unsigned)p && (unsigned)dx < (unsigned)p)
-        g = c_add(g, c_mulc(a.phi[pe.base + pix], a.w[dy * p + dx]));
+  for (int h = 0; h < NPX; ++h) {
+    const int i = threadIdx.x + 256 * h, tr = i / a.tile_cols, tc = i % a.tile_cols;
+    const bool act = tr < td.nr && tc < td.nc;
+    const int yi = cd->r0 + td.r0 + tr, xi = cd->c0 + td.c0 + tc;
+    float2 g = make_float2(0.f, 0.f);
+    const int64_t pix = (int64_t)yi * p + xi;
+    for (int s = 0; s < cd->m; ++s) {
+      const int k1 = a.tf_first[tile * MAXS + s + 1];
+      for (int k = a.tf_first[tile * MAXS + s]; k < k1; ++k) {
+        const PullEntry pe = a.pull[k];
+        const int dy = yi - pe.r, dx = xi - pe.c;
+        if (act && (unsigned)dy < (unsigned)p && (unsigned)dx < (unsigned)p)
+          g = c_add(g, c_mulc(a.phi[pe.base + pix], a.w[dy * p + dx]));
+      }
     }
+    if (act) a.grad_u[(int64_t)yi * a.W + xi] = g;
   }
-  if (act) a.grad_u[(int64_t)yi * a.W + xi] = g;
 }
 
 // dL/dw partial sums over frame chunks (FP64), then a fixed-order final sum.

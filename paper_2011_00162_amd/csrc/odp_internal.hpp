@@ -9,7 +9,7 @@ namespace odp {
 
 constexpr int MAXS = 8;                        // most subdomains over one pixel
 constexpr int MAXP = MAXS * (MAXS - 1) / 2;    // most pairs over one pixel
-constexpr int TILE_PIX = 256;                  // pixels (= threads) of a pixel-update tile
+constexpr int NPX = 2;                          // pixels per thread in the pixel-tile kernels
 constexpr int NXCD = 8;                        // MI355X accelerator complex dies
 
 // A cell is a rectangle of image pixels covered by the same set of subdomains
@@ -72,6 +72,26 @@ struct SweepArgs {
   int blind;
 };
 
+// One wavefront's share of a pixel-update tile whose cell has at most four copies
+// per pixel: its copy slot s and every index at the tile's top-left pixel (partner o
+// is copy t = o + (o >= s)), so a wavefront reads its whole descriptor in one
+// scalar round trip, with no loads that depend on other loads.
+struct WaveRec {
+  int64_t u0;                // u_sub index of the top-left, copy s
+  int64_t pu0[3];            // ... partner copies
+  int64_t lo0[3];            // Lam_{s,t} index of the top-left (written by this copy)
+  int64_t lt0[3];            // Lam_{t,s} index of the top-left
+  int32_t upitch, pupitch[3], lpitch[3];
+  int32_t s, m, lg, lcw;     // slot, copies, log2 copy groups, log2 tile width
+  int32_t nr, nc;            // tile extent
+  int32_t yi0, xi0;          // image coordinates of the top-left
+  int32_t k0, k1;            // pull records [k0, k1) of copy s
+  int32_t sub;               // subdomain of copy s
+  float r;                   // overlap penalty
+  int32_t pad;
+};
+static_assert(sizeof(WaveRec) == 160, "WaveRec layout");
+
 struct PixelArgs {
   float2* u;                 // u_sub (updated in place)
   const float* rcp;          // 1 / (eta den + r k + gamma); 0 = held pixel (non-blind)
@@ -80,6 +100,7 @@ struct PixelArgs {
   const TileDesc* tiles;
   int32_t n_tiles, p, tile_cols;
   int32_t n_uni;             // tiles [0, n_uni) belong to cells with at most 4 copies
+  const WaveRec* waves;      // [n_uni][4]
   const float2* psi;         // per-frame outputs of the sweep
   const int32_t* tf_first;   // [n_tiles*MAXS + 1]: frames of slot s overlapping tile t
   const PullEntry* pull;     // their records, ascending frame id

@@ -90,7 +90,7 @@ struct odp_plan {
   };
   TileSet tsets[3];
   int ts = 0;
-  int32_t xcd_slice = 1;
+  int32_t xcd_slice = 2;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> sweep_ev;   // kernel timing of the next sweeps
   size_t sweep_ev_next = 0, sweep_ev_stride = 1;
   // problems of a batch (one entry for a single problem)
@@ -106,8 +106,8 @@ struct odp_plan {
   int32_t chunk = 0;
   // workspace layout (byte offsets)
   struct {
-    size_t tw, w, frames, order, sub_first, offsets, rects, usub_off, cells, tiles, re_list, re_first, tf_first,
-        pull, den, rcp, fpart, tpart, stat_scratch, misc, pmax, psi, fmask, wpart, dft, bytes;
+    size_t tw, w, frames, order, sub_first, offsets, rects, usub_off, cells, tiles, waves, re_list, re_first,
+        tf_first, pull, den, rcp, fpart, tpart, stat_scratch, misc, pmax, psi, fmask, wpart, dft, bytes;
   } ws{};
   struct {
     size_t u_sub, gamma, lam, w, w_sub, delta, bytes;
@@ -127,9 +127,9 @@ namespace {
 
 // Cut every cell into tiles and list, per (tile, subdomain slot), the slot's frames
 // whose window meets the tile (ascending id).  A cell with m copies per pixel gets
-// tiles of 256 / m' pixels (m' = m rounded up to a power of two), so one workgroup
-// of 256 threads holds every copy of its pixels: width min(cols, 256 / m'), height
-// the rest (rows x cols = 256 is the shape for m = 1).
+// tiles of 512 / m' pixels (m' = m rounded up to a power of two), so one workgroup
+// of 256 threads, two pixels per thread, holds every copy of its pixels: width
+// min(cols, 512 / m'), height the rest (rows x cols = 512 is the shape for m = 1).
 void build_tiles(const odp_plan* P, int rows, int cols, odp_plan::TileSet& T) {
   const int p = P->p, D = P->D;
   T.rows = rows;
@@ -321,7 +321,7 @@ int build_geometry(odp_plan* P) {
   for (int j = 0; j < J; ++j) P->sub_first[P->frame_sub[j] + 1]++;
   for (int d = 0; d < D; ++d) P->sub_first[d + 1] += P->sub_first[d];
   P->chunk = (J + NXCD - 1) / NXCD;
-  static const int shapes[3][2] = {{8, 32}, {4, 64}, {16, 16}};
+  static const int shapes[3][2] = {{16, 32}, {8, 64}, {32, 16}};
   for (int k = 0; k < 3; ++k) build_tiles(P, shapes[k][0], shapes[k][1], P->tsets[k]);
   P->ts = 0;
   // twiddle table tw[i][k] = W_p^{i k} = exp(-2 pi i i k / p), i < p/16, k < 16, FP64 on the host
@@ -372,14 +372,16 @@ void layout(odp_plan* P) {
   P->ws.rects = take(sizeof(int32_t) * 4 * P->D);
   P->ws.usub_off = take(sizeof(int64_t) * P->D);
   P->ws.cells = take(sizeof(CellDesc) * P->cells.size());
-  size_t n_tiles = 1, n_re = 1, n_tf = 1, n_pull = 1;
+  size_t n_tiles = 1, n_uni = 1, n_re = 1, n_tf = 1, n_pull = 1;
   for (const auto& T : P->tsets) {
     n_tiles = std::max(n_tiles, T.tiles.size());
+    n_uni = std::max(n_uni, (size_t)T.n_uni);
     n_re = std::max(n_re, T.re_list.size());
     n_tf = std::max(n_tf, T.tf_first.size());
     n_pull = std::max(n_pull, T.pull.size());
   }
   P->ws.tiles = take(sizeof(TileDesc) * n_tiles);
+  P->ws.waves = take(sizeof(WaveRec) * 4 * n_uni);
   P->ws.re_list = take(sizeof(int32_t) * n_re);
   P->ws.re_first = take(sizeof(int32_t) * (P->D + 1));
   P->ws.tf_first = take(sizeof(int32_t) * n_tf);
@@ -439,18 +441,122 @@ IllumArgs illum_args(const odp_plan* P, const float2* w, int recompute) {
   return a;
 }
 
-int upload_tiles(odp_plan* P, hipStream_t s) {
+// The active tiling's arrays in launch order.  With xcd_slice = 2 the tiles of cells
+// with at most four copies are placed so that the tile at launch position i runs on
+// XCD i mod 8 whenever that is the XCD whose frame slice holds the frames of the
+// tile's first copy (its psi is then read back through that XCD's L2); the other
+// XCDs' leftovers fill the remaining positions.  tf_first, the pull records and
+// re_list follow the tiles (re_list keeps its order, so the statistics are summed
+// in the same order under every placement), and every wavefront of those tiles
+// gets its WaveRec.
+struct DevTiles {
+  std::vector<TileDesc> tiles;
+  std::vector<int32_t> re_list, tf_first;
+  std::vector<PullEntry> pull;
+  std::vector<WaveRec> waves;
+};
+
+void device_tiles(const odp_plan* P, DevTiles& o) {
   const odp_plan::TileSet& T = P->tset();
+  const size_t n = T.tiles.size(), nu = (size_t)T.n_uni;
+  std::vector<int32_t> perm(n);   // launch position -> tile
+  for (size_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
+  if (P->xcd_slice == 2 && P->chunk > 0) {
+    std::vector<std::vector<int32_t>> q(NXCD);
+    for (size_t t = 0; t < nu; ++t) {
+      const int d = P->cells[T.tiles[t].cell].sub[0];
+      const int mid = (P->sub_first[d] + P->sub_first[d + 1]) / 2;
+      q[std::min(NXCD - 1, mid / P->chunk)].push_back((int32_t)t);
+    }
+    std::vector<size_t> h(NXCD, 0);
+    for (size_t i = 0; i < nu; ++i) {
+      int x = (int)(i % NXCD);
+      if (h[x] >= q[x].size()) {  // XCD x has no tiles left: take from the longest queue
+        size_t left = 0;
+        for (int y = 0; y < NXCD; ++y)
+          if (q[y].size() - h[y] > left) {
+            left = q[y].size() - h[y];
+            x = y;
+          }
+      }
+      perm[i] = q[x][h[x]++];
+    }
+  }
+  std::vector<int32_t> inv(n);
+  for (size_t i = 0; i < n; ++i) inv[perm[i]] = (int32_t)i;
+  o.tiles.resize(n);
+  o.tf_first.assign(n * MAXS + 1, 0);
+  o.pull.clear();
+  o.pull.reserve(T.pull.size());
+  for (size_t i = 0; i < n; ++i) {
+    const int t = perm[i];
+    o.tiles[i] = T.tiles[t];
+    for (int sl = 0; sl < MAXS; ++sl) {
+      o.tf_first[i * MAXS + sl] = (int32_t)o.pull.size();
+      o.pull.insert(o.pull.end(), T.pull.begin() + T.tf_first[(size_t)t * MAXS + sl],
+                    T.pull.begin() + T.tf_first[(size_t)t * MAXS + sl + 1]);
+    }
+  }
+  o.tf_first[n * MAXS] = (int32_t)o.pull.size();
+  o.re_list.resize(T.re_list.size());
+  for (size_t k = 0; k < T.re_list.size(); ++k) {
+    const int32_t e = T.re_list[k];
+    o.re_list[k] = inv[e / MAXS] * MAXS + e % MAXS;
+  }
+  o.waves.assign(nu * 4, WaveRec{});
+  for (size_t i = 0; i < nu; ++i) {
+    const TileDesc& td = o.tiles[i];
+    const CellDesc& cd = P->cells[td.cell];
+    int lg = 0;
+    while ((1 << lg) < cd.m) ++lg;
+    const int tpg = 256 >> lg, cw = std::min(T.cols, NPX * tpg);
+    int lcw = 0;
+    while ((1 << lcw) < cw) ++lcw;
+    for (int wv = 0; wv < 4; ++wv) {
+      WaveRec& r = o.waves[i * 4 + wv];
+      const int sl = wv * 64 / tpg;
+      r.s = sl;
+      r.m = cd.m;
+      r.lg = lg;
+      r.lcw = lcw;
+      r.nr = td.nr;
+      r.nc = td.nc;
+      r.yi0 = cd.r0 + td.r0;
+      r.xi0 = cd.c0 + td.c0;
+      r.r = cd.r;
+      r.sub = cd.sub[std::min(sl, cd.m - 1)];
+      if (sl >= cd.m) continue;  // idle copy group: empty pull, no pixels
+      r.u0 = cd.ubase[sl] + (int64_t)td.r0 * cd.upitch[sl] + td.c0;
+      r.upitch = cd.upitch[sl];
+      r.k0 = o.tf_first[i * MAXS + sl];
+      r.k1 = o.tf_first[i * MAXS + sl + 1];
+      for (int pt = 0; pt < cd.m - 1; ++pt) {
+        const int t = pt + (pt >= sl), lo = std::min(sl, t), hi = std::max(sl, t), pq = hi * (hi - 1) / 2 + lo;
+        const int64_t li = cd.lbase[pq] + (int64_t)td.r0 * cd.lpitch[pq] + td.c0, lj = li + cd.lstride[pq];
+        r.lo0[pt] = sl < t ? li : lj;
+        r.lt0[pt] = sl < t ? lj : li;
+        r.lpitch[pt] = cd.lpitch[pq];
+        r.pu0[pt] = cd.ubase[t] + (int64_t)td.r0 * cd.upitch[t] + td.c0;
+        r.pupitch[pt] = cd.upitch[t];
+      }
+    }
+  }
+}
+
+int upload_tiles(odp_plan* P, hipStream_t s) {
+  DevTiles D;
+  device_tiles(P, D);
   auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
     if (bytes == 0) return hipSuccess;
     return hipMemcpyAsync(P->wsp + off, src, bytes, hipMemcpyHostToDevice, s);
   };
-  ODP_HIP(up(P->ws.tiles, T.tiles.data(), sizeof(TileDesc) * T.tiles.size()));
-  ODP_HIP(up(P->ws.re_list, T.re_list.data(), sizeof(int32_t) * T.re_list.size()));
-  ODP_HIP(up(P->ws.re_first, T.re_first.data(), sizeof(int32_t) * T.re_first.size()));
-  ODP_HIP(up(P->ws.tf_first, T.tf_first.data(), sizeof(int32_t) * T.tf_first.size()));
-  ODP_HIP(up(P->ws.pull, T.pull.data(), sizeof(PullEntry) * T.pull.size()));
-  // pageable host sources: finish before the vectors may change
+  ODP_HIP(up(P->ws.tiles, D.tiles.data(), sizeof(TileDesc) * D.tiles.size()));
+  ODP_HIP(up(P->ws.waves, D.waves.data(), sizeof(WaveRec) * D.waves.size()));
+  ODP_HIP(up(P->ws.re_list, D.re_list.data(), sizeof(int32_t) * D.re_list.size()));
+  ODP_HIP(up(P->ws.re_first, P->tset().re_first.data(), sizeof(int32_t) * P->tset().re_first.size()));
+  ODP_HIP(up(P->ws.tf_first, D.tf_first.data(), sizeof(int32_t) * D.tf_first.size()));
+  ODP_HIP(up(P->ws.pull, D.pull.data(), sizeof(PullEntry) * D.pull.size()));
+  // pageable host sources: finish before the vectors go out of scope
   ODP_HIP(hipStreamSynchronize(s));
   return ODP_OK;
 }
@@ -462,6 +568,8 @@ int set_penalties(odp_plan* P, const double* r, hipStream_t s) {
   if (!P->wsp) return ODP_OK;
   ODP_HIP(hipMemcpyAsync(P->wsp + P->ws.cells, P->cells.data(), sizeof(CellDesc) * P->cells.size(),
                          hipMemcpyHostToDevice, s));
+  const int rc = upload_tiles(P, s);   // the wave records carry r too
+  if (rc) return rc;
   ODP_HIP(launch_illum(illum_args(P, P->W_<float2>(P->ws.w), 0), s));
   ODP_HIP(hipStreamSynchronize(s));
   return ODP_OK;
@@ -825,6 +933,7 @@ static PixelArgs pixel_args(const odp_plan* P, char* b, double* stats) {
   a.lam = reinterpret_cast<float2*>(b + P->st.lam);
   a.cells = P->W_<CellDesc>(P->ws.cells);
   a.tiles = P->W_<TileDesc>(P->ws.tiles);
+  a.waves = P->W_<WaveRec>(P->ws.waves);
   a.n_tiles = (int32_t)P->tset().tiles.size();
   a.n_uni = P->tset().n_uni;
   a.p = P->p;
@@ -1004,12 +1113,12 @@ int odp_plan_set_tuning(odp_plan* P, int32_t transform, int32_t xcd_slice, int32
   if (transform == ODP_DFT_SPLIT_BF16 && P->p != 64)
     return fail(ODP_EUNSUPPORTED, "the split-BF16 DFT transform is built for p = 64");
   if (tiling < 0 || tiling > 2) return fail(ODP_EINVAL, "tiling must be 0, 1 or 2");
+  if (xcd_slice < 0 || xcd_slice > 2) return fail(ODP_EINVAL, "xcd_slice must be 0, 1 or 2");
   P->transform = transform;
-  P->xcd_slice = xcd_slice ? 1 : 0;
-  if (tiling != P->ts) {
-    P->ts = tiling;
-    if (P->wsp) return upload_tiles(P, s);
-  }
+  const bool moved = tiling != P->ts || (xcd_slice == 2) != (P->xcd_slice == 2);
+  P->xcd_slice = xcd_slice;
+  P->ts = tiling;
+  if (moved && P->wsp) return upload_tiles(P, s);
   return ODP_OK;
 }
 
@@ -1026,7 +1135,7 @@ int odp_plan_autotune(odp_plan* P, void* dev_scratch_state, int32_t iters, hipSt
   int bt = P->transform, bx = P->xcd_slice, bs = P->ts, tried = 0;
   int rc = ODP_OK;
   for (int tr : transforms) {
-    for (int xs = 1; xs >= 0 && !rc; --xs) {
+    for (int xs = 2; xs >= 0 && !rc; --xs) {
       for (int ts = 0; ts < 3 && !rc; ++ts) {
         rc = odp_plan_set_tuning(P, tr, xs, ts, s);
         if (!rc) rc = odp_admm_iterate(P, dev_scratch_state, 2, nullptr, s);  // warm-up

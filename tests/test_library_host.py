@@ -161,3 +161,16 @@ def test_sweep_event_arguments_are_checked():
     assert L.odp_plan_set_sweep_events(plan._h, None, one, 1, 1) == ODP_EINVAL  # null array
     assert L.odp_plan_set_sweep_events(plan._h, nul, one, 1, 1) == ODP_EINVAL   # null event
     assert L.odp_plan_set_sweep_events(plan._h, None, None, 0, 1) == 0
+
+
+def test_tuning_values_are_checked():
+    plan = odp.Plan(**_plan_args())
+    L = odp.lib()
+    assert L.odp_plan_set_tuning(plan._h, odp.ODP_FFT_F32, 3, 0, None) == ODP_EINVAL
+    assert L.odp_plan_set_tuning(plan._h, odp.ODP_FFT_F32, -1, 0, None) == ODP_EINVAL
+    assert L.odp_plan_set_tuning(plan._h, odp.ODP_FFT_F32, 0, 3, None) == ODP_EINVAL
+    for xcd in (0, 1, 2):
+        for tiling, shape in ((0, (16, 32)), (1, (8, 64)), (2, (32, 16))):
+            assert L.odp_plan_set_tuning(plan._h, odp.ODP_FFT_F32, xcd, tiling, None) == 0   # unbound: host only
+            t = plan.tuning()
+            assert (t.xcd_slice, t.tiling, (t.tile_rows, t.tile_cols)) == (xcd, tiling, shape)
