@@ -194,36 +194,44 @@ __device__ __forceinline__ PullEntry load_entry(const PullEntry* e) {
 }
 
 // Sums of the covering frames' contributions at the thread's NPX image pixels, over
-// the records [k0, k1) in order.  The records are the same for a whole copy group
-// (scalar loads when the group spans whole wavefronts) and are taken B at a time,
-// the last group padded with repeats of record k1 - 1 that count as outside every
-// window.  Only lanes inside a window load (a frame edge crossing a wavefront leaves
-// the other lanes idle instead of fetching a dummy element), and all loads of a
-// group are issued before any is used.
+// the records [k0, k1) in order.  Every list is padded to a multiple of PULL_B
+// records with records whose window contains no pixel, and PULL_B such records
+// follow the last list, so the records are read PULL_B at a time with no clamping
+// (scalar loads when the copy group spans whole wavefronts), and the next group is
+// requested before this group's psi loads.  pix8[h] is the byte offset
+// 8 (y p + x) of pixel h, so a psi address is a per-record scalar base plus a
+// per-lane 32-bit offset.  Only lanes inside a window load; the others add 0, which
+// leaves the sum unchanged (it never holds -0).
 template <bool BLIND>
 __device__ __forceinline__ void pull_pixels(const PullEntry* __restrict__ pull, int k0, int k1,
                                             const float2* __restrict__ psi, const float2* __restrict__ ws,
-                                            const int* yi, const int* xi, int p, float2* num, double* den) {
-  constexpr int B = 4;
+                                            const int* yi, const int* xi, const uint32_t* pix8, int p,
+                                            float2* num, double* den) {
+  constexpr int B = PULL_B;
+  PullEntry e[B];
+#pragma unroll
+  for (int q = 0; q < B; ++q) e[q] = load_entry(pull + k0 + q);
   for (int k = k0; k < k1; k += B) {
-    PullEntry e[B];
+    PullEntry en[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) en[q] = load_entry(pull + k + B + q);
     bool in[B][NPX];
     float2 ps[B][NPX], ww[B][NPX];
 #pragma unroll
-    for (int q = 0; q < B; ++q) e[q] = load_entry(pull + min(k + q, k1 - 1));
-#pragma unroll
-    for (int q = 0; q < B; ++q)
+    for (int q = 0; q < B; ++q) {
+      const char* fb = reinterpret_cast<const char*>(psi + e[q].base);
 #pragma unroll
       for (int h = 0; h < NPX; ++h) {
         const int dy = yi[h] - e[q].r, dx = xi[h] - e[q].c;
-        in[q][h] = k + q < k1 && (unsigned)dy < (unsigned)p && (unsigned)dx < (unsigned)p;
+        in[q][h] = (unsigned)dy < (unsigned)p && (unsigned)dx < (unsigned)p;
         ps[q][h] = make_float2(0.f, 0.f);
         ww[q][h] = make_float2(0.f, 0.f);
         if (in[q][h]) {
-          ps[q][h] = psi[e[q].base + (int64_t)yi[h] * p + xi[h]];
+          ps[q][h] = *reinterpret_cast<const float2*>(fb + pix8[h]);
           if (BLIND) ww[q][h] = ws[dy * p + dx];
         }
       }
+    }
 #pragma unroll
     for (int q = 0; q < B; ++q)
 #pragma unroll
@@ -233,9 +241,11 @@ __device__ __forceinline__ void pull_pixels(const PullEntry* __restrict__ pull, 
           num[h] = in[q][h] ? c_add(num[h], c) : num[h];
           den[h] += in[q][h] ? (double)ww[q][h].x * ww[q][h].x + (double)ww[q][h].y * ww[q][h].y : 0.0;
         } else {
-          num[h] = in[q][h] ? c_add(num[h], ps[q][h]) : num[h];
+          num[h] = c_add(num[h], ps[q][h]);
         }
       }
+#pragma unroll
+    for (int q = 0; q < B; ++q) e[q] = en[q];
   }
 }
 
@@ -347,7 +357,10 @@ __global__ __launch_bounds__(256, BLIND ? 1 : 6) void k_pixel_uni(PixelArgs a) {
     den[h] = 0.0;
   }
   const float2* ws = BLIND ? a.w_sub + (size_t)w.sub * p * p : nullptr;
-  pull_pixels<BLIND>(a.pull, w.k0, w.k1, a.psi, ws, yi, xi, p, num, den);
+  uint32_t pix8[NPX];
+#pragma unroll
+  for (int h = 0; h < NPX; ++h) pix8[h] = 8u * (uint32_t)(yi[h] * p + xi[h]);
+  pull_pixels<BLIND>(a.pull, w.k0, w.k1, a.psi, ws, yi, xi, pix8, p, num, den);
 
   float2 un[NPX], dv[NPX][NO];
 #pragma unroll
@@ -429,8 +442,11 @@ __global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
     den[h] = 0.0;
   }
   const float2* ws = BLIND ? a.w_sub + (size_t)cd->sub[sc] * p * p : nullptr;
-  pull_pixels<BLIND>(a.pull, a.tf_first[tile * MAXS + s], a.tf_first[tile * MAXS + s + 1], a.psi, ws, yi, xi, p,
-                     num, den);
+  uint32_t pix8[NPX];
+#pragma unroll
+  for (int h = 0; h < NPX; ++h) pix8[h] = 8u * (uint32_t)(yi[h] * p + xi[h]);
+  pull_pixels<BLIND>(a.pull, a.tf_first[tile * MAXS + s], a.tf_first[tile * MAXS + s + 1], a.psi, ws, yi, xi, pix8,
+                     p, num, den);
 #pragma unroll
   for (int h = 0; h < NPX; ++h) {
     float2 ut[NO], lo[NO], lt[NO];

@@ -10,6 +10,7 @@ namespace odp {
 constexpr int MAXS = 8;                        // most subdomains over one pixel
 constexpr int MAXP = MAXS * (MAXS - 1) / 2;    // most pairs over one pixel
 constexpr int NPX = 2;                          // pixels per thread in the pixel-tile kernels
+constexpr int PULL_B = 4;                       // pull records per group (lists padded to a multiple)
 constexpr int NXCD = 8;                        // MI355X accelerator complex dies
 
 // A cell is a rectangle of image pixels covered by the same set of subdomains
@@ -38,11 +39,13 @@ struct TileDesc {
 
 // One covering frame of a pixel tile: psi index of pixel (y, x) of the image is
 // base + y*p + x (base = j*p*p - row_j*p - col_j); the window is rows
-// [row_j, row_j + p) and columns [col_j, col_j + p).
+// [row_j, row_j + p) and columns [col_j, col_j + p).  Padding records have
+// base 0 and r = c = PULL_NONE, a window that holds no pixel.
 struct PullEntry {
   int64_t base;
   int32_t r, c;
 };
+constexpr int32_t PULL_NONE = -(1 << 29);
 
 struct FrameDesc {
   int64_t base;              // u_sub index of the window's top-left inside its subdomain
@@ -77,17 +80,17 @@ struct SweepArgs {
 // is copy t = o + (o >= s)), so a wavefront reads its whole descriptor in one
 // scalar round trip, with no loads that depend on other loads.
 struct WaveRec {
-  int64_t u0;                // u_sub index of the top-left, copy s
-  int64_t pu0[3];            // ... partner copies
-  int64_t lo0[3];            // Lam_{s,t} index of the top-left (written by this copy)
-  int64_t lt0[3];            // Lam_{t,s} index of the top-left
-  int32_t upitch, pupitch[3], lpitch[3];
   int32_t s, m, lg, lcw;     // slot, copies, log2 copy groups, log2 tile width
   int32_t nr, nc;            // tile extent
   int32_t yi0, xi0;          // image coordinates of the top-left
   int32_t k0, k1;            // pull records [k0, k1) of copy s
   int32_t sub;               // subdomain of copy s
   float r;                   // overlap penalty
+  int64_t u0;                // u_sub index of the top-left, copy s
+  int64_t pu0[3];            // ... partner copies
+  int64_t lo0[3];            // Lam_{s,t} index of the top-left (written by this copy)
+  int64_t lt0[3];            // Lam_{t,s} index of the top-left
+  int32_t upitch, pupitch[3], lpitch[3];
   int32_t pad;
 };
 static_assert(sizeof(WaveRec) == 160, "WaveRec layout");

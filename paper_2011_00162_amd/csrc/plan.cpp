@@ -188,9 +188,11 @@ void build_tiles(const odp_plan* P, int rows, int cols, odp_plan::TileSet& T) {
         if (r < y1 && r + p > y0 && c < x1 && c + p > x0)
           T.pull.push_back(PullEntry{(int64_t)j * p * p - (int64_t)r * p - c, r, c});
       }
+      while ((T.pull.size() - T.tf_first[t * MAXS + s]) % PULL_B) T.pull.push_back(PullEntry{0, PULL_NONE, PULL_NONE});
     }
   }
   T.tf_first[T.tiles.size() * MAXS] = (int32_t)T.pull.size();
+  for (int q = 0; q < PULL_B; ++q) T.pull.push_back(PullEntry{0, PULL_NONE, PULL_NONE});  // read ahead of the last list
 }
 
 int build_geometry(odp_plan* P) {
@@ -498,6 +500,7 @@ void device_tiles(const odp_plan* P, DevTiles& o) {
     }
   }
   o.tf_first[n * MAXS] = (int32_t)o.pull.size();
+  for (int q = 0; q < PULL_B; ++q) o.pull.push_back(PullEntry{0, PULL_NONE, PULL_NONE});  // read ahead of the last list
   o.re_list.resize(T.re_list.size());
   for (size_t k = 0; k < T.re_list.size(); ++k) {
     const int32_t e = T.re_list[k];
