@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libodp.so")
 
-SOURCES = ["kernels.hip", "blind.hip", "loss.hip", "dft_mfma.hip", "plan.cpp"]
+SOURCES = ["kernels.hip", "pixel.hip", "blind.hip", "loss.hip", "dft_mfma.hip", "plan.cpp"]
 
 # Packed-FP32 instructions stay disabled (-packed-fp32-ops): plain float code only.
 FLAGS = [
