@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256) void k_probe_avg(ProbeArgs a) {
 template <int P>
 __global__ __launch_bounds__(Frame<P>::T) void k_probe_project(ProbeArgs a) {
   using F = Frame<P>;
-  __shared__ float2 lds[F::LDS];
+  __shared__ __align__(16) float2 lds[F::LDS];
   const int t = threadIdx.x;
   const int col = F::a_col(t), r2 = F::a_r2(t);
   float2 v[16];

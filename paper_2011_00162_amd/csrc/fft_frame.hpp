@@ -10,9 +10,12 @@
 // Stage B: the same over the column index c1, in place in LDS.
 // Stage C: the N2 x N2 DFT over (r2, c2) of every (k1_row, k1_col) block.
 // Each thread holds 16 complex values in every stage (T = p*p/16 threads).
-// LDS rows are padded by N2 complex values so that the stage-B column reads of a
-// wavefront hit all 64 banks once per half-wave; stage-C reads are contiguous
-// runs of N2 values (128-bit loads).
+// LDS layout (at()): the columns of a row sit in blocks of 16, block b starting 2b
+// complex values late (p = 64 and 128), and the row pitch LP is chosen with it:
+// the 128-bit stage-C accesses of every 8 lanes then start in 8 different 4-bank
+// groups (unshifted rows give them 2-way conflicts at p = 64 and 4-way at
+// p = 128), the 64-bit stage-B column accesses of every 16 lanes hit 32 different
+// banks, and the row-contiguous stage-A accesses stay contiguous.
 //
 // The inverse runs the stages backwards with conjugated twiddles.  Neither
 // direction scales; the caller applies 1/p per direction (unitary F).
@@ -22,6 +25,12 @@
 #include <hip/hip_runtime.h>
 
 namespace odp {
+
+// Row stride of the stage-B twiddle table when copied to LDS: rows 18 complex
+// values (36 banks) apart start in different 4-bank groups, so the 128-bit reads
+// of the N2 different rows a wavefront needs do not conflict (16 would put every
+// row on the same banks).
+constexpr int TWL = 18;
 
 __device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 c_sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -122,9 +131,14 @@ template <int P>
 struct Frame {
   static constexpr int N2 = P / 16;      // second radix per axis
   static constexpr int T = P * N2;       // threads per frame = p*p/16
-  static constexpr int LP = P + N2;      // padded LDS row pitch (complex elements)
+  static constexpr int LP = P == 128 ? 152 : P == 64 ? 76 : P + N2;  // LDS row pitch (complex)
   static constexpr int LDS = P * LP;     // LDS complex elements per frame
   static constexpr int NC = (N2 * N2 >= 16) ? 1 : 16 / (N2 * N2);  // stage-C blocks per thread
+  static constexpr int SHIFT = P >= 64 ? 2 : 0;  // per 16-column block (complex values)
+  static_assert(P + SHIFT * (P / 16 - 1) <= LP, "shifted row must fit the row pitch");
+
+  // LDS index of (row, col): column block b = col / 16 starts SHIFT * b values late
+  __device__ static __forceinline__ int at(int row, int col) { return row * LP + col + SHIFT * (col >> 4); }
 
   // Stage-A line of thread t: column and r2.  Value r1 sits at row N2*r1 + r2.
   __device__ static __forceinline__ int a_col(int t) { return t % P; }
@@ -152,13 +166,16 @@ struct Frame {
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       const float2 x = k == 0 ? v[k] : c_mul(v[k], ta[k]);
-      lds[(N2 * k + r2) * LP + col] = x;
+      lds[at(N2 * k + r2, col)] = x;
     }
   }
 
+  // TS: row stride of the twiddle table tw (16 in global memory; TWL for the padded
+  // copy in LDS)
+  template <int TS = 16>
   __device__ static __forceinline__ void forward_bc(float2* v, float2* lds, const float2* __restrict__ tw, int t) {
     __syncthreads();
-    stage_b<false>(lds, tw, t);
+    stage_b<false, TS>(lds, tw, t);
     __syncthreads();
     stage_c_fwd(v, lds, t);
   }
@@ -166,25 +183,26 @@ struct Frame {
   // ---- inverse ---------------------------------------------------------------
   // v: 16 frequencies in the freq() layout.  On return v holds the 16 spatial
   // values of this thread's stage-A line (unscaled inverse DFT).
+  template <int TS = 16>
   __device__ static void inverse(float2* v, float2* lds, const float2* __restrict__ tw, int t) {
     stage_c_inv(v, lds, t);
     __syncthreads();
-    stage_b<true>(lds, tw, t);
+    stage_b<true, TS>(lds, tw, t);
     __syncthreads();
     const int col = a_col(t), r2 = a_r2(t);
-    const float2* ta = tw + 16 * uniform_r2(t);
+    const float2* ta = tw + TS * uniform_r2(t);
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-      const float2 x = lds[(N2 * k + r2) * LP + col];
+      const float2 x = lds[at(N2 * k + r2, col)];
       v[k] = k == 0 ? x : c_mulc(x, ta[k]);
     }
     dft16<true>(v);
   }
 
-  template <bool INV>
+  template <bool INV, int TS>
   __device__ static __forceinline__ void stage_b(float2* lds, const float2* __restrict__ tw, int t) {
     const int c2 = t % N2, R = t / N2;
-    const float4* tb4 = reinterpret_cast<const float4*>(tw + 16 * c2);
+    const float4* tb4 = reinterpret_cast<const float4*>(tw + TS * c2);
     float2 v[16], w[16];
 #pragma unroll
     for (int k = 0; k < 16; k += 2) {
@@ -192,22 +210,21 @@ struct Frame {
       w[k] = make_float2(q.x, q.y);
       w[k + 1] = make_float2(q.z, q.w);
     }
-    float2* row = lds + R * LP + c2;
     if (INV) {
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
-        const float2 x = row[N2 * k];
+        const float2 x = lds[at(R, c2 + N2 * k)];
         v[k] = k == 0 ? x : c_mulc(x, w[k]);
       }
       dft16<true>(v);
 #pragma unroll
-      for (int k = 0; k < 16; ++k) row[N2 * k] = v[k];
+      for (int k = 0; k < 16; ++k) lds[at(R, c2 + N2 * k)] = v[k];
     } else {
 #pragma unroll
-      for (int k = 0; k < 16; ++k) v[k] = row[N2 * k];
+      for (int k = 0; k < 16; ++k) v[k] = lds[at(R, c2 + N2 * k)];
       dft16<false>(v);
 #pragma unroll
-      for (int k = 0; k < 16; ++k) row[N2 * k] = k == 0 ? v[k] : c_mul(v[k], w[k]);
+      for (int k = 0; k < 16; ++k) lds[at(R, c2 + N2 * k)] = k == 0 ? v[k] : c_mul(v[k], w[k]);
     }
   }
 
@@ -236,9 +253,8 @@ struct Frame {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int b = t + 64 * q, k1c = b & 15, k1r = b >> 4;
-        const float2* base = lds + (2 * k1r) * LP + 2 * k1c;
-        float4 r0 = *reinterpret_cast<const float4*>(base);
-        float4 r1 = *reinterpret_cast<const float4*>(base + LP);
+        float4 r0 = *reinterpret_cast<const float4*>(lds + at(2 * k1r, 2 * k1c));
+        float4 r1 = *reinterpret_cast<const float4*>(lds + at(2 * k1r + 1, 2 * k1c));
         float2 a00 = make_float2(r0.x, r0.y), a01 = make_float2(r0.z, r0.w);
         float2 a10 = make_float2(r1.x, r1.y), a11 = make_float2(r1.z, r1.w);
         dft2<false>(a00, a10);
@@ -249,12 +265,11 @@ struct Frame {
       }
     } else if constexpr (P == 64) {
       const int k1c = t & 15, k1r = t >> 4;
-      const float2* base = lds + (4 * k1r) * LP + 4 * k1c;
       float2 a[16];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        float4 lo = *reinterpret_cast<const float4*>(base + r * LP);
-        float4 hi = *reinterpret_cast<const float4*>(base + r * LP + 2);
+        float4 lo = *reinterpret_cast<const float4*>(lds + at(4 * k1r + r, 4 * k1c));
+        float4 hi = *reinterpret_cast<const float4*>(lds + at(4 * k1r + r, 4 * k1c + 2));
         a[4 * r + 0] = make_float2(lo.x, lo.y); a[4 * r + 1] = make_float2(lo.z, lo.w);
         a[4 * r + 2] = make_float2(hi.x, hi.y); a[4 * r + 3] = make_float2(hi.z, hi.w);
       }
@@ -269,24 +284,22 @@ struct Frame {
       for (int q = 0; q < 2; ++q) {
         const int L = t + 1024 * q;
         const int c2 = L & 7, k1c = (L >> 3) & 15, k1r = L >> 7;
-        float2* base = lds + (8 * k1r) * LP + 8 * k1c + c2;
         float2 a[8];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) a[r] = base[r * LP];
+        for (int r = 0; r < 8; ++r) a[r] = lds[at(8 * k1r + r, 8 * k1c + c2)];
         dft8<false>(a);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) base[r * LP] = a[r];
+        for (int r = 0; r < 8; ++r) lds[at(8 * k1r + r, 8 * k1c + c2)] = a[r];
       }
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int L = t + 1024 * q;
         const int k1c = L & 15, k2r = (L >> 4) & 7, k1r = L >> 7;
-        const float2* base = lds + (8 * k1r + k2r) * LP + 8 * k1c;
         float2 a[8];
 #pragma unroll
         for (int c = 0; c < 8; c += 2) {
-          float4 x = *reinterpret_cast<const float4*>(base + c);
+          float4 x = *reinterpret_cast<const float4*>(lds + at(8 * k1r + k2r, 8 * k1c + c));
           a[c] = make_float2(x.x, x.y);
           a[c + 1] = make_float2(x.z, x.w);
         }
@@ -303,18 +316,16 @@ struct Frame {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int b = t + 64 * q, k1c = b & 15, k1r = b >> 4;
-        float2* base = lds + (2 * k1r) * LP + 2 * k1c;
         float2 a00 = v[4 * q + 0], a01 = v[4 * q + 1], a10 = v[4 * q + 2], a11 = v[4 * q + 3];
         dft2<true>(a00, a01);
         dft2<true>(a10, a11);
         dft2<true>(a00, a10);
         dft2<true>(a01, a11);
-        *reinterpret_cast<float4*>(base) = make_float4(a00.x, a00.y, a01.x, a01.y);
-        *reinterpret_cast<float4*>(base + LP) = make_float4(a10.x, a10.y, a11.x, a11.y);
+        *reinterpret_cast<float4*>(lds + at(2 * k1r, 2 * k1c)) = make_float4(a00.x, a00.y, a01.x, a01.y);
+        *reinterpret_cast<float4*>(lds + at(2 * k1r + 1, 2 * k1c)) = make_float4(a10.x, a10.y, a11.x, a11.y);
       }
     } else if constexpr (P == 64) {
       const int k1c = t & 15, k1r = t >> 4;
-      float2* base = lds + (4 * k1r) * LP + 4 * k1c;
       float2 a[16];
 #pragma unroll
       for (int e = 0; e < 16; ++e) a[e] = v[e];
@@ -324,9 +335,9 @@ struct Frame {
       for (int c = 0; c < 4; ++c) dft4<true>(a[c], a[4 + c], a[8 + c], a[12 + c]);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        *reinterpret_cast<float4*>(base + r * LP) =
+        *reinterpret_cast<float4*>(lds + at(4 * k1r + r, 4 * k1c)) =
             make_float4(a[4 * r].x, a[4 * r].y, a[4 * r + 1].x, a[4 * r + 1].y);
-        *reinterpret_cast<float4*>(base + r * LP + 2) =
+        *reinterpret_cast<float4*>(lds + at(4 * k1r + r, 4 * k1c + 2)) =
             make_float4(a[4 * r + 2].x, a[4 * r + 2].y, a[4 * r + 3].x, a[4 * r + 3].y);
       }
     } else {
@@ -334,27 +345,26 @@ struct Frame {
       for (int q = 0; q < 2; ++q) {
         const int L = t + 1024 * q;
         const int k1c = L & 15, k2r = (L >> 4) & 7, k1r = L >> 7;
-        float2* base = lds + (8 * k1r + k2r) * LP + 8 * k1c;
         float2 a[8];
 #pragma unroll
         for (int c = 0; c < 8; ++c) a[c] = v[8 * q + c];
         dft8<true>(a);
 #pragma unroll
         for (int c = 0; c < 8; c += 2)
-          *reinterpret_cast<float4*>(base + c) = make_float4(a[c].x, a[c].y, a[c + 1].x, a[c + 1].y);
+          *reinterpret_cast<float4*>(lds + at(8 * k1r + k2r, 8 * k1c + c)) =
+              make_float4(a[c].x, a[c].y, a[c + 1].x, a[c + 1].y);
       }
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int L = t + 1024 * q;
         const int c2 = L & 7, k1c = (L >> 3) & 15, k1r = L >> 7;
-        float2* base = lds + (8 * k1r) * LP + 8 * k1c + c2;
         float2 a[8];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) a[r] = base[r * LP];
+        for (int r = 0; r < 8; ++r) a[r] = lds[at(8 * k1r + r, 8 * k1c + c2)];
         dft8<true>(a);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) base[r * LP] = a[r];
+        for (int r = 0; r < 8; ++r) lds[at(8 * k1r + r, 8 * k1c + c2)] = a[r];
       }
     }
   }

@@ -43,8 +43,8 @@ __device__ __forceinline__ int sweep_frame(int32_t chunk, int32_t J, const int32
 template <int P, bool BLIND, bool STATS>
 __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
   using F = Frame<P>;
-  __shared__ float2 lds[F::LDS];
-  __shared__ float2 twl[F::N2 * 16];   // stage-B twiddles, read from LDS so that no
+  __shared__ __align__(16) float2 lds[F::LDS];
+  __shared__ __align__(16) float2 twl[F::N2 * TWL];   // stage-B twiddles, read from LDS so that no
                                        // wait on them also waits on the prefetches
   __shared__ double red[F::T / 64];
   const int j = sweep_frame(a.chunk, a.J, a.order, a.xcd_slice);
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
   }
   // the stage-B twiddles go to LDS after the gather's loads are issued, so waiting for
   // this copy overlaps their latency; visible after the first barrier of forward_bc
-  if (t < F::N2 * 16) twl[t] = a.tw[t];
+  if (t < F::N2 * 16) twl[(t >> 4) * TWL + (t & 15)] = a.tw[t];
   F::forward_a(v, lds, a.tw, t);
   // The thread's amplitudes (and, for P <= 64, multipliers) are fetched now, while
   // stages B and C run: between stages A and C the thread holds no frame data in
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
     if (PRE >= 1) spre[e] = a.sqrt_f[fbase + kr * P + kc];
     if (PRE >= 2) gpre[e] = a.gamma[fbase + kr * P + kc];
   }
-  F::forward_bc(v, lds, twl, t);
+  F::template forward_bc<TWL>(v, lds, twl, t);
 
   // all 16 multipliers are read before any is written back, so the loads are in
   // flight together (the stores could otherwise alias later loads for the compiler)
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
     }
   }
   __syncthreads();  // stage-C reads of all threads done before inverse writes reuse LDS
-  F::inverse(v, lds, twl, t);
+  F::template inverse<TWL>(v, lds, twl, t);
   // the inverse returns each thread's 16 points to the positions it gathered; the 16
   // probe values are read before any output is written, so they are in flight together
   if (!BLIND) {
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(Frame<P>::T) void k_forward(const float2* __restric
                                                          const int32_t* __restrict__ off,
                                                          float2* __restrict__ out) {
   using F = Frame<P>;
-  __shared__ float2 lds[F::LDS];
+  __shared__ __align__(16) float2 lds[F::LDS];
   const int j = blockIdx.x, t = threadIdx.x;
   const int col = F::a_col(t), r2 = F::a_r2(t);
   const int64_t base = (int64_t)off[2 * j] * W + off[2 * j + 1];
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(Frame<P>::T) void k_adjoint(const float2* __restric
                                                          const int32_t* __restrict__ off,
                                                          float2* __restrict__ u, int W) {
   using F = Frame<P>;
-  __shared__ float2 lds[F::LDS];
+  __shared__ __align__(16) float2 lds[F::LDS];
   const int j = blockIdx.x, t = threadIdx.x;
   float2 v[16];
 #pragma unroll

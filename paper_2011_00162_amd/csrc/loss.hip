@@ -19,8 +19,8 @@ namespace odp {
 template <int P, bool GRAD>
 __global__ __launch_bounds__(Frame<P>::T) void k_loss(LossArgs a) {
   using F = Frame<P>;
-  __shared__ float2 lds[F::LDS];
-  __shared__ float2 twl[F::N2 * 16];   // stage-B twiddles in LDS (no global-load waits)
+  __shared__ __align__(16) float2 lds[F::LDS];
+  __shared__ __align__(16) float2 twl[F::N2 * TWL];   // stage-B twiddles in LDS (no global-load waits)
   __shared__ double red[F::T / 64];
   const int j = blockIdx.x, t = threadIdx.x;
   const int col = F::a_col(t), r2 = F::a_r2(t);
@@ -34,9 +34,9 @@ __global__ __launch_bounds__(Frame<P>::T) void k_loss(LossArgs a) {
   }
   // the stage-B twiddles go to LDS after the gather's loads are issued, so waiting for
   // this copy overlaps their latency; visible after the first barrier of forward_bc
-  if (t < F::N2 * 16) twl[t] = a.tw[t];
+  if (t < F::N2 * 16) twl[(t >> 4) * TWL + (t & 15)] = a.tw[t];
   F::forward_a(v, lds, a.tw, t);
-  F::forward_bc(v, lds, twl, t);
+  F::template forward_bc<TWL>(v, lds, twl, t);
   double loss = 0.0;
   const size_t fbase = (size_t)j * P * P;
 #pragma unroll
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(Frame<P>::T) void k_loss(LossArgs a) {
   if (t == 0) a.frame_loss[j] = loss;
   if (!GRAD) return;
   __syncthreads();
-  F::inverse(v, lds, twl, t);
+  F::template inverse<TWL>(v, lds, twl, t);
 #pragma unroll
   for (int r1 = 0; r1 < 16; ++r1) a.phi[fbase + (F::N2 * r1 + r2) * P + col] = v[r1];
 }
