@@ -171,8 +171,8 @@ __global__ __launch_bounds__(256, WGS_PER_CU) void k_sweep_dft64(SweepArgs a, Df
   }
 
   for (; pos < pos_end; pos += step) {
-    const int j = a.order[pos];
-    const FrameDesc fd = a.frames[j];
+    const FrameDesc fd = a.fpos[pos];
+    const int j = fd.j;
     const size_t woff = (size_t)(a.w_per_sub ? fd.sub : fd.probe) * DP * DP;
     const float2* wp = a.w + woff;
     const size_t fbase = (size_t)j * DP * DP;

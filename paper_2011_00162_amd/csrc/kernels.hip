@@ -22,14 +22,13 @@ __device__ __forceinline__ void atomic_add_c(float2* p, float2 v) {
   unsafeAtomicAdd(&p->y, v.y);
 }
 
-__device__ __forceinline__ int sweep_frame(int32_t chunk, int32_t J, const int32_t* order, int xcd_slice) {
+__device__ __forceinline__ int sweep_pos(int32_t chunk, int xcd_slice) {
   // XCD-aware slicing: workgroup b runs on XCD b % 8; each XCD takes a
   // contiguous slice of the subdomain-grouped frame order, so neighbouring
   // windows (which share image patches) share one L2.  The autotuner may pick
   // the plain order instead.
   const int b = blockIdx.x;
-  const int pos = xcd_slice ? (b % NXCD) * chunk + b / NXCD : b;
-  return pos < J ? order[pos] : -1;
+  return xcd_slice ? (b % NXCD) * chunk + b / NXCD : b;
 }
 
 // ---------------------------------------------------------------------------
@@ -47,10 +46,11 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
   __shared__ __align__(16) float2 twl[F::N2 * TWL];   // stage-B twiddles, read from LDS so that no
                                        // wait on them also waits on the prefetches
   __shared__ double red[F::T / 64];
-  const int j = sweep_frame(a.chunk, a.J, a.order, a.xcd_slice);
-  if (j < 0) return;  // uniform over the workgroup
+  const int pos = sweep_pos(a.chunk, a.xcd_slice);
+  if (pos >= a.J) return;  // uniform over the workgroup
   const int t = threadIdx.x;
-  const FrameDesc fd = a.frames[j];
+  const FrameDesc fd = a.fpos[pos];
+  const int j = fd.j;
   const size_t woff = (size_t)(a.w_per_sub ? fd.sub : fd.probe) * P * P;
   const float2* w = a.w + woff;
   const int col = F::a_col(t), r2 = F::a_r2(t);

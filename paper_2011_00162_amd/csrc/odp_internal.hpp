@@ -52,7 +52,7 @@ struct FrameDesc {
   int32_t pitch;             // row pitch of that subdomain
   int32_t sub;               // subdomain id
   int32_t probe;             // probe index (one probe per problem of a batch)
-  int32_t pad;
+  int32_t j;                 // frame id
 };
 
 // ---------------------------------------------------------------- launch args
@@ -66,6 +66,7 @@ struct SweepArgs {
   const float* sqrt_f;       // [J][p][p]
   const FrameDesc* frames;
   const int32_t* order;      // frame processing order (grouped by subdomain)
+  const FrameDesc* fpos;     // frames[order[pos]] by position pos (one load per frame)
   int32_t J, chunk;          // frames, frames per XCD slice
   int32_t xcd_slice;         // 1: workgroup b takes slice b % 8 of the order; 0: order[b]
   float eps, eta;

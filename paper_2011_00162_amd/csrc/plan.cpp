@@ -106,7 +106,7 @@ struct odp_plan {
   int32_t chunk = 0;
   // workspace layout (byte offsets)
   struct {
-    size_t tw, w, frames, order, sub_first, offsets, rects, usub_off, cells, tiles, waves, re_list, re_first,
+    size_t tw, w, frames, fpos, order, sub_first, offsets, rects, usub_off, cells, tiles, waves, re_list, re_first,
         tf_first, pull, den, rcp, fpart, tpart, stat_scratch, misc, pmax, psi, fmask, wpart, dft, bytes;
   } ws{};
   struct {
@@ -312,7 +312,7 @@ int build_geometry(odp_plan* P) {
     fd.base = P->usub_off[d] + (int64_t)(P->offsets[2 * j] - R[0]) * fd.pitch + (P->offsets[2 * j + 1] - R[1]);
     fd.sub = d;
     fd.probe = P->sub_problem[d];
-    fd.pad = 0;
+    fd.j = j;
     P->frames[j] = fd;
   }
   P->order.resize(J);
@@ -369,6 +369,7 @@ void layout(odp_plan* P) {
   P->ws.w = take(sizeof(float2) * pp * P->n_probes());
   P->ws.frames = take(sizeof(FrameDesc) * P->J);
   P->ws.order = take(sizeof(int32_t) * P->J);
+  P->ws.fpos = take(sizeof(FrameDesc) * P->J);
   P->ws.sub_first = take(sizeof(int32_t) * (P->D + 1));
   P->ws.offsets = take(sizeof(int32_t) * 2 * P->J);
   P->ws.rects = take(sizeof(int32_t) * 4 * P->D);
@@ -802,6 +803,9 @@ int odp_plan_bind(odp_plan* P, void* dev_ws, const float* dev_sqrt_f, const odp_
   ODP_HIP(hipMemcpyAsync(P->wsp + P->ws.w, dev_w, sizeof(float2) * pp * P->n_probes(), hipMemcpyDeviceToDevice, s));
   ODP_HIP(up(P->ws.frames, P->frames.data(), sizeof(FrameDesc) * P->frames.size()));
   ODP_HIP(up(P->ws.order, P->order.data(), sizeof(int32_t) * P->order.size()));
+  std::vector<FrameDesc> fpos(P->J);
+  for (int q = 0; q < P->J; ++q) fpos[q] = P->frames[P->order[q]];
+  ODP_HIP(up(P->ws.fpos, fpos.data(), sizeof(FrameDesc) * fpos.size()));
   ODP_HIP(up(P->ws.sub_first, P->sub_first.data(), sizeof(int32_t) * P->sub_first.size()));
   ODP_HIP(up(P->ws.offsets, P->offsets.data(), sizeof(int32_t) * P->offsets.size()));
   ODP_HIP(up(P->ws.rects, P->rects.data(), sizeof(int32_t) * P->rects.size()));
@@ -918,6 +922,7 @@ static SweepArgs sweep_args(const odp_plan* P, char* b, double* stats) {
   a.sqrt_f = P->sqrt_f;
   a.frames = P->W_<FrameDesc>(P->ws.frames);
   a.order = P->W_<int32_t>(P->ws.order);
+  a.fpos = P->W_<FrameDesc>(P->ws.fpos);
   a.J = P->J;
   a.chunk = P->chunk;
   a.xcd_slice = P->xcd_slice;
