@@ -114,7 +114,8 @@ __device__ __forceinline__ void dft16(float2* v) {
 #pragma unroll
   for (int k1 = 1; k1 < 4; ++k1)
 #pragma unroll
-    for (int n2 = 1; n2 < 4; ++n2) v[4 * k1 + n2] = c_tw<INV>(v[4 * k1 + n2], w16(n2 * k1));
+    for (int n2 = 1; n2 < 4; ++n2)   // W16^4 = -i is a swap (a multiply by 0 would not fold away)
+      v[4 * k1 + n2] = n2 * k1 == 4 ? c_rot<INV>(v[4 * k1 + n2]) : c_tw<INV>(v[4 * k1 + n2], w16(n2 * k1));
 #pragma unroll
   for (int k1 = 0; k1 < 4; ++k1) dft4<INV>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
   // v[4 k1 + k2] = X[k1 + 4 k2]: transpose to natural order
