@@ -372,3 +372,178 @@ struct Frame {
 };
 
 }  // namespace odp
+
+namespace odp {
+
+// p = 128 with 512 threads and the LDS exchanges done one half of the frame at a time.
+// The same factorisation as Frame<128> (radix 16 x 8 per axis), but each thread holds
+// 32 values: two stage-A lines (column col = t % 128, r2 = g and g + 4, g = t / 128),
+// and the frame passes through a 64-row LDS buffer in two halves (rows 64h .. 64h + 63
+// hold the stage-A outputs k1 in [8h, 8h + 8)).  Stages B and C of one half need only
+// that half, and the elementwise prox can run on a half's frequencies at once, so the
+// sweep does forward B/C, prox and inverse C/B per half; only stage A (and its inverse)
+// needs both halves, and it runs in registers.  77 KB of LDS per frame lets two frames
+// share a CU, which overlaps one frame's memory phases with the other's arithmetic.
+//
+// Register slots v[0..31]:
+//   spatial:   v[16 l + r1] = x(row 8 r1 + g + 4 l, col)            l = 0, 1
+//   stage A:   v[16 l + k1] = line l after the radix-16 DFT and twiddle
+//   frequency: v[16 q + 8 h + k2c] = X(kr, kc), see freq(); half h occupies the slots
+//              its stage-A outputs left (8h .. 8h + 7 and 16 + 8h .. 16 + 8h + 7)
+struct Half128 {
+  static constexpr int P = 128, N2 = 8, T = 512;
+  static constexpr int LP = 152;                   // row pitch (complex), as Frame<128>
+  static constexpr int ROWS = 64;                  // rows per half
+  static constexpr int LDS = ROWS * LP;
+  __device__ static __forceinline__ int at(int row, int col) { return row * LP + col + 2 * (col >> 4); }
+  __device__ static __forceinline__ int a_col(int t) { return t & 127; }
+  __device__ static __forceinline__ int uniform_g(int t) { return __builtin_amdgcn_readfirstlane(t >> 7); }
+  // image row of spatial slot e (column a_col(t))
+  __device__ static __forceinline__ int row_of(int t, int e) { return 8 * (e & 15) + (t >> 7) + 4 * (e >> 4); }
+
+  // natural frequency (kr, kc) of slot e after the forward transform
+  __device__ static __forceinline__ void freq(int t, int e, int& kr, int& kc) {
+    const int q = e >> 4, h = (e >> 3) & 1, k2c = e & 7;
+    const int L = t + 512 * q;
+    const int k1c = L & 15, k2r = (L >> 4) & 7, k1r = 8 * h + (L >> 7);
+    kr = k1r + 16 * k2r;
+    kc = k1c + 16 * k2c;
+  }
+
+  // stage A of line l in registers (tw: [8][16] table W_128^{i k}, global; the row
+  // is wavefront-uniform, so the twiddles come through scalar loads)
+  __device__ static __forceinline__ void stage_a_fwd_line(float2* v, const float2* __restrict__ tw, int t, int l) {
+    const float2* ta = tw + 16 * (uniform_g(t) + 4 * l);
+    dft16<false>(v + 16 * l);
+#pragma unroll
+    for (int k = 1; k < 16; ++k) v[16 * l + k] = c_mul(v[16 * l + k], ta[k]);
+  }
+  __device__ static __forceinline__ void stage_a_inv_line(float2* v, const float2* __restrict__ tw, int t, int l) {
+    const float2* ta = tw + 16 * (uniform_g(t) + 4 * l);
+#pragma unroll
+    for (int k = 1; k < 16; ++k) v[16 * l + k] = c_mulc(v[16 * l + k], ta[k]);
+    dft16<true>(v + 16 * l);
+  }
+
+  // half h forward: stage-A outputs of the half into LDS, stages B and C, frequencies
+  // back into the same slots.  Starts with a barrier (the LDS buffer may still be read
+  // by the previous half); ends after the stage-C reads (no barrier).
+  template <int TS>
+  __device__ static __forceinline__ void half_fwd(float2* v, float2* lds, const float2* __restrict__ twl, int t,
+                                                  int h) {
+    const int col = a_col(t), g = t >> 7;
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < 2; ++l)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) lds[at(8 * k + g + 4 * l, col)] = v[16 * l + 8 * h + k];
+    __syncthreads();
+    stage_b<false, TS>(lds, twl, t);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {   // stage C, DFT8 over r2 of lines (k1r, k1c, c2)
+      const int L = t + 512 * q;
+      const int c2 = L & 7, k1c = (L >> 3) & 15, k1r = L >> 7;
+      float2 a[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) a[r] = lds[at(8 * k1r + r, 8 * k1c + c2)];
+      dft8<false>(a);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) lds[at(8 * k1r + r, 8 * k1c + c2)] = a[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {   // stage C, DFT8 over c2 of lines (k1r, k2r, k1c)
+      const int L = t + 512 * q;
+      const int k1c = L & 15, k2r = (L >> 4) & 7, k1r = L >> 7;
+      float2 a[8];
+#pragma unroll
+      for (int c = 0; c < 8; c += 2) {
+        const float4 x = *reinterpret_cast<const float4*>(lds + at(8 * k1r + k2r, 8 * k1c + c));
+        a[c] = make_float2(x.x, x.y);
+        a[c + 1] = make_float2(x.z, x.w);
+      }
+      dft8<false>(a);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) v[16 * q + 8 * h + c] = a[c];
+    }
+  }
+
+  // half h inverse: the exact reverse, ending with the stage-A inputs of the half back
+  // in their slots.  Starts with a barrier (the stage-C reads of the forward half);
+  // ends after the final LDS reads (no barrier).
+  template <int TS>
+  __device__ static __forceinline__ void half_inv(float2* v, float2* lds, const float2* __restrict__ twl, int t,
+                                                  int h) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int L = t + 512 * q;
+      const int k1c = L & 15, k2r = (L >> 4) & 7, k1r = L >> 7;
+      float2 a[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) a[c] = v[16 * q + 8 * h + c];
+      dft8<true>(a);
+#pragma unroll
+      for (int c = 0; c < 8; c += 2)
+        *reinterpret_cast<float4*>(lds + at(8 * k1r + k2r, 8 * k1c + c)) =
+            make_float4(a[c].x, a[c].y, a[c + 1].x, a[c + 1].y);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int L = t + 512 * q;
+      const int c2 = L & 7, k1c = (L >> 3) & 15, k1r = L >> 7;
+      float2 a[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) a[r] = lds[at(8 * k1r + r, 8 * k1c + c2)];
+      dft8<true>(a);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) lds[at(8 * k1r + r, 8 * k1c + c2)] = a[r];
+    }
+    __syncthreads();
+    stage_b<true, TS>(lds, twl, t);
+    __syncthreads();
+    const int col = a_col(t), g = t >> 7;
+#pragma unroll
+    for (int l = 0; l < 2; ++l)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[16 * l + 8 * h + k] = lds[at(8 * k + g + 4 * l, col)];
+  }
+
+  // stage B on the 64 rows of a half: thread t takes row t / 8 and c2 = t % 8 (the
+  // same column lines as Frame<128>, twiddle rows TS apart).  The twiddles are read
+  // where they are applied (after the DFT forward, before it inverse), so they never
+  // sit in registers across the butterfly.
+  template <bool INV, int TS>
+  __device__ static __forceinline__ void stage_b(float2* lds, const float2* __restrict__ tw, int t) {
+    const int c2 = t & 7, R = t >> 3;
+    const float4* tb4 = reinterpret_cast<const float4*>(tw + TS * c2);
+    float2 v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = lds[at(R, c2 + 8 * k)];
+    if (INV) {
+#pragma unroll
+      for (int k = 0; k < 16; k += 2) {
+        const float4 q = tb4[k / 2];
+        if (k > 0) v[k] = c_mulc(v[k], make_float2(q.x, q.y));
+        v[k + 1] = c_mulc(v[k + 1], make_float2(q.z, q.w));
+      }
+      dft16<true>(v);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) lds[at(R, c2 + 8 * k)] = v[k];
+    } else {
+      dft16<false>(v);
+#pragma unroll
+      for (int k = 0; k < 16; k += 2) {
+        const float4 q = tb4[k / 2];
+        if (k > 0) v[k] = c_mul(v[k], make_float2(q.x, q.y));
+        v[k + 1] = c_mul(v[k + 1], make_float2(q.z, q.w));
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) lds[at(R, c2 + 8 * k)] = v[k];
+    }
+  }
+};
+
+}  // namespace odp

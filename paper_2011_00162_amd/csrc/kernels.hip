@@ -141,6 +141,133 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
   for (int r1 = 0; r1 < 16; ++r1) a.psi[fbase + (F::N2 * r1 + r2) * P + col] = v[r1];
 }
 
+// An empty instruction that takes x in registers and may change it: values computed
+// before it cannot be recomputed or moved after it.
+__device__ __forceinline__ void pin(float2& x) { asm volatile("" : "+v"(x.x), "+v"(x.y)); }
+
+// K1 at p = 128: the same step on the two-half transform (Half128: 512 threads,
+// 77 KB of LDS, two frames per CU).  The prox of each half runs between that half's
+// forward and inverse stages B and C.
+template <bool BLIND, bool STATS>
+__global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_sweep128(SweepArgs a, ProxC pc) {
+  using F = Half128;
+  constexpr int P = 128;
+  __shared__ __align__(16) float2 lds[F::LDS];
+  __shared__ __align__(16) float2 twl[F::N2 * TWL];
+  __shared__ double red[F::T / 64];
+  const int pos = sweep_pos(a.chunk, a.xcd_slice);
+  if (pos >= a.J) return;  // uniform over the workgroup
+  const int t = threadIdx.x;
+  const FrameDesc fd = a.fpos[pos];
+  const int j = fd.j;
+  const size_t woff = (size_t)(a.w_per_sub ? fd.sub : fd.probe) * P * P;
+  const float2* w = a.w + woff;
+  // per-frame scalar bases; the per-element offsets below are 32-bit (a window spans
+  // at most 128 rows of its subdomain, a frame 128 x 128 values)
+  const float2* ub = a.u + fd.base;
+  const size_t fbase = (size_t)j * P * P;
+  float2* gb = a.gamma + fbase;
+  const float* sb = a.sqrt_f + fbase;
+  float2* pb = a.psi + fbase;
+  const int col = F::a_col(t);
+  const float inv_p = 1.0f / (float)P;
+
+  // gather and stage A one line at a time; the second line's gather runs in groups of
+  // 8 rows, so the first line's transform and 16 products stay in registers without
+  // spilling
+  float2 v[32];
+#pragma unroll
+  for (int l = 0; l < 2; ++l) {
+#pragma unroll
+    for (int r0 = 0; r0 < 16; r0 += 8) {
+#pragma unroll
+      for (int r1 = r0; r1 < r0 + 8; ++r1) {
+        const int row = F::row_of(t, 16 * l + r1);
+        const uint32_t ob = 8u * (uint32_t)(row * fd.pitch + col);
+        v[16 * l + r1] = c_mul(*reinterpret_cast<const float2*>(reinterpret_cast<const char*>(ub) + ob),
+                               w[(uint32_t)(row * P + col)]);
+      }
+      if (l == 1) asm volatile("" ::: "memory");   // keep the next group's loads after these
+    }
+    // stage-B twiddles to LDS after the first line's loads are issued (visible after
+    // the first barrier of half_fwd)
+    if (l == 0 && t < F::N2 * 16) twl[(t >> 4) * TWL + (t & 15)] = a.tw[t];
+    F::stage_a_fwd_line(v, a.tw, t, l);
+    // the line's 16 outputs are complete here: the compiler may not sink parts of the
+    // butterfly past the first half (their intermediates would outnumber the outputs)
+#pragma unroll
+    for (int k = 0; k < 16; ++k) pin(v[16 * l + k]);
+    asm volatile("" ::: "memory");   // the second line's loads start after this transform
+  }
+
+  double mis = 0.0, gsum = 0.0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    F::half_fwd<TWL>(v, lds, twl, t, h);
+    // amplitudes and multipliers in two groups of 8 (each group's loads before its
+    // stores); the other frame on the CU computes meanwhile
+#pragma unroll
+    for (int qq = 0; qq < 2; ++qq) {
+      float2 gpre[8];
+      float spre[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        int kr, kc;
+        F::freq(t, 16 * qq + 8 * h + i, kr, kc);
+        spre[i] = sb[(uint32_t)(kr * P + kc)];
+        gpre[i] = gb[(uint32_t)(kr * P + kc)];
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int e = 16 * qq + 8 * h + i;
+        const float2 X = c_scale(v[e], inv_p);
+        const float sf = spre[i];
+        const float2 y = c_add(gpre[i], X);
+        const float2 z = prox_stagm(y, sf, pc);
+        const float2 g = c_sub(y, z);
+        gpre[i] = g;
+        v[e] = c_scale(c_sub(z, g), inv_p);   // both 1/p factors of the unitary pair applied here
+        if (STATS) {
+          const double ax = sqrt((double)X.x * X.x + (double)X.y * X.y);
+          mis += fabs(ax - (double)sf);
+          gsum += g_eps(ax, (double)sf, (double)a.eps);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        int kr, kc;
+        F::freq(t, 16 * qq + 8 * h + i, kr, kc);
+        gb[(uint32_t)(kr * P + kc)] = gpre[i];
+      }
+    }
+    F::half_inv<TWL>(v, lds, twl, t, h);
+  }
+  if (STATS) {
+    mis = block_sum<F::T>(mis, red);
+    gsum = block_sum<F::T>(gsum, red);
+    if (t == 0) {
+      a.part[2 * j] = mis;
+      a.part[2 * j + 1] = gsum;
+    }
+  }
+  // inverse stage A and the output one line at a time
+#pragma unroll
+  for (int l = 0; l < 2; ++l) {
+    asm volatile("" ::: "memory");   // one line's probe loads at a time
+    F::stage_a_inv_line(v, a.tw, t, l);
+    if (!BLIND) {
+      const float2* wo = a.w_out + woff;
+      float2 wk[16];
+#pragma unroll
+      for (int r1 = 0; r1 < 16; ++r1) wk[r1] = wo[(uint32_t)(F::row_of(t, 16 * l + r1) * P + col)];
+#pragma unroll
+      for (int r1 = 0; r1 < 16; ++r1) v[16 * l + r1] = c_mulc(v[16 * l + r1], wk[r1]);
+    }
+#pragma unroll
+    for (int r1 = 0; r1 < 16; ++r1) pb[(uint32_t)(F::row_of(t, 16 * l + r1) * P + col)] = v[16 * l + r1];
+  }
+}
+
 hipError_t launch_sweep(int p, const SweepArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const ProxC pc = prox_coeffs(a.eps, a.eta);
   const dim3 grid(NXCD * a.chunk);
@@ -157,7 +284,14 @@ hipError_t launch_sweep(int p, const SweepArgs& a, hipStream_t s, hipEvent_t ev0
   }
   ODP_SWEEP(32)
   ODP_SWEEP(64)
-  ODP_SWEEP(128)
+  if (p == 128) {
+    constexpr int T = Half128::T;
+    if (bl && st) ODP_SWEEP_GO((k_sweep128<true, true>), T);
+    else if (bl) ODP_SWEEP_GO((k_sweep128<true, false>), T);
+    else if (st) ODP_SWEEP_GO((k_sweep128<false, true>), T);
+    else ODP_SWEEP_GO((k_sweep128<false, false>), T);
+    return hipGetLastError();
+  }
 #undef ODP_SWEEP
 #undef ODP_SWEEP_GO
   return hipErrorInvalidValue;

@@ -123,6 +123,7 @@ STEP_CASES = [
     ("grid3x3_eta2", tiny_spec(n=160, p=32, step=8, jitter=2, dy=3, dx=3, radius=12, peak=1e4), 2.0),
     ("grid2x3_p64", tiny_spec(n=256, p=64, step=16, jitter=2, dy=2, dx=3, radius=24, peak=1e3), 0.1),
     ("narrow_blocks", tiny_spec(n=120, p=32, step=6, jitter=1, dy=2, dx=5, radius=12), 0.5),
+    ("grid2x2_p128", tiny_spec(n=256, p=128, step=32, jitter=2, dy=2, dx=2, radius=48, peak=1e3), 0.1),
 ]
 
 
