@@ -250,18 +250,25 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
       a.part[2 * j + 1] = gsum;
     }
   }
-  // inverse stage A and the output one line at a time
+  // inverse stage A and the output one line at a time; the second line's probe loads
+  // are issued before the first line's stores (see the prox above)
+  const float2* wo = a.w_out + woff;
+  float2 wk[2][16];
 #pragma unroll
   for (int l = 0; l < 2; ++l) {
-    asm volatile("" ::: "memory");   // one line's probe loads at a time
+    asm volatile("" ::: "memory");
     F::stage_a_inv_line(v, a.tw, t, l);
     if (!BLIND) {
-      const float2* wo = a.w_out + woff;
-      float2 wk[16];
+      if (l == 0) {
 #pragma unroll
-      for (int r1 = 0; r1 < 16; ++r1) wk[r1] = wo[(uint32_t)(F::row_of(t, 16 * l + r1) * P + col)];
+        for (int r1 = 0; r1 < 16; ++r1) wk[0][r1] = wo[(uint32_t)(F::row_of(t, r1) * P + col)];
+      }
 #pragma unroll
-      for (int r1 = 0; r1 < 16; ++r1) v[16 * l + r1] = c_mulc(v[16 * l + r1], wk[r1]);
+      for (int r1 = 0; r1 < 16; ++r1) v[16 * l + r1] = c_mulc(v[16 * l + r1], wk[l][r1]);
+      if (l == 0) {
+#pragma unroll
+        for (int r1 = 0; r1 < 16; ++r1) wk[1][r1] = wo[(uint32_t)(F::row_of(t, 16 + r1) * P + col)];
+      }
     }
 #pragma unroll
     for (int r1 = 0; r1 < 16; ++r1) pb[(uint32_t)(F::row_of(t, 16 * l + r1) * P + col)] = v[16 * l + r1];
