@@ -375,6 +375,11 @@ struct Frame {
 
 namespace odp {
 
+// An empty instruction that takes x in registers and may change it: values computed
+// before it cannot be recomputed or moved after it (used to keep the compiler from
+// sinking a butterfly's tail past later phases, where its intermediates would spill).
+__device__ __forceinline__ void pin(float2& x) { asm volatile("" : "+v"(x.x), "+v"(x.y)); }
+
 // p = 128 with 512 threads and the LDS exchanges done one half of the frame at a time.
 // The same factorisation as Frame<128> (radix 16 x 8 per axis), but each thread holds
 // 32 values: two stage-A lines (column col = t % 128, r2 = g and g + 4, g = t / 128),

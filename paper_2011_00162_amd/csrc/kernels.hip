@@ -141,10 +141,6 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
   for (int r1 = 0; r1 < 16; ++r1) a.psi[fbase + (F::N2 * r1 + r2) * P + col] = v[r1];
 }
 
-// An empty instruction that takes x in registers and may change it: values computed
-// before it cannot be recomputed or moved after it.
-__device__ __forceinline__ void pin(float2& x) { asm volatile("" : "+v"(x.x), "+v"(x.y)); }
-
 // K1 at p = 128: the same step on the two-half transform (Half128: 512 threads,
 // 77 KB of LDS, two frames per CU).  The prox of each half runs between that half's
 // forward and inverse stages B and C.

@@ -64,6 +64,89 @@ __global__ __launch_bounds__(Frame<P>::T) void k_loss(LossArgs a) {
   for (int r1 = 0; r1 < 16; ++r1) a.phi[fbase + (F::N2 * r1 + r2) * P + col] = v[r1];
 }
 
+// The same at p = 128 on the two-half transform (Half128: 512 threads, 77 KB of LDS,
+// two frames per CU): each half's frequencies are scored, scaled and sent back
+// through the inverse stages as soon as that half's forward stages end.
+template <bool GRAD>
+__global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_loss128(LossArgs a) {
+  using F = Half128;
+  constexpr int P = 128;
+  __shared__ __align__(16) float2 lds[F::LDS];
+  __shared__ __align__(16) float2 twl[F::N2 * TWL];
+  __shared__ double red[F::T / 64];
+  const int j = blockIdx.x, t = threadIdx.x;
+  const int col = F::a_col(t);
+  const int64_t base = (int64_t)a.offsets[2 * j] * a.W + a.offsets[2 * j + 1];
+  const float inv_p = 1.0f / (float)P;
+  // per-frame scalar bases, 32-bit element offsets (a window spans 128 image rows)
+  const char* ub = reinterpret_cast<const char*>(a.u + base);
+  const size_t fbase = (size_t)j * P * P;
+  const float* sb = a.sqrt_f + fbase;
+  float2* phib = a.phi + fbase;
+  float2 v[32];
+#pragma unroll
+  for (int l = 0; l < 2; ++l) {
+#pragma unroll
+    for (int r0 = 0; r0 < 16; r0 += 8) {
+#pragma unroll
+      for (int r1 = r0; r1 < r0 + 8; ++r1) {
+        const int row = F::row_of(t, 16 * l + r1);
+        const uint32_t ob = 8u * (uint32_t)(row * a.W + col);
+        v[16 * l + r1] = c_mul(*reinterpret_cast<const float2*>(ub + ob), a.w[(uint32_t)(row * P + col)]);
+      }
+      if (l == 1) asm volatile("" ::: "memory");   // keep the next group's loads after these
+    }
+    if (l == 0 && t < F::N2 * 16) twl[(t >> 4) * TWL + (t & 15)] = a.tw[t];
+    F::stage_a_fwd_line(v, a.tw, t, l);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) pin(v[16 * l + k]);
+    asm volatile("" ::: "memory");
+  }
+  double loss = 0.0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    F::half_fwd<TWL>(v, lds, twl, t, h);
+#pragma unroll
+    for (int qq = 0; qq < 2; ++qq) {   // two groups of 8, each finished before the next
+      float sfq[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        int kr, kc;
+        F::freq(t, 16 * qq + 8 * h + i, kr, kc);
+        sfq[i] = sb[(uint32_t)(kr * P + kc)];
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int e = 16 * qq + 8 * h + i;
+        const float2 X = c_scale(v[e], inv_p);
+        const float sf = sfq[i];
+        const float a2 = X.x * X.x + X.y * X.y;
+        const double ax = sqrt((double)a2);
+        loss += (ax - sf) * (ax - sf);
+        if (GRAD) {
+          const bool nz = a2 > 0.0f;
+          const float inv = nz ? __builtin_amdgcn_rsqf(a2) : 0.0f;
+          const float sc = nz ? 2.0f * (1.0f - sf * inv) : 0.0f;
+          v[e] = c_scale(X, sc * inv_p);
+        }
+        pin(v[e]);
+      }
+      asm volatile("" ::: "memory");
+    }
+    if (GRAD) F::half_inv<TWL>(v, lds, twl, t, h);
+  }
+  loss = block_sum<F::T>(loss, red);
+  if (t == 0) a.frame_loss[j] = loss;
+  if (!GRAD) return;
+#pragma unroll
+  for (int l = 0; l < 2; ++l) {
+    asm volatile("" ::: "memory");
+    F::stage_a_inv_line(v, a.tw, t, l);
+#pragma unroll
+    for (int r1 = 0; r1 < 16; ++r1) phib[(uint32_t)(F::row_of(t, 16 * l + r1) * P + col)] = v[16 * l + r1];
+  }
+}
+
 // dL/du on every subdomain tile: pull over all frames covering the pixel (every
 // slot of the tile's cell holds a disjoint set of frames).  Pixels in no
 // subdomain are covered by no frame and stay 0 (cleared by the caller).
@@ -139,6 +222,12 @@ hipError_t launch_loss(int p, const LossArgs& a, bool grad, hipStream_t s) {
   }
   ODP_LOSS(32)
   ODP_LOSS(64)
+  // p = 128: the loss alone on the two-half transform; with the gradient the per-element
+  // FP64 work and the inverse path spill on it (measured slower), so it keeps Frame<128>
+  if (p == 128 && !grad) {
+    hipLaunchKernelGGL((k_loss128<false>), dim3(a.J), dim3(Half128::T), 0, s, a);
+    return hipGetLastError();
+  }
   ODP_LOSS(128)
 #undef ODP_LOSS
   return hipErrorInvalidValue;
