@@ -62,6 +62,15 @@ def init_state(geom: Geometry, w0: np.ndarray) -> OD2BPState:
                       gamma=np.zeros((geom.J, p, p), dtype=np.complex128), lam=lam, v={})
 
 
+def initial_probe(sqrt_f: np.ndarray) -> np.ndarray:
+    """The initial probe of the blind tests (Sec. 4, extended tests, following the
+    reference it cites there): w0 = (1/J) sum_j F*(sqrt f_j), the mean over the frames
+    of the adjoint (inverse, F being unitary) transform of the amplitudes.
+    sqrt_f: [J][p][p] in natural frequency order."""
+    sf = np.asarray(sqrt_f, dtype=np.float64)
+    return np.mean(ops.ifft2(sf.astype(np.complex128)), axis=0)
+
+
 def project_support(x: np.ndarray, mask) -> np.ndarray:
     """P_O x = F^{-1}(M o F x); mask None is the identity."""
     if mask is None:

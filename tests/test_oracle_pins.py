@@ -502,3 +502,42 @@ def test_amplitude_loss_gradient_finite_difference():
     # at the truth the loss and both gradients vanish
     L0, gu0, gw0 = amploss.grad(ut, w, off, f)
     assert L0 < 1e-20 and np.abs(gu0).max() < 1e-10 and np.abs(gw0).max() < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# blind initial probe w0 = (1/J) sum_j F*(sqrt f_j)  (Sec. 4, extended tests)
+# ---------------------------------------------------------------------------
+
+def test_initial_probe_closed_forms():
+    p = 16
+    # constant amplitudes c: F* of a constant is c p at the origin, 0 elsewhere
+    w0 = blind.initial_probe(np.full((5, p, p), 2.5))
+    want = np.zeros((p, p), complex)
+    want[0, 0] = 2.5 * p
+    np.testing.assert_allclose(w0, want, atol=1e-12)
+    # one frame lit at frequency (a, b) only: a plane wave exp(+2 pi i (a x + b y) / p) / p;
+    # with a second frame of zeros the mean halves it
+    a, b = 3, 11
+    sf = np.zeros((2, p, p))
+    sf[0, a, b] = 1.0
+    y, x = np.meshgrid(np.arange(p), np.arange(p), indexing="ij")
+    want = 0.5 * np.exp(2j * np.pi * (a * y + b * x) / p) / p
+    np.testing.assert_allclose(blind.initial_probe(sf), want, atol=1e-12)
+
+
+def test_initial_probe_bruteforce_sum():
+    # the double sum over frames and frequencies written out, on a tiny case
+    rng = np.random.default_rng(3)
+    J, p = 3, 4
+    sf = rng.uniform(0.0, 2.0, (J, p, p))
+    want = np.zeros((p, p), complex)
+    for j in range(J):
+        for y in range(p):
+            for x in range(p):
+                acc = 0j
+                for ky in range(p):
+                    for kx in range(p):
+                        acc += sf[j, ky, kx] * np.exp(2j * np.pi * (ky * y + kx * x) / p)
+                want[y, x] += acc / p
+    want /= J
+    np.testing.assert_allclose(blind.initial_probe(sf), want, atol=1e-12)
