@@ -289,6 +289,17 @@ class Plan:
     def frame_sweep(self, state: State, stats: torch.Tensor | None = None, stream=None) -> None:
         check(lib().odp_frame_sweep(self._h, _ptr(state.buf), _ptr(stats), _stream(stream)))
 
+    def blind_initial_probe(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """w0 = (1/J) sum_j F*(sqrt f_j) from the bound amplitudes: [p, p], or [n, p, p] for
+        a batch plan (one per problem)."""
+        i = self.info
+        n = self.n_problems()
+        shape = (n, i.p, i.p) if n > 1 else (i.p, i.p)
+        out = torch.empty(shape, dtype=torch.complex64, device=self.workspace.device) if out is None else out
+        _c64(out, shape)
+        check(lib().odp_blind_initial_probe(self._h, _ptr(out), _stream(stream)))
+        return out
+
     def probe_update(self, state: State, stream=None) -> None:
         check(lib().odp_probe_update(self._h, _ptr(state.buf), _stream(stream)))
 

@@ -94,6 +94,65 @@ __global__ __launch_bounds__(256) void k_probe_copies(ProbeArgs a) {
   a.delta[o] = make_float2((float)((double)dl.x + wx - w.x), (float)((double)dl.y + wy - w.y));
 }
 
+// Initial probe of a blind run (Sec. 4, extended tests): w0 = (1/J) sum_j F^{-1}(sqrt f_j).
+// F^{-1} is linear, so the amplitudes are summed over the frames first (FP64, frames of a
+// chunk in order, then the chunks in order) and one unitary inverse transform follows.
+__global__ __launch_bounds__(256) void k_init_part(InitProbeArgs a) {
+  const int pp = a.p * a.p, k = blockIdx.x * 256 + threadIdx.x, c = blockIdx.y;
+  if (k >= pp) return;
+  const int j0 = c * a.frames_per_chunk, j1 = min(a.J, j0 + a.frames_per_chunk);
+  double s0 = 0.0, s1 = 0.0;   // two interleaved partial sums (even, odd frames), added in order
+  int j = j0;
+  for (; j + 1 < j1; j += 2) {
+    s0 += (double)a.sqrt_f[(size_t)j * pp + k];
+    s1 += (double)a.sqrt_f[(size_t)(j + 1) * pp + k];
+  }
+  if (j < j1) s0 += (double)a.sqrt_f[(size_t)j * pp + k];
+  a.part[(size_t)c * pp + k] = s0 + s1;
+}
+
+__global__ __launch_bounds__(256) void k_init_final(InitProbeArgs a) {
+  const int pp = a.p * a.p, k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= pp) return;
+  double s = 0.0;
+  for (int c = 0; c < a.n_chunks; ++c) s += a.part[(size_t)c * pp + k];
+  a.w[k] = make_float2((float)(s / (double)a.J), 0.0f);
+}
+
+// in place on w: every thread reads its 16 frequencies before the first barrier of the
+// inverse, and writes only after the last
+template <int P>
+__global__ __launch_bounds__(Frame<P>::T) void k_init_ifft(InitProbeArgs a) {
+  using F = Frame<P>;
+  __shared__ __align__(16) float2 lds[F::LDS];
+  const int t = threadIdx.x;
+  float2 v[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    int kr, kc;
+    F::freq(t, e, kr, kc);
+    v[e] = a.w[kr * P + kc];
+  }
+  F::inverse(v, lds, a.tw, t);
+  const int col = F::a_col(t), r2 = F::a_r2(t);
+  const float s = 1.0f / (float)P;   // unitary inverse
+#pragma unroll
+  for (int r1 = 0; r1 < 16; ++r1) a.w[(F::N2 * r1 + r2) * P + col] = c_scale(v[r1], s);
+}
+
+hipError_t launch_init_probe(const InitProbeArgs& a, hipStream_t s) {
+  const int pp = a.p * a.p;
+  hipLaunchKernelGGL(k_init_part, dim3((pp + 255) / 256, a.n_chunks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_init_final, dim3((pp + 255) / 256), dim3(256), 0, s, a);
+#define ODP_INIT(PP) \
+  if (a.p == PP) hipLaunchKernelGGL((k_init_ifft<PP>), dim3(1), dim3(Frame<PP>::T), 0, s, a);
+  ODP_INIT(32)
+  ODP_INIT(64)
+  ODP_INIT(128)
+#undef ODP_INIT
+  return hipGetLastError();
+}
+
 hipError_t launch_probe_update(const ProbeArgs& a, hipStream_t s) {
   const int pp = a.p * a.p;
   hipLaunchKernelGGL(k_probe_avg, dim3((pp + 255) / 256), dim3(256), 0, s, a);

@@ -171,6 +171,16 @@ struct ProbeArgs {
 };
 hipError_t launch_probe_update(const ProbeArgs& a, hipStream_t s);
 
+struct InitProbeArgs {       // w0 = (1/J) sum_j F^{-1}(sqrt f_j) of one problem
+  const float* sqrt_f;       // [J][p][p] of the problem's frames
+  int32_t J, p;
+  int32_t frames_per_chunk, n_chunks;
+  double* part;              // [n_chunks][p][p] partial sums
+  float2* w;                 // [p][p] out
+  const float2* tw;          // twiddle table of p
+};
+hipError_t launch_init_probe(const InitProbeArgs& a, hipStream_t s);
+
 struct LossArgs {
   const float2* u;           // image [H][W]
   int32_t H, W;

@@ -1002,6 +1002,27 @@ int odp_plan_set_sweep_events(odp_plan* P, const hipEvent_t* start, const hipEve
   return ODP_OK;
 }
 
+int odp_blind_initial_probe(const odp_plan* P, odp_c32* w_out, hipStream_t s) {
+  if (!P || !w_out) return fail(ODP_EINVAL, "null argument");
+  if (!P->wsp || !P->sqrt_f) return fail(ODP_EINVAL, "plan is not bound");
+  const size_t pp = (size_t)P->p * P->p;
+  for (int i = 0; i < P->n_probes(); ++i) {
+    const odp_plan::Entry& e = P->batch[i];
+    InitProbeArgs a;
+    a.sqrt_f = P->sqrt_f + (size_t)e.J0 * pp;
+    a.J = e.J;
+    a.p = P->p;
+    a.n_chunks = std::min(LOSS_CHUNKS, std::max(1, e.J));
+    a.frames_per_chunk = (e.J + a.n_chunks - 1) / a.n_chunks;
+    a.n_chunks = (e.J + a.frames_per_chunk - 1) / a.frames_per_chunk;
+    a.part = P->W_<double>(P->ws.wpart);   // 2 p^2 LOSS_CHUNKS doubles: room for every chunk
+    a.w = reinterpret_cast<float2*>(w_out) + i * pp;
+    a.tw = P->W_<float2>(P->ws.tw);
+    ODP_HIP(launch_init_probe(a, s));
+  }
+  return ODP_OK;
+}
+
 int odp_probe_update(odp_plan* P, void* dev_state, hipStream_t s) {
   if (!P || !dev_state) return fail(ODP_EINVAL, "null argument");
   if (!P->wsp) return fail(ODP_EINVAL, "plan is not bound");

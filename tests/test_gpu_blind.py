@@ -114,3 +114,36 @@ def test_blind_p128_parity():
     plan.iterate(st, 4)
     ost, _ = blind.od2bp_run(g, f, w0, P["eps"], P["eta"], P["r"], mu, 4, state=ost)
     check(ost, 1e-3)   # K-iteration reconstruction bound
+
+
+@pytest.mark.parametrize("n,p,step,rad", [(128, 32, 8, 12), (192, 64, 16, 24), (256, 128, 32, 48)], ids=["p32", "p64", "p128"])
+def test_initial_probe_matches_oracle(n, p, step, rad):
+    """w0 = (1/J) sum_j F*(sqrt f_j) (Sec. 4, extended tests) from the bound amplitudes."""
+    from tests.gpu_util import gpu_plan
+    from tests.oracle_problems import oracle_problem
+    spec = tiny_spec(n=n, p=p, step=step, jitter=2, dy=2, dx=2, radius=rad, peak=1e4)
+    say("initial probe", p)
+    P = oracle_problem(spec)
+    _, sf32, _ = rounded_inputs(P)
+    plan = gpu_plan(P, blind=True, mu=1.0)
+    got = host(plan.blind_initial_probe())
+    want = blind.initial_probe(sf32.astype(np.float64))
+    assert rel(got, want) <= 1e-5, rel(got, want)
+
+
+def test_initial_probe_per_problem_of_a_batch():
+    from tests.gpu_util import dev_f32
+    import paper_2011_00162_amd as odp
+    from tests.oracle_problems import oracle_problem
+    specs = [tiny_spec(n=128, p=32, step=8, jitter=1, dy=1, dx=2, radius=12, peak=1e4),
+             tiny_spec(n=160, p=32, step=8, jitter=2, dy=2, dx=2, radius=12, peak=1e3)]
+    Ps = [oracle_problem(s) for s in specs]
+    sfs = [rounded_inputs(P)[1] for P in Ps]
+    probs = [dict(H=s.n, W=s.n, p=s.p, offsets=P["pr"]["offsets"], frame_sub=P["pr"]["frame_sub"], r=1.0)
+             for s, P in zip(specs, Ps)]
+    plan = odp.Plan.batch(probs)
+    w = torch.stack([dev_c64(np.asarray(P["pr"]["w"])) for P in Ps])
+    plan.bind(dev_f32(np.concatenate(sfs)), w)
+    got = host(plan.blind_initial_probe())
+    for i, sf in enumerate(sfs):
+        assert rel(got[i], blind.initial_probe(sf.astype(np.float64))) <= 1e-5, i

@@ -174,3 +174,12 @@ def test_tuning_values_are_checked():
             assert L.odp_plan_set_tuning(plan._h, odp.ODP_FFT_F32, xcd, tiling, None) == 0   # unbound: host only
             t = plan.tuning()
             assert (t.xcd_slice, t.tiling, (t.tile_rows, t.tile_cols)) == (xcd, tiling, shape)
+
+
+def test_initial_probe_arguments_are_checked():
+    import ctypes as C
+    plan = odp.Plan(**_plan_args())
+    L = odp.lib()
+    assert L.odp_blind_initial_probe(None, C.c_void_p(0x1000), None) == ODP_EINVAL   # null plan
+    assert L.odp_blind_initial_probe(plan._h, None, None) == ODP_EINVAL              # null output
+    assert L.odp_blind_initial_probe(plan._h, C.c_void_p(0x1000), None) == ODP_EINVAL   # not bound
