@@ -138,6 +138,24 @@ def od2pm_run(geom, w, f, eps, eta, r, n_iter, state=None):
     return st, hist
 
 
+def run_until(step, st, measure: str | None, tol: float, max_iter: int):
+    """Step 5 of Algorithms 2 and 3 with the stopping rules of Sec. 4.
+
+    ``step(st) -> (st, stats)`` is one iteration; after each one the rule is checked on
+    the measures that iteration produced: ``stats["RF"]`` (of the iterate entering it, the
+    noise-free rule RF <= 1e-5) or ``stats["RE"]`` (of the iterate it returns, the noisy
+    rule RE <= 1e-3); the run also ends after ``max_iter`` iterations.  The output is the
+    last iterate.  Returns (state, per-iteration stats); len(stats) iterations ran.
+    """
+    hist = []
+    while len(hist) < max_iter:
+        st, s = step(st)
+        hist.append(s)
+        if measure is not None and s[measure] <= tol:
+            break
+    return st, hist
+
+
 def admm_undecomposed(shape, w, offsets, f, eps, eta, n_iter, u0=None, gamma0=None):
     """ADMM without domain decomposition (the D = 1 row of Table 1), written separately.
 

@@ -17,7 +17,7 @@ import synthetic
 from oracle import amploss, blind, operators as ops, stagm
 from oracle.geometry import build_geometry, cover_count, multiplicity, overlap_width, GeometryError
 from oracle.od2p import (admm_undecomposed, augmented_lagrangian, init_state, merge, od2pm_run,
-                         od2pm_step, forward_sub, adjoint_sub, subdomain_illumination, snr_db)
+                         od2pm_step, forward_sub, adjoint_sub, run_until, subdomain_illumination, snr_db)
 from tests.oracle_problems import oracle_problem, tiny_spec
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -541,3 +541,57 @@ def test_initial_probe_bruteforce_sum():
                 want[y, x] += acc / p
     want /= J
     np.testing.assert_allclose(blind.initial_probe(sf), want, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# T20  stopping rules (Sec. 4) at Step 5 of Algorithms 2 and 3
+# ---------------------------------------------------------------------------
+
+def _stepper(P):
+    g, w, f = P["geom"], P["pr"]["w"], P["f"]
+    den = [subdomain_illumination(g, w, d) for d in range(g.D)]
+    return lambda st: od2pm_step(g, w, f, st, P["eps"], P["eta"], P["r"], den=den)
+
+
+def test_stopping_rule_stops_at_first_iteration_meeting_tol():
+    P = oracle_problem(tiny_spec(dy=2, dx=2, n=32, step=4, peak=1e3))
+    g = P["geom"]
+    K = 16
+    ref, hist = od2pm_run(g, P["pr"]["w"], P["f"], P["eps"], P["eta"], P["r"], K)
+    re = np.array([h["RE"] for h in hist])
+    # a strict record low after a few iterations: every earlier RE is larger
+    lows = [m for m in range(3, K - 1) if re[m] < re[:m].min()]
+    assert lows, re
+    m = lows[len(lows) // 2]
+    st, h = run_until(_stepper(P), init_state(g), "RE", float(re[m]), K)
+    assert len(h) == m + 1                       # checked after the iteration, with <=
+    want, _ = od2pm_run(g, P["pr"]["w"], P["f"], P["eps"], P["eta"], P["r"], m + 1)
+    assert all(np.array_equal(a, b) for a, b in zip(st.u, want.u))
+    assert np.array_equal(st.gamma, want.gamma)
+    # just below that value the rule does not hold at m
+    _, h2 = run_until(_stepper(P), init_state(g), "RE", float(np.nextafter(re[m], 0.0)), K)
+    assert len(h2) > m + 1
+
+
+def test_stopping_rule_cap_and_no_rule():
+    P = oracle_problem(tiny_spec(dy=1, dx=2))
+    g = P["geom"]
+    _, h = run_until(_stepper(P), init_state(g), "RF", -1.0, 5)
+    assert len(h) == 5
+    _, h = run_until(_stepper(P), init_state(g), None, 0.0, 3)
+    assert len(h) == 3
+    _, h = run_until(_stepper(P), init_state(g), "RE", 1.0, 0)
+    assert h == []
+
+
+def test_paper_rules_stop_at_once_from_the_noise_free_truth():
+    # RF of the truth is 0 and the truth is a fixed point (RE = 0): both of the paper's
+    # rules (RF <= 1e-5 within 1000 iterations, RE <= 1e-3 within 200) hold after one
+    P = oracle_problem(tiny_spec(dy=2, dx=2, n=32, step=4))
+    g = P["geom"]
+    ut = P["pr"]["u_true"]
+    for measure, tol, cap in (("RF", 1e-5, 1000), ("RE", 1e-3, 200)):
+        st = init_state(g)
+        st.u = [ut[g.rects[d, 0]:g.rects[d, 2], g.rects[d, 1]:g.rects[d, 3]].copy() for d in range(g.D)]
+        _, h = run_until(_stepper(P), st, measure, tol, cap)
+        assert len(h) == 1 and h[0][measure] <= tol
