@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libodp.so")
 
 ODP_OK, ODP_EINVAL, ODP_EGEOM, ODP_EHIP, ODP_ENOMEM, ODP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 ODP_FFT_F32, ODP_DFT_SPLIT_BF16 = 0, 1
+ODP_STOP_NONE, ODP_STOP_RF, ODP_STOP_RE = 0, 1, 2
 
 # every symbol include/odp.h declares
 EXPORTS = [
@@ -23,7 +24,7 @@ EXPORTS = [
     "odp_pixel_update", "odp_merge", "odp_amp_loss", "odp_last_error", "odp_version",
     "odp_batch_plan_create", "odp_batch_get_entry", "odp_batch_set_penalties", "odp_plan_get_tuning",
     "odp_plan_set_tuning", "odp_plan_autotune", "odp_graph_create", "odp_graph_launch", "odp_graph_destroy",
-    "odp_plan_set_sweep_events",
+    "odp_plan_set_sweep_events", "odp_plan_set_stopping", "odp_state_get_stop_status",
 ]
 
 
@@ -53,7 +54,12 @@ class PlanInfo(C.Structure):
 
 
 class StateLayout(C.Structure):
-    _fields_ = [(n, C.c_size_t) for n in ("u_sub", "gamma", "lam", "w", "w_sub", "delta", "bytes")]
+    _fields_ = [(n, C.c_size_t) for n in ("u_sub", "gamma", "lam", "w", "w_sub", "delta", "stop", "bytes")]
+
+
+class StopStatus(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("stopped", C.c_int32), ("rf", C.c_double), ("re", C.c_double),
+                ("g", C.c_double)]
 
 
 class BatchEntry(C.Structure):
@@ -105,6 +111,8 @@ def lib() -> C.CDLL:
         "odp_batch_set_penalties": (C.c_int, [vp, vp, vp]),
         "odp_plan_get_tuning": (C.c_int, [vp, C.POINTER(Tuning)]),
         "odp_plan_set_tuning": (C.c_int, [vp, i32, i32, i32, vp]),
+        "odp_plan_set_stopping": (C.c_int, [vp, i32, C.c_double, i32]),
+        "odp_state_get_stop_status": (C.c_int, [vp, vp, vp, vp]),
         "odp_plan_autotune": (C.c_int, [vp, vp, i32, vp, C.POINTER(Tuning)]),
         "odp_graph_create": (C.c_int, [vp, vp, i32, i32, C.POINTER(vp)]),
         "odp_graph_launch": (C.c_int, [vp, vp]),

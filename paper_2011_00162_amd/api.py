@@ -9,7 +9,8 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from ._lib import (ODP_FFT_F32, BatchEntry, PlanInfo, Problem, StateLayout, Tuning, check, lib)
+from ._lib import (ODP_FFT_F32, ODP_STOP_NONE, BatchEntry, PlanInfo, Problem, StateLayout, StopStatus, Tuning,
+                   check, lib)
 
 
 def _stream(stream=None) -> C.c_void_p:
@@ -191,6 +192,18 @@ class Plan:
 
     def set_tuning(self, transform: int, xcd_slice: int, tiling: int, stream=None) -> None:
         check(lib().odp_plan_set_tuning(self._h, int(transform), int(xcd_slice), int(tiling), _stream(stream)))
+
+    def set_stopping(self, measure: int = ODP_STOP_NONE, tol: float = 0.0, max_iter: int = 0) -> None:
+        """Device-side stopping rule of Sec. 4 (ODP_STOP_RF / ODP_STOP_RE, tolerance,
+        iteration cap); applies to later iterations and graphs created afterwards."""
+        check(lib().odp_plan_set_stopping(self._h, int(measure), float(tol), int(max_iter)))
+
+    def stop_status(self, state: "State", stream=None) -> list[dict]:
+        """Per problem: iterations run, whether it stopped, and its last RF, RE, G."""
+        n = self.n_problems()
+        arr = (StopStatus * n)()
+        check(lib().odp_state_get_stop_status(self._h, _ptr(state.buf), C.cast(arr, C.c_void_p), _stream(stream)))
+        return [dict(iters=e.iters, stopped=bool(e.stopped), rf=e.rf, re=e.re, g=e.g) for e in arr]
 
     def autotune(self, scratch: "State", iters: int = 5, stream=None) -> Tuning:
         t = Tuning()

@@ -18,7 +18,7 @@ namespace odp {
 // (1/D) sum_d (w_d + Delta_d) per probe pixel, FP64 over d in ascending order
 __global__ __launch_bounds__(256) void k_probe_avg(ProbeArgs a) {
   const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= a.p * a.p) return;
+  if (k >= a.p * a.p || (a.stop && a.stop[0].stopped)) return;
   const size_t pp = (size_t)a.p * a.p;
   double sx = 0.0, sy = 0.0;
   for (int d = 0; d < a.D; ++d) {
@@ -36,6 +36,7 @@ template <int P>
 __global__ __launch_bounds__(Frame<P>::T) void k_probe_project(ProbeArgs a) {
   using F = Frame<P>;
   __shared__ __align__(16) float2 lds[F::LDS];
+  if (a.stop && a.stop[0].stopped) return;  // uniform over the workgroup
   const int t = threadIdx.x;
   const int col = F::a_col(t), r2 = F::a_r2(t);
   float2 v[16];
@@ -60,6 +61,7 @@ __global__ __launch_bounds__(Frame<P>::T) void k_probe_project(ProbeArgs a) {
 // partial sums are added in wavefront order.
 __global__ __launch_bounds__(256) void k_probe_copies(ProbeArgs a) {
   __shared__ double part[3][4][64];
+  if (a.stop && a.stop[0].stopped) return;  // uniform over the workgroup
   const int p = a.p, d = blockIdx.y, lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int k = blockIdx.x * 64 + lane;
   const bool ok = k < p * p;

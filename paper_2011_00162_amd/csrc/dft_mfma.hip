@@ -172,6 +172,7 @@ __global__ __launch_bounds__(256, WGS_PER_CU) void k_sweep_dft64(SweepArgs a, Df
 
   for (; pos < pos_end; pos += step) {
     const FrameDesc fd = a.fpos[pos];
+    if (a.stop && a.stop[fd.probe].stopped) continue;   // its problem met its stopping rule
     const int j = fd.j;
     const size_t woff = (size_t)(a.w_per_sub ? fd.sub : fd.probe) * DP * DP;
     const float2* wp = a.w + woff;

@@ -50,6 +50,7 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
   if (pos >= a.J) return;  // uniform over the workgroup
   const int t = threadIdx.x;
   const FrameDesc fd = a.fpos[pos];
+  if (a.stop && a.stop[fd.probe].stopped) return;   // its problem met its stopping rule
   const int j = fd.j;
   const size_t woff = (size_t)(a.w_per_sub ? fd.sub : fd.probe) * P * P;
   const float2* w = a.w + woff;
@@ -155,6 +156,7 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
   if (pos >= a.J) return;  // uniform over the workgroup
   const int t = threadIdx.x;
   const FrameDesc fd = a.fpos[pos];
+  if (a.stop && a.stop[fd.probe].stopped) return;   // its problem met its stopping rule
   const int j = fd.j;
   const size_t woff = (size_t)(a.w_per_sub ? fd.sub : fd.probe) * P * P;
   const float2* w = a.w + woff;
@@ -511,6 +513,49 @@ __global__ void k_stats_final(const double* scratch, int D, const double* sum_sf
   out3[0] = scratch[2 * D] / sum_sf[0];
   out3[1] = re;
   out3[2] = scratch[2 * D + 1];
+}
+
+// end of an iteration under a stopping rule (Sec. 4): per problem, its measures and the
+// rule; problems already stopped keep their status
+__global__ __launch_bounds__(256) void k_stop_check(StopArgs a) {
+  __shared__ double sh[4];
+  const int i = blockIdx.x;
+  StopStatus* st = a.status + i;
+  if (st->stopped) return;  // uniform over the workgroup
+  const int J0 = a.prob[4 * i], J = a.prob[4 * i + 1], D0 = a.prob[4 * i + 2], D = a.prob[4 * i + 3];
+  double s0 = 0.0, s1 = 0.0;
+  for (int k = threadIdx.x; k < J; k += 256) {
+    s0 += a.frame_part[2 * (size_t)(J0 + k)];
+    s1 += a.frame_part[2 * (size_t)(J0 + k) + 1];
+  }
+  s0 = block_sum<256>(s0, sh);
+  s1 = block_sum<256>(s1, sh);
+  if (threadIdx.x != 0) return;
+  double re = 0.0;
+  for (int d = D0; d < D0 + D; ++d) {
+    const double num = a.sub_sums[2 * d], den = a.sub_sums[2 * d + 1];
+    re = fmax(re, den > 0.0 ? sqrt(num / den) : 0.0);
+  }
+  const double rf = s0 / a.sum_sf[(size_t)i * a.sum_sf_stride];
+  const int it = st->iters + 1;
+  const double m = a.measure == 1 ? rf : re;
+  const bool met = a.measure != 0 && m <= a.tol;   // false for NaN
+  st->iters = it;
+  st->rf = rf;
+  st->re = re;
+  st->g = s1;
+  st->stopped = (met || (a.max_iter > 0 && it >= a.max_iter)) ? 1 : 0;
+}
+
+hipError_t launch_stop_check(const StopArgs& a, const double* tile_part, const int32_t* re_list,
+                             const int32_t* re_first, int D, double* scratch, hipStream_t s) {
+  // per-subdomain (|du|^2, |u|^2) into scratch (blocks [0, D) of the statistics reduction)
+  hipLaunchKernelGGL(k_stats_reduce, dim3(D), dim3(256), 0, s, a.frame_part, 0, tile_part, re_list, re_first, D,
+                     scratch);
+  StopArgs b = a;
+  b.sub_sums = scratch;
+  hipLaunchKernelGGL(k_stop_check, dim3(a.n), dim3(256), 0, s, b);
+  return hipGetLastError();
 }
 
 hipError_t launch_stats(const double* frame_part, int J, const double* tile_part, const int32_t* re_list,

@@ -55,6 +55,15 @@ struct FrameDesc {
   int32_t j;                 // frame id
 };
 
+// Per-problem progress under a stopping rule (Sec. 4), kept in the state buffer;
+// layout identical to odp_stop_status.
+struct StopStatus {
+  int32_t iters;             // iterations run
+  int32_t stopped;           // 1 once the rule or the iteration cap was met
+  double rf, re, g;          // measures of the last iteration run
+};
+static_assert(sizeof(StopStatus) == 32, "StopStatus layout");
+
 // ---------------------------------------------------------------- launch args
 struct SweepArgs {
   const float2* u;           // u_sub
@@ -74,6 +83,7 @@ struct SweepArgs {
   float2* psi;               // [J][p][p] per-frame output, natural spatial layout:
                              //   non-blind conj(w) o F^{-1}(z - Gamma), blind F^{-1}(z - Gamma)
   int blind;
+  const StopStatus* stop;    // [n_problems] or null: frames of stopped problems are skipped
 };
 
 // One wavefront's share of a pixel-update tile whose cell has at most four copies
@@ -92,7 +102,7 @@ struct WaveRec {
   int64_t lo0[3];            // Lam_{s,t} index of the top-left (written by this copy)
   int64_t lt0[3];            // Lam_{t,s} index of the top-left
   int32_t upitch, pupitch[3], lpitch[3];
-  int32_t pad;
+  int32_t prob;              // problem of the tile (batch index; 0 for a single problem)
 };
 static_assert(sizeof(WaveRec) == 160, "WaveRec layout");
 
@@ -111,6 +121,7 @@ struct PixelArgs {
   const float2* w_sub;       // blind: probe copies (the illumination is formed in the pull)
   float eta, gamma;          // (r is per cell)
   double* part;              // [n_tiles][MAXS][2] (|du|^2, |u|^2) or null
+  const StopStatus* stop;    // [n_problems] or null: tiles of stopped problems are skipped
 };
 
 struct IllumArgs {           // den and rcp on every subdomain pixel
@@ -168,8 +179,26 @@ struct ProbeArgs {
   const float* fmask;        // [p][p] support indicator or null
   const float2* tw;
   double eta, mu;
+  const StopStatus* stop;    // [1] or null: nothing is done once the problem has stopped
 };
 hipError_t launch_probe_update(const ProbeArgs& a, hipStream_t s);
+
+// One iteration's end under a stopping rule: per problem i (one workgroup each, skipped
+// once stopped) RF_i from its frames' partials and its sum of sqrt f, RE_i as the max
+// over its subdomains of sqrt(|du|^2 / |u|^2), G_i; then iters_i += 1 and the rule.
+struct StopArgs {
+  const double* frame_part;  // [J][2] (L1 misfit, G_eps) of the sweep
+  const double* sub_sums;    // [D][2] (|du|^2, |u|^2) per subdomain (k_stats_reduce)
+  const int32_t* prob;       // [n][4] = (J0, J, D0, D)
+  const double* sum_sf;      // problem i's sum of sqrt f at sum_sf[i * sum_sf_stride]
+  int32_t sum_sf_stride, n;
+  int32_t measure;           // 0 none, 1 RF, 2 RE
+  int32_t max_iter;          // 0: no cap
+  double tol;
+  StopStatus* status;        // [n]
+};
+hipError_t launch_stop_check(const StopArgs& a, const double* tile_part, const int32_t* re_list,
+                             const int32_t* re_first, int D, double* scratch, hipStream_t s);
 
 struct InitProbeArgs {       // w0 = (1/J) sum_j F^{-1}(sqrt f_j) of one problem
   const float* sqrt_f;       // [J][p][p] of the problem's frames

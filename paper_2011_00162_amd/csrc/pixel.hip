@@ -154,6 +154,7 @@ __global__ __launch_bounds__(256, BLIND ? 1 : 6) void k_pixel_uni(PixelArgs a) {
   const int tile = blockIdx.x;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const WaveRec w = a.waves[(size_t)tile * 4 + wv];
+  if (a.stop && a.stop[w.prob].stopped) return;  // every wavefront of the tile: one problem
   const int p = a.p, s = w.s, m = w.m;
   const int tpg = 256 >> w.lg;                   // threads per copy group
   const int q = threadIdx.x & (tpg - 1);
@@ -252,6 +253,7 @@ __global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
   const int tile = a.n_uni + blockIdx.x;
   const TileDesc td = a.tiles[tile];
   const CellDesc* cd = a.cells + td.cell;
+  if (a.stop && a.stop[cd->probe].stopped) return;  // its problem met its stopping rule
   const int p = a.p, m = cd->m;
   const float r = cd->r;
   const int lg = copy_groups_log2(m);

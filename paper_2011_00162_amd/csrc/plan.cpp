@@ -91,6 +91,10 @@ struct odp_plan {
   TileSet tsets[3];
   int ts = 0;
   int32_t xcd_slice = 2;
+  // stopping rule (Sec. 4) evaluated on the device after every iteration
+  int32_t stop_measure = ODP_STOP_NONE, stop_max_iter = 0;
+  double stop_tol = 0.0;
+  bool stopping() const { return stop_measure != ODP_STOP_NONE || stop_max_iter > 0; }
   std::vector<std::pair<hipEvent_t, hipEvent_t>> sweep_ev;   // kernel timing of the next sweeps
   size_t sweep_ev_next = 0, sweep_ev_stride = 1;
   // problems of a batch (one entry for a single problem)
@@ -107,10 +111,10 @@ struct odp_plan {
   // workspace layout (byte offsets)
   struct {
     size_t tw, w, frames, fpos, order, sub_first, offsets, rects, usub_off, cells, tiles, waves, re_list, re_first,
-        tf_first, pull, den, rcp, fpart, tpart, stat_scratch, misc, pmax, psi, fmask, wpart, dft, bytes;
+        tf_first, pull, den, rcp, fpart, tpart, stat_scratch, misc, pmax, psi, fmask, wpart, dft, prob, bytes;
   } ws{};
   struct {
-    size_t u_sub, gamma, lam, w, w_sub, delta, bytes;
+    size_t u_sub, gamma, lam, w, w_sub, delta, stop, bytes;
   } st{};
   // bound state
   char* wsp = nullptr;
@@ -400,6 +404,7 @@ void layout(odp_plan* P) {
   P->ws.fmask = take(sizeof(float) * pp);
   P->ws.wpart = take(sizeof(double) * 2 * pp * LOSS_CHUNKS);
   P->ws.dft = take(sizeof(uint16_t) * P->dft.size() + 16);
+  P->ws.prob = take(sizeof(int32_t) * 4 * P->n_probes());
   P->ws.bytes = o;
   size_t s = 0;
   auto stake = [&](size_t bytes) {
@@ -413,6 +418,7 @@ void layout(odp_plan* P) {
   P->st.w = P->blind ? stake(sizeof(float2) * pp) : 0;
   P->st.w_sub = P->blind ? stake(sizeof(float2) * pp * P->D) : 0;
   P->st.delta = P->blind ? stake(sizeof(float2) * pp * P->D) : 0;
+  P->st.stop = stake(sizeof(StopStatus) * P->n_probes());
   P->st.bytes = s;
 }
 
@@ -529,6 +535,7 @@ void device_tiles(const odp_plan* P, DevTiles& o) {
       r.xi0 = cd.c0 + td.c0;
       r.r = cd.r;
       r.sub = cd.sub[std::min(sl, cd.m - 1)];
+      r.prob = cd.probe;
       if (sl >= cd.m) continue;  // idle copy group: empty pull, no pixels
       r.u0 = cd.ubase[sl] + (int64_t)td.r0 * cd.upitch[sl] + td.c0;
       r.upitch = cd.upitch[sl];
@@ -755,6 +762,7 @@ int odp_state_get_layout(const odp_plan* P, odp_state_layout* o) {
   o->w = P->st.w;
   o->w_sub = P->st.w_sub;
   o->delta = P->st.delta;
+  o->stop = P->st.stop;
   o->bytes = P->st.bytes;
   return ODP_OK;
 }
@@ -815,17 +823,22 @@ int odp_plan_bind(odp_plan* P, void* dev_ws, const float* dev_sqrt_f, const odp_
   if (rc) return rc;
   if (!P->fmask.empty()) ODP_HIP(up(P->ws.fmask, P->fmask.data(), sizeof(float) * pp));
   if (!P->dft.empty()) ODP_HIP(up(P->ws.dft, P->dft.data(), sizeof(uint16_t) * P->dft.size()));
+  std::vector<int32_t> prob;
+  for (const odp_plan::Entry& e : P->batch) prob.insert(prob.end(), {e.J0, e.J, e.D0, e.D});
+  ODP_HIP(up(P->ws.prob, prob.data(), sizeof(int32_t) * prob.size()));
   ODP_HIP(launch_illum(illum_args(P, P->W_<float2>(P->ws.w), 1), s));
   double* misc = P->W_<double>(P->ws.misc);
   ODP_HIP(launch_sum_max(P->W_<double>(P->ws.den), P->p_sub, dev_sqrt_f, (int64_t)P->J * pp, misc, s));
-  // the largest illumination of each problem (penalty scales are chosen from it)
+  // the largest illumination of each problem (penalty scales are chosen from it) and
+  // its sum of sqrt f (the denominator of its RF)
   const int nb = P->n_probes();
   double* pm = P->W_<double>(P->ws.pmax);
   for (int i = 0; i < nb; ++i) {
     const odp_plan::Entry& e = P->batch[i];
     const int64_t u0 = P->usub_off[e.D0];
     const int64_t u1 = e.D0 + e.D < P->D ? P->usub_off[e.D0 + e.D] : P->p_sub;
-    ODP_HIP(launch_sum_max(P->W_<double>(P->ws.den) + u0, u1 - u0, dev_sqrt_f, 0, pm + (size_t)i * (2 + 2048), s));
+    ODP_HIP(launch_sum_max(P->W_<double>(P->ws.den) + u0, u1 - u0, dev_sqrt_f + (size_t)e.J0 * pp,
+                           (int64_t)e.J * pp, pm + (size_t)i * (2 + 2048), s));
   }
   double host[2] = {0, 0};
   std::vector<double> hp((size_t)nb * (2 + 2048));
@@ -901,6 +914,8 @@ int odp_state_init(const odp_plan* P, void* dev_state, const odp_c32* dev_w0, hi
   ODP_HIP(launch_fill(reinterpret_cast<float2*>(b + P->st.u_sub), P->p_sub, make_float2(1.f, 0.f), s));
   ODP_HIP(launch_fill(reinterpret_cast<float2*>(b + P->st.gamma), (int64_t)pp * P->J, make_float2(0.f, 0.f), s));
   ODP_HIP(launch_fill(reinterpret_cast<float2*>(b + P->st.lam), P->n_lam, make_float2(0.f, 0.f), s));
+  ODP_HIP(launch_fill(reinterpret_cast<float2*>(b + P->st.stop),
+                      (int64_t)(sizeof(StopStatus) / sizeof(float2)) * P->n_probes(), make_float2(0.f, 0.f), s));
   if (P->blind) {
     const float2* w0 = reinterpret_cast<const float2*>(dev_w0);
     ODP_HIP(launch_copy(reinterpret_cast<float2*>(b + P->st.w), w0, (int64_t)pp, s));
@@ -928,9 +943,10 @@ static SweepArgs sweep_args(const odp_plan* P, char* b, double* stats) {
   a.xcd_slice = P->xcd_slice;
   a.eps = (float)P->eps;
   a.eta = (float)P->eta;
-  a.part = stats ? P->W_<double>(P->ws.fpart) : nullptr;
+  a.part = stats || P->stopping() ? P->W_<double>(P->ws.fpart) : nullptr;
   a.psi = P->W_<float2>(P->ws.psi);
   a.blind = P->blind;
+  a.stop = P->stopping() ? reinterpret_cast<const StopStatus*>(b + P->st.stop) : nullptr;
   return a;
 }
 
@@ -952,7 +968,8 @@ static PixelArgs pixel_args(const odp_plan* P, char* b, double* stats) {
   a.w_sub = P->blind ? reinterpret_cast<const float2*>(b + P->st.w_sub) : nullptr;
   a.eta = (float)P->eta;
   a.gamma = (float)P->gamma;
-  a.part = stats ? P->W_<double>(P->ws.tpart) : nullptr;
+  a.part = stats || P->stopping() ? P->W_<double>(P->ws.tpart) : nullptr;
+  a.stop = P->stopping() ? reinterpret_cast<const StopStatus*>(b + P->st.stop) : nullptr;
   return a;
 }
 
@@ -1043,6 +1060,7 @@ int odp_probe_update(odp_plan* P, void* dev_state, hipStream_t s) {
   a.tw = P->W_<float2>(P->ws.tw);
   a.eta = P->eta;
   a.mu = P->mu;
+  a.stop = P->stopping() ? reinterpret_cast<const StopStatus*>(b + P->st.stop) : nullptr;
   ODP_HIP(launch_probe_update(a, s));
   return ODP_OK;
 }
@@ -1050,9 +1068,48 @@ int odp_probe_update(odp_plan* P, void* dev_state, hipStream_t s) {
 int odp_pixel_update(odp_plan* P, void* dev_state, double* dev_stats, hipStream_t s) {
   if (!P || !dev_state) return fail(ODP_EINVAL, "null argument");
   if (!P->wsp) return fail(ODP_EINVAL, "plan is not bound");
-  ODP_HIP(launch_pixel(pixel_args(P, static_cast<char*>(dev_state), dev_stats), dev_stats != nullptr,
-                       P->blind != 0, s));
-  if (dev_stats) return finish_stats(P, dev_stats, s);
+  char* b = static_cast<char*>(dev_state);
+  const PixelArgs pa = pixel_args(P, b, dev_stats);
+  ODP_HIP(launch_pixel(pa, pa.part != nullptr, P->blind != 0, s));
+  if (dev_stats) {
+    int rc = finish_stats(P, dev_stats, s);
+    if (rc) return rc;
+  }
+  if (P->stopping()) {
+    StopArgs sa;
+    sa.frame_part = P->W_<double>(P->ws.fpart);
+    sa.sub_sums = nullptr;
+    sa.prob = P->W_<int32_t>(P->ws.prob);
+    sa.sum_sf = P->W_<double>(P->ws.pmax) + 1;
+    sa.sum_sf_stride = 2 + 2048;
+    sa.n = P->n_probes();
+    sa.measure = P->stop_measure;
+    sa.max_iter = P->stop_max_iter;
+    sa.tol = P->stop_tol;
+    sa.status = reinterpret_cast<StopStatus*>(b + P->st.stop);
+    ODP_HIP(launch_stop_check(sa, P->W_<double>(P->ws.tpart), P->W_<int32_t>(P->ws.re_list),
+                              P->W_<int32_t>(P->ws.re_first), P->D, P->W_<double>(P->ws.stat_scratch), s));
+  }
+  return ODP_OK;
+}
+
+int odp_plan_set_stopping(odp_plan* P, int32_t measure, double tol, int32_t max_iter) {
+  if (!P) return fail(ODP_EINVAL, "null argument");
+  if (measure < ODP_STOP_NONE || measure > ODP_STOP_RE) return fail(ODP_EINVAL, "unknown stopping measure");
+  if (measure != ODP_STOP_NONE && !(tol >= 0.0)) return fail(ODP_EINVAL, "tolerance must be non-negative");
+  if (max_iter < 0) return fail(ODP_EINVAL, "negative iteration cap");
+  P->stop_measure = measure;
+  P->stop_tol = measure != ODP_STOP_NONE ? tol : 0.0;
+  P->stop_max_iter = max_iter;
+  return ODP_OK;
+}
+
+int odp_state_get_stop_status(const odp_plan* P, const void* dev_state, odp_stop_status* out, hipStream_t s) {
+  if (!P || !dev_state || !out) return fail(ODP_EINVAL, "null argument");
+  static_assert(sizeof(odp_stop_status) == sizeof(StopStatus), "stop status layout");
+  ODP_HIP(hipMemcpyAsync(out, static_cast<const char*>(dev_state) + P->st.stop,
+                         sizeof(StopStatus) * P->n_probes(), hipMemcpyDeviceToHost, s));
+  ODP_HIP(hipStreamSynchronize(s));
   return ODP_OK;
 }
 
@@ -1163,6 +1220,10 @@ int odp_plan_autotune(odp_plan* P, void* dev_scratch_state, int32_t iters, hipSt
   double best_ms = 1e300;
   int bt = P->transform, bx = P->xcd_slice, bs = P->ts, tried = 0;
   int rc = ODP_OK;
+  // time whole iterations: no problem of the scratch state may stop early
+  const int32_t sm = P->stop_measure, smax = P->stop_max_iter;
+  P->stop_measure = ODP_STOP_NONE;
+  P->stop_max_iter = 0;
   for (int tr : transforms) {
     for (int xs = 2; xs >= 0 && !rc; --xs) {
       for (int ts = 0; ts < 3 && !rc; ++ts) {
@@ -1191,6 +1252,8 @@ int odp_plan_autotune(odp_plan* P, void* dev_scratch_state, int32_t iters, hipSt
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
+  P->stop_measure = sm;
+  P->stop_max_iter = smax;
   if (rc) return rc;
   rc = odp_plan_set_tuning(P, bt, bx, bs, s);
   if (rc) return rc;

@@ -1,0 +1,187 @@
+"""GPU tests of the device-side stopping rules (Sec. 4): each problem of a plan stops
+after the first iteration whose measure meets the tolerance, or at the iteration cap;
+its state then stays that iterate while the other problems go on, in eager calls and
+inside a graph.  The stop points come from the FP64 oracle's trajectories."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+import paper_2011_00162_amd as odp
+from oracle.od2p import od2pm_run
+from tests.gpu_util import dev_c64, dev_f32, gpu_plan, host, rel, rel_list, rounded_inputs, same_state
+from tests.oracle_problems import oracle_problem, tiny_spec
+
+pytestmark = pytest.mark.gpu
+
+# the tolerance sits at least this factor away from every measure the decision reads,
+# so the FP32 measures (within about 1e-3 of the oracle's) take the same decisions
+MARGIN = 1.05
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+
+
+def _pick_tol(seqs, first=2, after=3, all_stop=True):
+    """(tol, stop indices): tol between two consecutive distinct values of all sequences,
+    at least MARGIN from both; per sequence the first index m with value <= tol,
+    first <= m < len - after (so iterations remain after the stop), or None where no
+    value is <= tol (allowed unless all_stop).  Among the candidates, the one giving the
+    most distinct outcomes, then the latest first stop."""
+    vals = sorted({float(v) for s in seqs for v in s}, reverse=True)
+    best = None
+    for a, b in zip(vals, vals[1:]):
+        if not (b > 0 and a / b >= MARGIN ** 2):
+            continue
+        tol = math.sqrt(a * b)
+        ms = []
+        for s in seqs:
+            hit = [k for k, v in enumerate(s) if v <= tol]
+            if (not hit and all_stop) or (hit and not first <= hit[0] < len(s) - after):
+                break
+            ms.append(hit[0] if hit else None)
+        else:
+            stops = [m for m in ms if m is not None]
+            if not stops:
+                continue
+            key = (len(set(ms)), min(stops))
+            if best is None or key > best[0]:
+                best = (key, tol, ms)
+    assert best is not None, "no tolerance with margin"
+    return best[1], best[2]
+
+
+def _oracle_run(P, K):
+    w, _, f = rounded_inputs(P)
+    return od2pm_run(P["geom"], w, f, P["eps"], P["eta"], P["r"], K)
+
+
+@pytest.mark.parametrize("measure,peak", [(odp.ODP_STOP_RE, 1e4), (odp.ODP_STOP_RF, None)], ids=["RE_noisy", "RF_clean"])
+def test_single_problem_stops_where_the_oracle_does(measure, peak):
+    spec = tiny_spec(n=128, p=32, step=8, jitter=1, dy=1, dx=2, radius=12, peak=peak)
+    say("stop single", measure)
+    P = oracle_problem(spec)
+    K = 16
+    _, hist = _oracle_run(P, K)
+    key = "RE" if measure == odp.ODP_STOP_RE else "RF"
+    tol, (m,) = _pick_tol([[h[key] for h in hist]])
+    plan = gpu_plan(P)
+    plan.set_stopping(measure, tol, 0)
+    st = plan.new_state()
+    assert plan.stop_status(st)[0] == dict(iters=0, stopped=False, rf=0.0, re=0.0, g=0.0)
+    plan.iterate(st, K)
+    s = plan.stop_status(st)[0]
+    assert (s["iters"], s["stopped"]) == (m + 1, True), (s, m)
+    assert abs(s["rf"] - hist[m]["RF"]) <= 1e-3 * hist[m]["RF"]
+    assert abs(s["re"] - hist[m]["RE"]) <= 1e-3 * hist[m]["RE"]
+    ost, _ = _oracle_run(P, m + 1)
+    assert rel_list([host(t) for t in st.u_sub()], ost.u) <= 1e-4
+    # the stopped state is exactly the iterate of m + 1 iterations (the rule off)
+    plan.set_stopping(odp.ODP_STOP_NONE, 0.0, 0)
+    ref = plan.new_state()
+    plan.iterate(ref, m + 1, stats=True)
+    assert same_state(st, ref)
+
+
+def test_iteration_cap_and_state_init_reset():
+    spec = tiny_spec(n=128, p=32, step=8, jitter=1, dy=2, dx=2, radius=12, peak=1e4)
+    say("stop cap")
+    P = oracle_problem(spec)
+    plan = gpu_plan(P)
+    plan.set_stopping(odp.ODP_STOP_NONE, 0.0, 3)
+    st = plan.new_state()
+    plan.iterate(st, 5)
+    s = plan.stop_status(st)[0]
+    assert (s["iters"], s["stopped"]) == (3, True)
+    plan.set_stopping(odp.ODP_STOP_NONE, 0.0, 0)
+    ref = plan.new_state()
+    plan.iterate(ref, 3, stats=True)
+    assert same_state(st, ref)
+    assert plan.stop_status(ref)[0]["iters"] == 0          # no rule: no progress kept
+    plan.set_stopping(odp.ODP_STOP_NONE, 0.0, 3)
+    from paper_2011_00162_amd._lib import lib
+    assert lib().odp_state_init(plan._h, st.buf.data_ptr(), None, None) == 0
+    assert plan.stop_status(st)[0]["iters"] == 0           # init clears the progress
+    plan.iterate(st, 4)
+    assert same_state(st, ref)
+
+
+def test_blind_problem_freezes_probe_and_image():
+    spec = tiny_spec(n=128, p=32, step=8, jitter=1, dy=2, dx=2, radius=12, peak=1e4)
+    say("stop blind")
+    P = oracle_problem(spec)
+    g = P["geom"]
+    mu = 0.5 * P["eta"] * max(len(fr) for fr in g.frames_of)
+    plan = gpu_plan(P, blind=True, mu=mu)
+    w0 = plan.blind_initial_probe()
+    plan.set_stopping(odp.ODP_STOP_RF, 0.0, 2)              # RF > 0 here: the cap decides
+    st = plan.new_state(w0=w0)
+    plan.iterate(st, 4)
+    s = plan.stop_status(st)[0]
+    assert (s["iters"], s["stopped"]) == (2, True)
+    plan.set_stopping(odp.ODP_STOP_NONE, 0.0, 0)
+    ref = plan.new_state(w0=w0)
+    plan.iterate(ref, 2, stats=True)
+    assert same_state(st, ref)                             # u, Gamma, Lam, w, w_d, Delta
+
+
+def _batch_items():
+    # uneven sizes, partitions and noise: their RE trajectories fall at different rates
+    shapes = [(128, 8, 1, 1, 2, 1e4, 31), (96, 6, 1, 2, 1, 1e5, 33), (160, 8, 2, 2, 3, 1e3, 35)]
+    out = []
+    for n, step, jit, dy, dx, peak, seed in shapes:
+        P = oracle_problem(tiny_spec(n=n, p=32, step=step, jitter=jit, dy=dy, dx=dx, radius=12, peak=peak,
+                                     seed=seed))
+        out.append(P)
+    return out
+
+
+def test_batch_problems_stop_independently_also_in_a_graph():
+    say("stop batch")
+    items = _batch_items()
+    K = 14
+    runs = [_oracle_run(P, K)[1] for P in items]
+    tol, ms = _pick_tol([[h["RE"] for h in hist] for hist in runs], all_stop=False)
+    want = [(K, False) if m is None else (m + 1, True) for m in ms]
+    say("stop batch tol", tol, "iterations, stopped", want)
+    assert len({m for m in ms}) >= 2                   # the problems do not all stop together
+    plan = odp.Plan.batch([dict(H=P["pr"]["spec"].n, W=P["pr"]["spec"].n, p=32, offsets=P["pr"]["offsets"],
+                                frame_sub=P["pr"]["frame_sub"], r=P["r"]) for P in items])
+    sf = np.concatenate([rounded_inputs(P)[1] for P in items])
+    w = np.stack([rounded_inputs(P)[0] for P in items])
+    plan.bind(dev_f32(sf), dev_c64(w))
+    plan.set_stopping(odp.ODP_STOP_RE, tol, 0)
+    a = plan.new_state()
+    plan.iterate(a, K)
+    stat = plan.stop_status(a)
+    assert [(s["iters"], s["stopped"]) for s in stat] == want, (stat, ms)
+    for i, (P, (n_it, _)) in enumerate(zip(items, want)):
+        e = plan.entry(i)
+        ost, _ = _oracle_run(P, n_it)
+        # the K-iteration reconstruction bound (a noisy problem runs all K here)
+        assert rel_list([host(t) for t in a.u_sub()[e.D0:e.D0 + e.D]], ost.u) <= 1e-3, i
+    # a graph of K iterations gives the same outcome and states; on a second replay (eager
+    # work in between) the stopped problems stay as they are and the others go on
+    b = plan.new_state()
+    gr = odp.Graph([plan], [b], K)
+    gr.launch()
+    torch.cuda.synchronize()
+    assert plan.stop_status(b) == stat
+    assert same_state(a, b)
+    c = b.clone()
+    gr.launch()
+    torch.cuda.synchronize()
+    after = plan.stop_status(b)
+    for i, (_, stopped) in enumerate(want):
+        e = plan.entry(i)
+        same_u = all(torch.equal(x, y) for x, y in zip(b.u_sub()[e.D0:e.D0 + e.D], c.u_sub()[e.D0:e.D0 + e.D]))
+        same_g = torch.equal(b.gamma()[e.J0:e.J0 + e.J], c.gamma()[e.J0:e.J0 + e.J])
+        if stopped:
+            assert after[i] == stat[i] and same_u and same_g, i
+        else:
+            assert after[i]["iters"] > K and not same_u, i
