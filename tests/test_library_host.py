@@ -183,3 +183,19 @@ def test_initial_probe_arguments_are_checked():
     assert L.odp_blind_initial_probe(None, C.c_void_p(0x1000), None) == ODP_EINVAL   # null plan
     assert L.odp_blind_initial_probe(plan._h, None, None) == ODP_EINVAL              # null output
     assert L.odp_blind_initial_probe(plan._h, C.c_void_p(0x1000), None) == ODP_EINVAL   # not bound
+
+
+def test_stopping_arguments_are_checked():
+    plan = odp.Plan(**_plan_args())
+    L = odp.lib()
+    assert L.odp_plan_set_stopping(None, odp.ODP_STOP_RF, 1e-5, 1000) == ODP_EINVAL
+    assert L.odp_plan_set_stopping(plan._h, 3, 1e-5, 0) == ODP_EINVAL           # unknown measure
+    assert L.odp_plan_set_stopping(plan._h, -1, 1e-5, 0) == ODP_EINVAL
+    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_RE, -1e-3, 0) == ODP_EINVAL
+    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_RE, float("nan"), 0) == ODP_EINVAL
+    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_RE, 1e-3, -1) == ODP_EINVAL
+    # the paper's two rules and a bare cap (host-side settings: no device needed)
+    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_RF, 1e-5, 1000) == 0
+    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_RE, 1e-3, 200) == 0
+    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_NONE, float("nan"), 7) == 0
+    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_NONE, 0.0, 0) == 0
