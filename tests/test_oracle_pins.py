@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import synthetic
-from oracle import amploss, blind, operators as ops, stagm
+from oracle import amploss, balance, blind, operators as ops, stagm
 from oracle.geometry import build_geometry, cover_count, multiplicity, overlap_width, GeometryError
 from oracle.od2p import (admm_undecomposed, augmented_lagrangian, init_state, merge, od2pm_run,
                          od2pm_step, forward_sub, adjoint_sub, run_until, subdomain_illumination, snr_db)
@@ -595,3 +595,67 @@ def test_paper_rules_stop_at_once_from_the_noise_free_truth():
         st.u = [ut[g.rects[d, 0]:g.rects[d, 2], g.rects[d, 1]:g.rects[d, 3]].copy() for d in range(g.D)]
         _, h = run_until(_stepper(P), st, measure, tol, cap)
         assert len(h) == 1 and h[0][measure] <= tol
+
+
+# ---------------------------------------------------------------------------
+# T21  automatic overlap penalty: residual balancing (He, Yang, Wang 2000;
+#      Boyd et al. 2011, Sec. 3.4.1) on the consensus constraints
+# ---------------------------------------------------------------------------
+
+def test_consensus_residuals_closed_form():
+    P = oracle_problem(tiny_spec(dy=1, dx=2))
+    g = P["geom"]
+    assert len(g.pairs) == 1
+    (i1, i2, rc) = g.pairs[0]
+    n_ov = (rc[2] - rc[0]) * (rc[3] - rc[1])
+    old = init_state(g)
+    new = old.copy()
+    d0, d1, c01, c10 = 0.3 - 0.1j, -0.2j, 0.5 + 0.25j, -1.5
+    new.u = [old.u[0] + d0, old.u[1] + d1]
+    new.lam[(i1, i2)] = np.full_like(old.lam[(i1, i2)], c01)
+    new.lam[(i2, i1)] = np.full_like(old.lam[(i2, i1)], c10)
+    res = balance.consensus_residuals(g, old, new)
+    want_P = n_ov * (abs(c01) ** 2 + abs(c10) ** 2)
+    assert math.isclose(res["P"], want_P, rel_tol=1e-13)
+    assert math.isclose(res["L"], want_P, rel_tol=1e-13)          # old multipliers are 0
+    assert math.isclose(res["S"], n_ov * (abs(d0) ** 2 + abs(d1) ** 2), rel_tol=1e-13)
+    assert math.isclose(res["U"], n_ov * (abs(1 + d0) ** 2 + abs(1 + d1) ** 2), rel_tol=1e-13)
+
+
+def test_balance_rule_thresholds():
+    mu, tau = 10.0, 2.0
+    f = lambda P, S, U=1.0, L=1.0: balance.balance_factor(dict(P=P, S=S, U=U, L=L), mu, tau)
+    assert f(1.0, 1.0) == 1.0
+    assert f(100.0 * 1.0001, 1.0) == tau          # rp > mu rd: strengthen the consensus
+    assert f(1.0, 100.0 * 1.0001) == 1.0 / tau    # rd > mu rp: relax it
+    assert f(100.0, 1.0) == 1.0                   # rp = mu rd exactly: kept (strict rule)
+    assert f(1.0, 1.0, U=0.0) == 1.0 and f(1.0, 1.0, L=0.0) == 1.0
+
+
+def test_balanced_run_without_triggers_is_the_plain_run():
+    P = oracle_problem(tiny_spec(dy=1, dx=2))
+    g, w, f = P["geom"], P["pr"]["w"], P["f"]
+    a, _, rh = balance.od2pm_run_balanced(g, w, f, P["eps"], P["eta"], P["r"], 6, mu=np.inf, period=1)
+    b, _ = od2pm_run(g, w, f, P["eps"], P["eta"], P["r"], 6)
+    assert rh == [P["r"]] * 6
+    assert all(np.array_equal(x, y) for x, y in zip(a.u, b.u))
+    assert all(np.array_equal(a.lam[k], b.lam[k]) for k in a.lam)
+
+
+def test_penalty_change_keeps_the_unscaled_multipliers():
+    # with period 1 and mu = 1 the rule changes r at almost every iteration; across each
+    # change r Lam equals what the plain step with the old r produced (tau = 2: exact)
+    P = oracle_problem(tiny_spec(dy=2, dx=2, n=32, step=4, peak=1e3))
+    g, w, f = P["geom"], P["pr"]["w"], P["f"]
+    K = 5
+    _, _, rh = balance.od2pm_run_balanced(g, w, f, P["eps"], P["eta"], P["r"], K, mu=1.0, period=1)
+    changed = [k for k in range(1, K) if rh[k] != rh[k - 1]]
+    assert changed, rh
+    k = changed[0]                                     # iteration k + 1 changed r
+    prev, _, _ = balance.od2pm_run_balanced(g, w, f, P["eps"], P["eta"], P["r"], k, mu=1.0, period=1)
+    plain, _ = od2pm_step(g, w, f, prev, P["eps"], P["eta"], rh[k - 1])
+    bal, _, rh2 = balance.od2pm_run_balanced(g, w, f, P["eps"], P["eta"], P["r"], k + 1, mu=1.0, period=1)
+    assert rh2[-1] == rh[k] and rh[k] / rh[k - 1] in (2.0, 0.5)
+    for key in bal.lam:
+        assert np.array_equal(rh[k] * bal.lam[key], rh[k - 1] * plain.lam[key])
+    assert all(np.array_equal(x, y) for x, y in zip(bal.u, plain.u))
