@@ -42,12 +42,19 @@ def consensus_residuals(geom, old: OD2PState, new: OD2PState) -> dict:
     return dict(P=P, S=S, U=U, L=L)
 
 
+def normalised_residuals(res: dict):
+    """(rp, rd), or None when a normaliser vanishes."""
+    if not (res["U"] > 0.0 and res["L"] > 0.0):
+        return None
+    return np.sqrt(res["P"] / res["U"]), np.sqrt(res["S"] / res["L"])
+
+
 def balance_factor(res: dict, mu: float, tau: float) -> float:
     """The rule's factor on r (tau, 1/tau or 1); 1 when a normaliser vanishes."""
-    if not (res["U"] > 0.0 and res["L"] > 0.0):
+    nr = normalised_residuals(res)
+    if nr is None:
         return 1.0
-    rp = np.sqrt(res["P"] / res["U"])
-    rd = np.sqrt(res["S"] / res["L"])
+    rp, rd = nr
     if rp > mu * rd:
         return tau
     if rd > mu * rp:
@@ -56,10 +63,11 @@ def balance_factor(res: dict, mu: float, tau: float) -> float:
 
 
 def od2pm_run_balanced(geom, w, f, eps, eta, r, n_iter, mu=10.0, tau=2.0, period=10, until=None,
-                       state=None):
+                       state=None, trace=None):
     """n_iter iterations of Algorithm 2 with r chosen by residual balancing.
 
-    Returns (state, per-iteration stats, r after each iteration)."""
+    Returns (state, per-iteration stats, r after each iteration); ``trace``, if a list,
+    receives (iteration, rp, rd) at every check."""
     st = init_state(geom) if state is None else state
     den = [subdomain_illumination(geom, w, d) for d in range(geom.D)]
     until = n_iter if until is None else until
@@ -68,7 +76,10 @@ def od2pm_run_balanced(geom, w, f, eps, eta, r, n_iter, mu=10.0, tau=2.0, period
         new, s = od2pm_step(geom, w, f, st, eps, eta, r, den=den)
         new.z = None
         if k % period == 0 and k <= until:
-            fac = balance_factor(consensus_residuals(geom, st, new), mu, tau)
+            res = consensus_residuals(geom, st, new)
+            if trace is not None:
+                trace.append((k, *(normalised_residuals(res) or (np.nan, np.nan))))
+            fac = balance_factor(res, mu, tau)
             if fac != 1.0:
                 r *= fac
                 new.lam = {key: a / fac for key, a in new.lam.items()}

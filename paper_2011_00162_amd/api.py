@@ -198,6 +198,14 @@ class Plan:
         iteration cap); applies to later iterations and graphs created afterwards."""
         check(lib().odp_plan_set_stopping(self._h, int(measure), float(tol), int(max_iter)))
 
+    def set_balancing(self, mu: float = 10.0, tau: float = 2.0, period: int = 0, until: int = 0) -> None:
+        """Overlap penalties by residual balancing every `period` iterations (0: off)."""
+        check(lib().odp_plan_set_balancing(self._h, float(mu), float(tau), int(period), int(until)))
+
+    def penalties(self) -> list[float]:
+        """The overlap penalty r of each problem (changed by balancing)."""
+        return [self.entry(i).r for i in range(self.n_problems())]
+
     def stop_status(self, state: "State", stream=None) -> list[dict]:
         """Per problem: iterations run, whether it stopped, and its last RF, RE, G."""
         n = self.n_problems()

@@ -476,29 +476,30 @@ hipError_t launch_sum_max(const double* x, int64_t n, const float* y, int64_t ny
 // ---------------------------------------------------------------------------
 // per-iteration statistics: RF, RE, G_eps (Sec. 4, eq. STAGM), fixed order
 // ---------------------------------------------------------------------------
+// blocks [0, D): the NPS pixel statistics of subdomain b into scratch[NPS b ...];
+// block D: the frames' (L1 misfit, G_eps) into scratch[NPS D], scratch[NPS D + 1]
 __global__ __launch_bounds__(256) void k_stats_reduce(const double* frame_part, int J, const double* tile_part,
                                                       const int32_t* re_list, const int32_t* re_first, int D,
                                                       double* scratch) {
   __shared__ double sh[4];
   const int b = blockIdx.x;
-  double s0 = 0.0, s1 = 0.0;
+  double v[NPS] = {};
   if (b < D) {
     for (int k = re_first[b] + threadIdx.x; k < re_first[b + 1]; k += 256) {
       const int e = re_list[k];
-      s0 += tile_part[2 * (size_t)e];
-      s1 += tile_part[2 * (size_t)e + 1];
+#pragma unroll
+      for (int q = 0; q < NPS; ++q) v[q] += tile_part[NPS * (size_t)e + q];
     }
   } else {
     for (int k = threadIdx.x; k < J; k += 256) {
-      s0 += frame_part[2 * k];
-      s1 += frame_part[2 * k + 1];
+      v[0] += frame_part[2 * k];
+      v[1] += frame_part[2 * k + 1];
     }
   }
-  s0 = block_sum<256>(s0, sh);
-  s1 = block_sum<256>(s1, sh);
-  if (threadIdx.x == 0) {
-    scratch[2 * b] = s0;
-    scratch[2 * b + 1] = s1;
+  const int nq = b < D ? NPS : 2;
+  for (int q = 0; q < nq; ++q) {
+    const double t = block_sum<256>(v[q], sh);
+    if (threadIdx.x == 0) scratch[NPS * (size_t)b + q] = t;
   }
 }
 
@@ -506,13 +507,52 @@ __global__ void k_stats_final(const double* scratch, int D, const double* sum_sf
   if (threadIdx.x != 0) return;
   double re = 0.0;
   for (int d = 0; d < D; ++d) {
-    const double num = scratch[2 * d], den = scratch[2 * d + 1];
+    const double num = scratch[NPS * d], den = scratch[NPS * d + 1];
     const double v = den > 0.0 ? sqrt(num / den) : 0.0;
     re = fmax(re, v);
   }
-  out3[0] = scratch[2 * D] / sum_sf[0];
+  out3[0] = scratch[NPS * D] / sum_sf[0];
   out3[1] = re;
-  out3[2] = scratch[2 * D + 1];
+  out3[2] = scratch[NPS * D + 1];
+}
+
+hipError_t launch_stats(const double* frame_part, int J, const double* tile_part, const int32_t* re_list,
+                        const int32_t* re_first, int D, const double* sum_sf, double* out3, double* scratch,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_stats_reduce, dim3(D + 1), dim3(256), 0, s, frame_part, J, tile_part, re_list, re_first,
+                     D, scratch);
+  hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(64), 0, s, scratch, D, sum_sf, out3);
+  return hipGetLastError();
+}
+
+// per problem (one thread each), its subdomains in ascending order
+__global__ void k_residual_sums(const double* scratch, const int32_t* prob, int n, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int D0 = prob[4 * i + 2], D = prob[4 * i + 3];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int d = D0; d < D0 + D; ++d)
+    for (int k = 0; k < 4; ++k) v[k] += scratch[NPS * (size_t)d + 2 + k];
+  for (int k = 0; k < 4; ++k) out[4 * (size_t)i + k] = v[k];
+}
+
+hipError_t launch_residual_sums(const double* tile_part, const int32_t* re_list, const int32_t* re_first, int D,
+                                const int32_t* prob, int n, double* scratch, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats_reduce, dim3(D), dim3(256), 0, s, (const double*)nullptr, 0, tile_part, re_list,
+                     re_first, D, scratch);
+  hipLaunchKernelGGL(k_residual_sums, dim3((n + 63) / 64), dim3(64), 0, s, scratch, prob, n, out);
+  return hipGetLastError();
+}
+
+__global__ void k_scale(float2* x, int64_t n, float f) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = c_scale(x[i], f);
+}
+
+hipError_t launch_scale(float2* x, int64_t n, float f, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, f);
+  return hipGetLastError();
 }
 
 // end of an iteration under a stopping rule (Sec. 4): per problem, its measures and the
@@ -533,7 +573,7 @@ __global__ __launch_bounds__(256) void k_stop_check(StopArgs a) {
   if (threadIdx.x != 0) return;
   double re = 0.0;
   for (int d = D0; d < D0 + D; ++d) {
-    const double num = a.sub_sums[2 * d], den = a.sub_sums[2 * d + 1];
+    const double num = a.sub_sums[NPS * d], den = a.sub_sums[NPS * d + 1];
     re = fmax(re, den > 0.0 ? sqrt(num / den) : 0.0);
   }
   const double rf = s0 / a.sum_sf[(size_t)i * a.sum_sf_stride];
@@ -558,14 +598,6 @@ hipError_t launch_stop_check(const StopArgs& a, const double* tile_part, const i
   return hipGetLastError();
 }
 
-hipError_t launch_stats(const double* frame_part, int J, const double* tile_part, const int32_t* re_list,
-                        const int32_t* re_first, int D, const double* sum_sf, double* out3, double* scratch,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_stats_reduce, dim3(D + 1), dim3(256), 0, s, frame_part, J, tile_part, re_list, re_first,
-                     D, scratch);
-  hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(64), 0, s, scratch, D, sum_sf, out3);
-  return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------
 // merge (Sec. 4): mean of the copies over each pixel, 1 where no subdomain

@@ -11,6 +11,7 @@ constexpr int MAXS = 8;                        // most subdomains over one pixel
 constexpr int MAXP = MAXS * (MAXS - 1) / 2;    // most pairs over one pixel
 constexpr int NPX = 2;                          // pixels per thread in the pixel-tile kernels
 constexpr int PULL_B = 4;                       // pull records per group (lists padded to a multiple)
+constexpr int NPS = 6;                          // pixel-update statistics per (tile, copy slot)
 constexpr int NXCD = 8;                        // MI355X accelerator complex dies
 
 // A cell is a rectangle of image pixels covered by the same set of subdomains
@@ -120,7 +121,7 @@ struct PixelArgs {
   const PullEntry* pull;     // their records, ascending frame id
   const float2* w_sub;       // blind: probe copies (the illumination is formed in the pull)
   float eta, gamma;          // (r is per cell)
-  double* part;              // [n_tiles][MAXS][2] (|du|^2, |u|^2) or null
+  double* part;              // [n_tiles][MAXS][NPS] statistics (pixel_stats) or null
   const StopStatus* stop;    // [n_problems] or null: tiles of stopped problems are skipped
 };
 
@@ -199,6 +200,13 @@ struct StopArgs {
 };
 hipError_t launch_stop_check(const StopArgs& a, const double* tile_part, const int32_t* re_list,
                              const int32_t* re_first, int D, double* scratch, hipStream_t s);
+
+// Consensus residual sums of each problem for the penalty rule (per-subdomain sums from
+// the statistics reduction in scratch): out[4 i + k] = sum over its subdomains of
+// (|Lam^{n+1} - Lam^n|^2, (m-1)|du|^2, (m-1)|u^{n+1}|^2, |Lam^{n+1}|^2).
+hipError_t launch_residual_sums(const double* tile_part, const int32_t* re_list, const int32_t* re_first, int D,
+                                const int32_t* prob, int n, double* scratch, double* out, hipStream_t s);
+hipError_t launch_scale(float2* x, int64_t n, float f, hipStream_t s);
 
 struct InitProbeArgs {       // w0 = (1/J) sum_j F^{-1}(sqrt f_j) of one problem
   const float* sqrt_f;       // [J][p][p] of the problem's frames

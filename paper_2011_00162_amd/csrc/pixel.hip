@@ -116,31 +116,49 @@ __device__ __forceinline__ float2 pixel_value(const PixelArgs& a, int m, float r
   return rc == 0.0f ? uo : c_scale(acc, rc);
 }
 
-// per copy group: (|du|^2, |u|^2) over the thread's pixels, reduced in a fixed order
-// into part[tile][s]
-__device__ __forceinline__ void pixel_stats(const PixelArgs& a, int tile, int m, int tpg, double du, double uu,
+// per copy group, NPS sums over the thread's pixels (the per-copy |du|^2 and |u|^2, then
+// the consensus residual terms over the copy's ordered pairs: |Lam^{n+1} - Lam^n|^2,
+// (m-1)|du|^2, (m-1)|u^{n+1}|^2, |Lam^{n+1}|^2), reduced in a fixed order into
+// part[tile][s][NPS]
+__device__ __forceinline__ void pixel_stats(const PixelArgs& a, int tile, int m, int tpg, double (&v)[NPS],
                                             double (*red)[8]) {
   const int g = min(tpg, 64);                    // lanes of one group inside a wavefront
-  for (int o = g >> 1; o > 0; o >>= 1) {
-    du += __shfl_xor(du, o, 64);
-    uu += __shfl_xor(uu, o, 64);
-  }
+  for (int o = g >> 1; o > 0; o >>= 1)
+#pragma unroll
+    for (int k = 0; k < NPS; ++k) v[k] += __shfl_xor(v[k], o, 64);
   const int chunk = threadIdx.x / g;             // 256 / g <= 8 chunks, tpg / g per group
-  if ((threadIdx.x & (g - 1)) == 0) {
-    red[0][chunk] = du;
-    red[1][chunk] = uu;
-  }
+  if ((threadIdx.x & (g - 1)) == 0)
+#pragma unroll
+    for (int k = 0; k < NPS; ++k) red[k][chunk] = v[k];
   __syncthreads();
   if (threadIdx.x < MAXS && (int)threadIdx.x < m) {
     const int per = tpg / g;
-    double a0 = 0.0, a1 = 0.0;
-    for (int c = threadIdx.x * per; c < (int)(threadIdx.x + 1) * per; ++c) {
-      a0 += red[0][c];
-      a1 += red[1][c];
+#pragma unroll
+    for (int k = 0; k < NPS; ++k) {
+      double acc = 0.0;
+      for (int c = threadIdx.x * per; c < (int)(threadIdx.x + 1) * per; ++c) acc += red[k][c];
+      a.part[((size_t)tile * MAXS + threadIdx.x) * NPS + k] = acc;
     }
-    a.part[((size_t)tile * MAXS + threadIdx.x) * 2] = a0;
-    a.part[((size_t)tile * MAXS + threadIdx.x) * 2 + 1] = a1;
   }
+}
+
+// consensus residual terms of one pixel of copy s (the last four of pixel_stats)
+template <int NO>
+__device__ __forceinline__ void residual_terms(int m, float2 un, float2 uo, const float2* lo, const float2 (&dv)[NO],
+                                               double (&v)[NPS]) {
+#pragma unroll
+  for (int o = 0; o < NO; ++o)
+    if (o < m - 1) {
+      const float2 ln = c_sub(un, dv[o]);       // Lam^{n+1}, as stored
+      const double ix = (double)ln.x - lo[o].x, iy = (double)ln.y - lo[o].y;
+      v[2] += ix * ix + iy * iy;
+      v[5] += (double)ln.x * ln.x + (double)ln.y * ln.y;
+    }
+  const double ex = (double)un.x - uo.x, ey = (double)un.y - uo.y;
+  v[0] += ex * ex + ey * ey;
+  v[1] += (double)un.x * un.x + (double)un.y * un.y;
+  v[3] += (double)(m - 1) * (ex * ex + ey * ey);
+  v[4] += (double)(m - 1) * ((double)un.x * un.x + (double)un.y * un.y);
 }
 
 // Tiles of cells with at most four copies: each wavefront lies inside one copy group
@@ -149,7 +167,7 @@ __device__ __forceinline__ void pixel_stats(const PixelArgs& a, int tile, int m,
 // a 512 x 512 problem with 4 x 4 subdomains resident at once.
 template <bool STATS, bool BLIND>
 __global__ __launch_bounds__(256, BLIND ? 1 : 6) void k_pixel_uni(PixelArgs a) {
-  __shared__ double red[2][8];
+  __shared__ double red[NPS][8];
   constexpr int NO = 3;                          // partner copies at most
   const int tile = blockIdx.x;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -207,6 +225,7 @@ __global__ __launch_bounds__(256, BLIND ? 1 : 6) void k_pixel_uni(PixelArgs a) {
   pull_pixels<BLIND>(a.pull, w.k0, w.k1, a.psi, ws, yi, xi, pix8, p, num, den);
 
   float2 un[NPX], dv[NPX][NO];
+  double sv[NPS] = {};
 #pragma unroll
   for (int h = 0; h < NPX; ++h) {
     float2 ut[NO], lo[NO], lt[NO];
@@ -217,6 +236,7 @@ __global__ __launch_bounds__(256, BLIND ? 1 : 6) void k_pixel_uni(PixelArgs a) {
       lt[o] = lt_[o][h];
     }
     un[h] = pixel_value<BLIND, NO>(a, m, w.r, num[h], den[h], uo[h], rc[h], ut, lo, lt, dv[h]);
+    if (STATS && act[h]) residual_terms<NO>(m, un[h], uo[h], lo, dv[h], sv);
   }
   __syncthreads();  // every copy's reads of u^n and Lam^n precede the writes below
 #pragma unroll
@@ -228,17 +248,7 @@ __global__ __launch_bounds__(256, BLIND ? 1 : 6) void k_pixel_uni(PixelArgs a) {
         if (o < m - 1)   // Lam + u^{n+1} - v
           a.lam[w.lo0[o] + (int64_t)tr[h] * w.lpitch[o] + tc[h]] = c_sub(un[h], dv[h][o]);
     }
-  if (STATS) {
-    double du = 0.0, uu = 0.0;
-#pragma unroll
-    for (int h = 0; h < NPX; ++h)
-      if (act[h]) {
-        const double ex = (double)un[h].x - uo[h].x, ey = (double)un[h].y - uo[h].y;
-        du += ex * ex + ey * ey;
-        uu += (double)un[h].x * un[h].x + (double)un[h].y * un[h].y;
-      }
-    pixel_stats(a, tile, m, tpg, du, uu, red);
-  }
+  if (STATS) pixel_stats(a, tile, m, tpg, sv, red);
 }
 
 // log2 of the copy groups of a cell with m copies (m rounded up to a power of two)
@@ -248,7 +258,7 @@ __device__ __forceinline__ int copy_groups_log2(int m) { return m <= 1 ? 0 : m <
 // varies inside a wavefront, so the descriptors come from the cell, per lane.
 template <bool STATS, bool BLIND>
 __global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
-  __shared__ double red[2][8];
+  __shared__ double red[NPS][8];
   constexpr int NO = MAXS - 1;
   const int tile = a.n_uni + blockIdx.x;
   const TileDesc td = a.tiles[tile];
@@ -274,6 +284,7 @@ __global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
     xi[h] = cd->c0 + x[h];
   }
   float2 uo[NPX], un[NPX], dv[NPX][NO];
+  double sv[NPS] = {};
   float rc[NPX];
   int64_t idx[NPX];
   float2 num[NPX];
@@ -308,6 +319,7 @@ __global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
       }
     }
     un[h] = pixel_value<BLIND, NO>(a, m, r, num[h], den[h], uo[h], rc[h], ut, lo, lt, dv[h]);
+    if (STATS && act[h]) residual_terms<NO>(m, un[h], uo[h], lo, dv[h], sv);
   }
   __syncthreads();  // every copy's reads of u^n and Lam^n precede the writes below
 #pragma unroll
@@ -324,17 +336,7 @@ __global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
         }
       }
     }
-  if (STATS) {
-    double du = 0.0, uu = 0.0;
-#pragma unroll
-    for (int h = 0; h < NPX; ++h)
-      if (act[h]) {
-        const double ex = (double)un[h].x - uo[h].x, ey = (double)un[h].y - uo[h].y;
-        du += ex * ex + ey * ey;
-        uu += (double)un[h].x * un[h].x + (double)un[h].y * un[h].y;
-      }
-    pixel_stats(a, tile, m, tpg, du, uu, red);
-  }
+  if (STATS) pixel_stats(a, tile, m, tpg, sv, red);
 }
 
 hipError_t launch_pixel(const PixelArgs& a, bool stats, bool blind, hipStream_t s) {

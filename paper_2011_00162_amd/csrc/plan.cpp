@@ -95,6 +95,11 @@ struct odp_plan {
   int32_t stop_measure = ODP_STOP_NONE, stop_max_iter = 0;
   double stop_tol = 0.0;
   bool stopping() const { return stop_measure != ODP_STOP_NONE || stop_max_iter > 0; }
+  // overlap penalties by residual balancing (0 = off), host-driven every bal_period iterations
+  int32_t bal_period = 0, bal_until = 0;
+  int64_t bal_count = 0;
+  double bal_mu = 10.0, bal_tau = 2.0;
+  bool balancing() const { return bal_period > 0; }
   std::vector<std::pair<hipEvent_t, hipEvent_t>> sweep_ev;   // kernel timing of the next sweeps
   size_t sweep_ev_next = 0, sweep_ev_stride = 1;
   // problems of a batch (one entry for a single problem)
@@ -111,7 +116,7 @@ struct odp_plan {
   // workspace layout (byte offsets)
   struct {
     size_t tw, w, frames, fpos, order, sub_first, offsets, rects, usub_off, cells, tiles, waves, re_list, re_first,
-        tf_first, pull, den, rcp, fpart, tpart, stat_scratch, misc, pmax, psi, fmask, wpart, dft, prob, bytes;
+        tf_first, pull, den, rcp, fpart, tpart, stat_scratch, misc, pmax, psi, fmask, wpart, dft, prob, resid, bytes;
   } ws{};
   struct {
     size_t u_sub, gamma, lam, w, w_sub, delta, stop, bytes;
@@ -396,8 +401,8 @@ void layout(odp_plan* P) {
   P->ws.den = take(sizeof(double) * P->p_sub);
   P->ws.rcp = take(sizeof(float) * P->p_sub);
   P->ws.fpart = take(sizeof(double) * 2 * P->J);
-  P->ws.tpart = take(sizeof(double) * 2 * MAXS * n_tiles);
-  P->ws.stat_scratch = take(sizeof(double) * 2 * (P->D + 1));
+  P->ws.tpart = take(sizeof(double) * NPS * MAXS * n_tiles);
+  P->ws.stat_scratch = take(sizeof(double) * NPS * (P->D + 1));
   P->ws.misc = take(sizeof(double) * (2 + 2 * 1024 + 8));
   P->ws.pmax = take(sizeof(double) * (2 + 2 * 1024) * P->n_probes());
   P->ws.psi = take(sizeof(float2) * pp * P->J);
@@ -405,6 +410,7 @@ void layout(odp_plan* P) {
   P->ws.wpart = take(sizeof(double) * 2 * pp * LOSS_CHUNKS);
   P->ws.dft = take(sizeof(uint16_t) * P->dft.size() + 16);
   P->ws.prob = take(sizeof(int32_t) * 4 * P->n_probes());
+  P->ws.resid = take(sizeof(double) * 4 * P->n_probes());
   P->ws.bytes = o;
   size_t s = 0;
   auto stake = [&](size_t bytes) {
@@ -943,7 +949,7 @@ static SweepArgs sweep_args(const odp_plan* P, char* b, double* stats) {
   a.xcd_slice = P->xcd_slice;
   a.eps = (float)P->eps;
   a.eta = (float)P->eta;
-  a.part = stats || P->stopping() ? P->W_<double>(P->ws.fpart) : nullptr;
+  a.part = stats || P->stopping() || P->balancing() ? P->W_<double>(P->ws.fpart) : nullptr;
   a.psi = P->W_<float2>(P->ws.psi);
   a.blind = P->blind;
   a.stop = P->stopping() ? reinterpret_cast<const StopStatus*>(b + P->st.stop) : nullptr;
@@ -968,9 +974,52 @@ static PixelArgs pixel_args(const odp_plan* P, char* b, double* stats) {
   a.w_sub = P->blind ? reinterpret_cast<const float2*>(b + P->st.w_sub) : nullptr;
   a.eta = (float)P->eta;
   a.gamma = (float)P->gamma;
-  a.part = stats || P->stopping() ? P->W_<double>(P->ws.tpart) : nullptr;
+  a.part = stats || P->stopping() || P->balancing() ? P->W_<double>(P->ws.tpart) : nullptr;
   a.stop = P->stopping() ? reinterpret_cast<const StopStatus*>(b + P->st.stop) : nullptr;
   return a;
+}
+
+// Residual balancing of the overlap penalties (He, Yang and Wang 2000; Boyd et al. 2011,
+// Sec. 3.4.1) after the iteration just issued: per problem, the normalised primal
+// consensus residual rp = ||pi u - v|| / ||pi u|| against the dual rd = ||pi du|| / ||Lam||;
+// r <- tau r when rp > mu rd, r <- r / tau when rd > mu rp, and the problem's scaled
+// multipliers Lam <- Lam r_old / r_new.  Reads the sums to the host (synchronises).
+static int balance_penalties(odp_plan* P, char* b, hipStream_t s) {
+  const int n = P->n_probes();
+  double* dev = P->W_<double>(P->ws.resid);
+  ODP_HIP(launch_residual_sums(P->W_<double>(P->ws.tpart), P->W_<int32_t>(P->ws.re_list),
+                               P->W_<int32_t>(P->ws.re_first), P->D, P->W_<int32_t>(P->ws.prob), n,
+                               P->W_<double>(P->ws.stat_scratch), dev, s));
+  std::vector<double> h((size_t)4 * n);
+  ODP_HIP(hipMemcpyAsync(h.data(), dev, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+  ODP_HIP(hipStreamSynchronize(s));
+  std::vector<double> r(n);
+  bool changed = false;
+  for (int i = 0; i < n; ++i) {
+    const odp_plan::Entry& e = P->batch[i];
+    r[i] = e.r;
+    const double Pr = h[4 * i], S = h[4 * i + 1], U = h[4 * i + 2], L = h[4 * i + 3];
+    if (e.D < 2 || !(U > 0.0 && L > 0.0)) continue;
+    const double rp = std::sqrt(Pr / U), rd = std::sqrt(S / L);
+    double fac = 1.0;
+    if (rp > P->bal_mu * rd) fac = P->bal_tau;
+    else if (rd > P->bal_mu * rp) fac = 1.0 / P->bal_tau;
+    if (fac == 1.0) continue;
+    r[i] = e.r * fac;
+    changed = true;
+    // the problem's multipliers: its pairs are contiguous (pairs are ordered by their
+    // first subdomain, and a problem's subdomains are contiguous)
+    int64_t l0 = -1, l1 = -1;
+    for (const Pair& q : P->pairs)
+      if (q.a >= e.D0 && q.a < e.D0 + e.D) {
+        if (l0 < 0) l0 = q.off;
+        l1 = q.off + 2LL * (q.r1 - q.r0) * (q.c1 - q.c0);
+      }
+    if (l0 >= 0)
+      ODP_HIP(launch_scale(reinterpret_cast<float2*>(b + P->st.lam) + l0, l1 - l0, (float)(1.0 / fac), s));
+  }
+  if (!changed) return ODP_OK;
+  return set_penalties(P, r.data(), s);
 }
 
 static int finish_stats(const odp_plan* P, double* stats, hipStream_t s) {
@@ -1093,6 +1142,19 @@ int odp_pixel_update(odp_plan* P, void* dev_state, double* dev_stats, hipStream_
   return ODP_OK;
 }
 
+int odp_plan_set_balancing(odp_plan* P, double mu, double tau, int32_t period, int32_t until) {
+  if (!P) return fail(ODP_EINVAL, "null argument");
+  if (period < 0 || until < 0) return fail(ODP_EINVAL, "negative period or limit");
+  if (period > 0 && !(mu >= 1.0 && tau > 1.0 && std::isfinite(tau)))
+    return fail(ODP_EINVAL, "need mu >= 1 and a finite tau > 1");
+  P->bal_period = period;
+  P->bal_until = until;
+  P->bal_mu = mu;
+  P->bal_tau = tau;
+  P->bal_count = 0;
+  return ODP_OK;
+}
+
 int odp_plan_set_stopping(odp_plan* P, int32_t measure, double tol, int32_t max_iter) {
   if (!P) return fail(ODP_EINVAL, "null argument");
   if (measure < ODP_STOP_NONE || measure > ODP_STOP_RE) return fail(ODP_EINVAL, "unknown stopping measure");
@@ -1123,6 +1185,13 @@ int odp_admm_iterate(odp_plan* P, void* dev_state, int32_t n_iter, double* dev_s
     if (!rc && P->blind) rc = odp_probe_update(P, dev_state, s);
     if (!rc) rc = odp_pixel_update(P, dev_state, st, s);
     if (rc) return rc;
+    if (P->balancing()) {
+      ++P->bal_count;
+      if (P->bal_count % P->bal_period == 0 && (P->bal_until == 0 || P->bal_count <= P->bal_until)) {
+        rc = balance_penalties(P, static_cast<char*>(dev_state), s);
+        if (rc) return rc;
+      }
+    }
   }
   return ODP_OK;
 }
@@ -1221,9 +1290,10 @@ int odp_plan_autotune(odp_plan* P, void* dev_scratch_state, int32_t iters, hipSt
   int bt = P->transform, bx = P->xcd_slice, bs = P->ts, tried = 0;
   int rc = ODP_OK;
   // time whole iterations: no problem of the scratch state may stop early
-  const int32_t sm = P->stop_measure, smax = P->stop_max_iter;
+  const int32_t sm = P->stop_measure, smax = P->stop_max_iter, bp = P->bal_period;
   P->stop_measure = ODP_STOP_NONE;
   P->stop_max_iter = 0;
+  P->bal_period = 0;
   for (int tr : transforms) {
     for (int xs = 2; xs >= 0 && !rc; --xs) {
       for (int ts = 0; ts < 3 && !rc; ++ts) {
@@ -1254,6 +1324,7 @@ int odp_plan_autotune(odp_plan* P, void* dev_scratch_state, int32_t iters, hipSt
   hipEventDestroy(e1);
   P->stop_measure = sm;
   P->stop_max_iter = smax;
+  P->bal_period = bp;
   if (rc) return rc;
   rc = odp_plan_set_tuning(P, bt, bx, bs, s);
   if (rc) return rc;
@@ -1281,6 +1352,9 @@ int odp_graph_create(odp_plan* const* plans, void* const* states, int32_t n, int
   *out = nullptr;
   for (int i = 0; i < n; ++i)
     if (!plans[i] || !states[i] || !plans[i]->wsp) return fail(ODP_EINVAL, "unbound plan or null state");
+  for (int i = 0; i < n; ++i)
+    if (plans[i]->balancing())
+      return fail(ODP_EUNSUPPORTED, "penalty balancing reads residuals on the host: not in a graph");
   // One capture stream forks into one stream per distinct plan (pairs of one plan share
   // its workspace and stay on one branch, in the given order): distinct plans touch
   // disjoint memory, so the graph holds independent chains of n_iter iterations that the

@@ -1,0 +1,123 @@
+"""GPU tests of the automatic overlap penalty (residual balancing on the consensus
+constraints): the penalties the library picks, and the iterates, against the FP64
+oracle's balanced runs."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2011_00162_amd as odp
+from oracle import balance
+from oracle.od2p import od2pm_run
+from tests.gpu_util import dev_c64, dev_f32, gpu_plan, host, rel_list, rounded_inputs, same_state
+from tests.oracle_problems import oracle_problem, tiny_spec
+
+pytestmark = pytest.mark.gpu
+
+# every check's ratio rp/rd stays this factor away from mu and 1/mu, so the GPU's
+# residuals (FP32 iterates, FP64 sums) take the oracle's decisions
+MARGIN = 1.03
+PERIOD = 4
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+
+
+def _balanced(P, K, mu):
+    w, _, f = rounded_inputs(P)
+    tr = []
+    st, _, rh = balance.od2pm_run_balanced(P["geom"], w, f, P["eps"], P["eta"], P["r"], K, mu=mu, period=PERIOD,
+                                           trace=tr)
+    return st, rh, tr
+
+
+def _clear(tr, mu):
+    lm = math.log(mu)
+    return all(abs(abs(math.log(rp / rd)) - lm) >= math.log(MARGIN) for _, rp, rd in tr
+               if np.isfinite(rp) and np.isfinite(rd))
+
+
+def _pick_mu(Ps, K):
+    """The first mu whose oracle runs keep every check clear of both thresholds and
+    change r at least once."""
+    for mu in (10.0, 8.0, 6.0, 5.0, 4.0, 3.0):
+        runs = [_balanced(P, K, mu) for P in Ps]
+        if all(_clear(tr, mu) for _, _, tr in runs) and any(len(set(rh)) > 1 for _, rh, _ in runs):
+            return mu, runs
+    pytest.fail("no mu with margin")
+
+
+def test_single_problem_penalties_follow_the_oracle():
+    spec = tiny_spec(n=160, p=32, step=8, jitter=2, dy=1, dx=4, radius=12, peak=None)
+    say("balance single")
+    P = oracle_problem(spec)
+    K = 24
+    mu, [(ost, rh, _)] = _pick_mu([P], K)
+    plan = gpu_plan(P)
+    plan.set_balancing(mu, 2.0, PERIOD, 0)
+    st = plan.new_state()
+    got = []
+    for _ in range(K // PERIOD):
+        plan.iterate(st, PERIOD)
+        got.append(plan.penalties()[0])
+    want = rh[PERIOD - 1::PERIOD]
+    say("balance r/r0", [g / P["r"] for g in got], "mu", mu)
+    assert all(math.isclose(g, x, rel_tol=1e-12) for g, x in zip(got, want)), (got, want)
+    assert len(set(got)) > 1
+    assert rel_list([host(t) for t in st.u_sub()], ost.u) <= 1e-4
+
+
+def test_batch_penalties_adapt_per_problem_and_graphs_refuse():
+    say("balance batch")
+    specs = [tiny_spec(n=128, p=32, step=8, jitter=1, dy=2, dx=2, radius=12, peak=1e4, seed=41),
+             tiny_spec(n=160, p=32, step=8, jitter=2, dy=1, dx=4, radius=12, peak=None, seed=42),
+             tiny_spec(n=96, p=32, step=8, jitter=1, dy=1, dx=1, radius=12, peak=1e4, seed=43)]
+    Ps = [oracle_problem(s) for s in specs]
+    K = 16
+    mu, runs = _pick_mu(Ps, K)
+    plan = odp.Plan.batch([dict(H=P["pr"]["spec"].n, W=P["pr"]["spec"].n, p=32, offsets=P["pr"]["offsets"],
+                                frame_sub=P["pr"]["frame_sub"], r=P["r"]) for P in Ps])
+    plan.bind(dev_f32(np.concatenate([rounded_inputs(P)[1] for P in Ps])),
+              dev_c64(np.stack([rounded_inputs(P)[0] for P in Ps])))
+    plan.set_balancing(mu, 2.0, PERIOD, 0)
+    st = plan.new_state()
+    with pytest.raises(odp.OdpError):
+        odp.Graph([plan], [st], 2)                  # host-driven: not capturable
+    plan.iterate(st, K)
+    got = plan.penalties()
+    for i, ((ost, rh, _), P) in enumerate(zip(runs, Ps)):
+        assert math.isclose(got[i], rh[-1], rel_tol=1e-12), (i, got[i], rh[-1])
+        e = plan.entry(i)
+        # the K-iteration reconstruction bound
+        assert rel_list([host(t) for t in st.u_sub()[e.D0:e.D0 + e.D]], ost.u) <= 1e-3, i
+    assert got[2] == Ps[2]["r"]                     # one subdomain: nothing to balance
+
+
+def test_balancing_off_and_until():
+    spec = tiny_spec(n=128, p=32, step=8, jitter=1, dy=2, dx=2, radius=12, peak=1e4)
+    say("balance off / until")
+    P = oracle_problem(spec)
+    plan = gpu_plan(P)
+    plan.set_balancing(np.inf, 2.0, 1, 0)           # checks every iteration, never triggers
+    a = plan.new_state()
+    plan.iterate(a, 6)
+    assert plan.penalties() == [P["r"]]
+    plan.set_balancing(10.0, 2.0, 0, 0)             # off
+    b = plan.new_state()
+    plan.iterate(b, 6, stats=True)
+    assert same_state(a, b)
+    w, _, f = rounded_inputs(P)
+    tr = []
+    _, _, rh = balance.od2pm_run_balanced(P["geom"], w, f, P["eps"], P["eta"], P["r"], 12, mu=1.0, period=1,
+                                          until=3, trace=tr)
+    assert _clear(tr, 1.0)
+    plan.set_params(r=P["r"])
+    plan.set_balancing(1.0, 2.0, 1, 3)              # mu = 1: a change at each of the first 3
+    c = plan.new_state()
+    plan.iterate(c, 12)
+    assert math.isclose(plan.penalties()[0], rh[-1], rel_tol=1e-12)
+    assert rh[2] != P["r"] and rh[3:] == [rh[2]] * 9

@@ -199,3 +199,18 @@ def test_stopping_arguments_are_checked():
     assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_RE, 1e-3, 200) == 0
     assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_NONE, float("nan"), 7) == 0
     assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_NONE, 0.0, 0) == 0
+
+
+def test_balancing_arguments_are_checked():
+    plan = odp.Plan(**_plan_args())
+    L = odp.lib()
+    assert L.odp_plan_set_balancing(None, 10.0, 2.0, 10, 0) == ODP_EINVAL
+    assert L.odp_plan_set_balancing(plan._h, 10.0, 2.0, -1, 0) == ODP_EINVAL      # negative period
+    assert L.odp_plan_set_balancing(plan._h, 10.0, 2.0, 10, -1) == ODP_EINVAL     # negative limit
+    assert L.odp_plan_set_balancing(plan._h, 0.5, 2.0, 10, 0) == ODP_EINVAL       # mu < 1
+    assert L.odp_plan_set_balancing(plan._h, 10.0, 1.0, 10, 0) == ODP_EINVAL      # tau <= 1
+    assert L.odp_plan_set_balancing(plan._h, 10.0, float("inf"), 10, 0) == ODP_EINVAL
+    assert L.odp_plan_set_balancing(plan._h, float("nan"), 2.0, 10, 0) == ODP_EINVAL
+    assert L.odp_plan_set_balancing(plan._h, 10.0, 2.0, 10, 500) == 0
+    assert L.odp_plan_set_balancing(plan._h, float("inf"), 2.0, 1, 0) == 0         # never triggers
+    assert L.odp_plan_set_balancing(plan._h, 0.0, 0.0, 0, 0) == 0                  # off: values unchecked
