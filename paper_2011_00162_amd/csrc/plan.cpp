@@ -986,6 +986,9 @@ static PixelArgs pixel_args(const odp_plan* P, char* b, double* stats) {
 // multipliers Lam <- Lam r_old / r_new.  Reads the sums to the host (synchronises).
 static int balance_penalties(odp_plan* P, char* b, hipStream_t s) {
   const int n = P->n_probes();
+  bool any_pairs = false;
+  for (const odp_plan::Entry& e : P->batch) any_pairs = any_pairs || e.D >= 2;
+  if (!any_pairs) return ODP_OK;   // nothing to balance: no read, no synchronisation
   double* dev = P->W_<double>(P->ws.resid);
   ODP_HIP(launch_residual_sums(P->W_<double>(P->ws.tpart), P->W_<int32_t>(P->ws.re_list),
                                P->W_<int32_t>(P->ws.re_first), P->D, P->W_<int32_t>(P->ws.prob), n,
