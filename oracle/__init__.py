@@ -16,6 +16,8 @@ od2p       Algorithm 2 (OD2Pm; Algorithm 1 is D=2), an undecomposed ADMM, merge,
            augmented Lagrangian (Sec. 2.3, 3.1, 4)
 blind      Algorithm 3 (OD2BP) with the probe-support projection (Sec. 3.2)
 amploss    amplitude data-term loss and its gradient in u and w
+local      one iteration of Algorithm 2 or 3 on chosen subdomains only (sampled checks at
+           full problem sizes)
 balance    overlap penalty r chosen by residual balancing (future work of Sec. 4.3 and 5;
            He, Yang and Wang 2000; Boyd et al. 2011, Sec. 3.4.1)
 """

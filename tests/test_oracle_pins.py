@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import synthetic
-from oracle import amploss, balance, blind, operators as ops, stagm
+from oracle import amploss, balance, blind, local, operators as ops, stagm
 from oracle.geometry import build_geometry, cover_count, multiplicity, overlap_width, GeometryError
 from oracle.od2p import (admm_undecomposed, augmented_lagrangian, init_state, merge, od2pm_run,
                          od2pm_step, forward_sub, adjoint_sub, run_until, subdomain_illumination, snr_db)
@@ -659,3 +659,63 @@ def test_penalty_change_keeps_the_unscaled_multipliers():
     for key in bal.lam:
         assert np.array_equal(rh[k] * bal.lam[key], rh[k - 1] * plain.lam[key])
     assert all(np.array_equal(x, y) for x, y in zip(bal.u, plain.u))
+
+
+# ---------------------------------------------------------------------------
+# T22  the iteration on chosen subdomains equals the whole iteration there
+# ---------------------------------------------------------------------------
+
+def _random_state(g, rng):
+    st = init_state(g)
+    st.u = [1.0 + 0.3 * crandn(*a.shape, rng=rng) for a in st.u]
+    st.gamma = 0.2 * crandn(*st.gamma.shape, rng=rng)
+    st.lam = {k: 0.1 * crandn(*a.shape, rng=rng) for k, a in st.lam.items()}
+    return st
+
+
+def _same(a, b):
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-12 * max(1.0, float(np.abs(b).max())))
+
+
+def test_local_step_equals_full_step():
+    P = oracle_problem(tiny_spec(dy=3, dx=3, n=40, step=4, peak=1e3))
+    g, w, f = P["geom"], P["pr"]["w"], P["f"]
+    rng = np.random.default_rng(5)
+    st = _random_state(g, rng)
+    full, _ = od2pm_step(g, w, f, st, P["eps"], P["eta"], P["r"])
+    subs = [0, 4, 8]                                   # a corner, the centre (8 neighbours), a corner
+    loc = local.od2pm_step_local(g, w, f, st.u, st.lam, st.gamma, P["eps"], P["eta"], P["r"], subs)
+    assert sorted(loc["u"]) == subs
+    for d in subs:
+        _same(loc["u"][d], full.u[d])
+        for j in g.frames_of[d]:
+            _same(loc["gamma"][j], full.gamma[j])
+    assert {k[0] for k in loc["lam"]} == set(subs)
+    for k, a in loc["lam"].items():
+        _same(a, full.lam[k])
+
+
+@pytest.mark.parametrize("mu,gamma_p", [(3.0, 0.5), (np.inf, 0.0)])
+def test_local_blind_step_equals_full_step(mu, gamma_p):
+    P = oracle_problem(tiny_spec(dy=2, dx=3, n=36, step=4, peak=1e3))
+    g, w, f = P["geom"], P["pr"]["w"], P["f"]
+    rng = np.random.default_rng(6)
+    s0 = _random_state(g, rng)
+    st = blind.init_state(g, w)
+    st.u, st.gamma, st.lam = s0.u, s0.gamma, s0.lam
+    st.w_sub = [w * (1.0 + 0.05 * crandn(*w.shape, rng=rng)) for _ in range(g.D)]
+    st.delta = [0.01 * crandn(*w.shape, rng=rng) for _ in range(g.D)]
+    mask = (rng.random(w.shape) < 0.8).astype(float)
+    full, _ = blind.od2bp_step(g, f, st, P["eps"], P["eta"], P["r"], mu, gamma_p, mask)
+    subs = [1, 5]
+    loc = local.od2bp_step_local(g, f, st.u, st.lam, st.gamma, st.w_sub, st.delta, P["eps"], P["eta"], P["r"], mu,
+                                 subs, gamma_p=gamma_p, mask=mask)
+    _same(loc["w"], full.w)
+    for d in subs:
+        _same(loc["u"][d], full.u[d])
+        _same(loc["w_sub"][d], full.w_sub[d])
+        _same(loc["delta"][d], full.delta[d])
+        for j in g.frames_of[d]:
+            _same(loc["gamma"][j], full.gamma[j])
+    for k, a in loc["lam"].items():
+        _same(a, full.lam[k])
