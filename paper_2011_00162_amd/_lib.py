@@ -25,6 +25,7 @@ EXPORTS = [
     "odp_batch_plan_create", "odp_batch_get_entry", "odp_batch_set_penalties", "odp_plan_get_tuning",
     "odp_plan_set_tuning", "odp_plan_autotune", "odp_graph_create", "odp_graph_launch", "odp_graph_destroy",
     "odp_plan_set_sweep_events", "odp_plan_set_stopping", "odp_state_get_stop_status", "odp_plan_set_balancing",
+    "odp_plan_workspace_bytes", "odp_state_bytes",
 ]
 
 
@@ -113,6 +114,8 @@ def lib() -> C.CDLL:
         "odp_plan_set_tuning": (C.c_int, [vp, i32, i32, i32, vp]),
         "odp_plan_set_stopping": (C.c_int, [vp, i32, C.c_double, i32]),
         "odp_plan_set_balancing": (C.c_int, [vp, C.c_double, C.c_double, i32, i32]),
+        "odp_plan_workspace_bytes": (C.c_size_t, [vp]),
+        "odp_state_bytes": (C.c_size_t, [vp]),
         "odp_state_get_stop_status": (C.c_int, [vp, vp, vp, vp]),
         "odp_plan_autotune": (C.c_int, [vp, vp, i32, vp, C.POINTER(Tuning)]),
         "odp_graph_create": (C.c_int, [vp, vp, i32, i32, C.POINTER(vp)]),

@@ -760,6 +760,9 @@ int odp_plan_get_info(const odp_plan* P, odp_plan_info* o) {
   return ODP_OK;
 }
 
+size_t odp_plan_workspace_bytes(const odp_plan* P) { return P ? P->ws.bytes : 0; }
+size_t odp_state_bytes(const odp_plan* P) { return P ? P->st.bytes : 0; }
+
 int odp_state_get_layout(const odp_plan* P, odp_state_layout* o) {
   if (!P || !o) return fail(ODP_EINVAL, "null argument");
   o->u_sub = P->st.u_sub;

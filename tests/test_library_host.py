@@ -214,3 +214,11 @@ def test_balancing_arguments_are_checked():
     assert L.odp_plan_set_balancing(plan._h, 10.0, 2.0, 10, 500) == 0
     assert L.odp_plan_set_balancing(plan._h, float("inf"), 2.0, 1, 0) == 0         # never triggers
     assert L.odp_plan_set_balancing(plan._h, 0.0, 0.0, 0, 0) == 0                  # off: values unchecked
+
+
+def test_size_helpers_match_plan_info():
+    plan = odp.Plan(**_plan_args())
+    L = odp.lib()
+    assert L.odp_plan_workspace_bytes(plan._h) == plan.info.workspace_bytes > 0
+    assert L.odp_state_bytes(plan._h) == plan.info.state_bytes > 0
+    assert L.odp_plan_workspace_bytes(None) == 0 and L.odp_state_bytes(None) == 0
