@@ -15,17 +15,31 @@
 
 namespace odp {
 
-// (1/D) sum_d (w_d + Delta_d) per probe pixel, FP64 over d in ascending order
+// (1/D) sum_d (w_d + Delta_d) per probe pixel in FP64: the four wavefronts of a workgroup
+// take every fourth copy (ascending within each) for the same 64 pixels, and their partial
+// sums are added in wavefront order
 __global__ __launch_bounds__(256) void k_probe_avg(ProbeArgs a) {
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= a.p * a.p || (a.stop && a.stop[0].stopped)) return;
+  __shared__ double part[2][4][64];
+  if (a.stop && a.stop[0].stopped) return;  // uniform over the workgroup
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int k = blockIdx.x * 64 + lane;
+  const bool ok = k < a.p * a.p;
   const size_t pp = (size_t)a.p * a.p;
   double sx = 0.0, sy = 0.0;
-  for (int d = 0; d < a.D; ++d) {
-    const float2 ws = a.w_sub[d * pp + k], dl = a.delta[d * pp + k];
-    sx += (double)ws.x + dl.x;
-    sy += (double)ws.y + dl.y;
+  if (ok) {
+#pragma unroll 4
+    for (int d = grp; d < a.D; d += 4) {
+      const float2 ws = a.w_sub[d * pp + k], dl = a.delta[d * pp + k];
+      sx += (double)ws.x + dl.x;
+      sy += (double)ws.y + dl.y;
+    }
   }
+  part[0][grp][lane] = sx;
+  part[1][grp][lane] = sy;
+  __syncthreads();
+  if (grp != 0 || !ok) return;
+  sx = ((part[0][0][lane] + part[0][1][lane]) + part[0][2][lane]) + part[0][3][lane];
+  sy = ((part[1][0][lane] + part[1][1][lane]) + part[1][2][lane]) + part[1][3][lane];
   const double invD = 1.0 / (double)a.D;
   a.w[k] = make_float2((float)(sx * invD), (float)(sy * invD));
 }
@@ -69,15 +83,32 @@ __global__ __launch_bounds__(256) void k_probe_copies(ProbeArgs a) {
   const int ky = kk / p, kx = kk % p;
   double nr = 0.0, ni = 0.0, den = 0.0;
   const int q1 = a.sub_first[d + 1];
-#pragma unroll 2
-  for (int q = a.sub_first[d] + grp; q < q1; q += 4) {
-    const int j = a.order[q];
-    const FrameDesc fd = a.frames[j];
-    const float2 pu = a.u[fd.base + (int64_t)ky * fd.pitch + kx];
-    const float2 ph = a.phi[(size_t)j * p * p + kk];
+  const size_t pp = (size_t)p * p;
+  auto acc = [&](const float2 pu, const float2 ph) {
     nr += (double)pu.x * ph.x + (double)pu.y * ph.y;   // conj(S_j u) o phi
     ni += (double)pu.x * ph.y - (double)pu.y * ph.x;
     den += (double)pu.x * pu.x + (double)pu.y * pu.y;
+  };
+  // four frames of this wavefront per step: their descriptors (one scalar load each, from
+  // the subdomain-grouped array) and then all eight vector loads are issued before the
+  // sums, which take the frames in ascending order
+  int qi = a.sub_first[d] + grp;
+  for (; qi + 12 < q1; qi += 16) {
+    FrameDesc f[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) f[i] = a.fpos[qi + 4 * i];
+    float2 pu[4], ph[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      pu[i] = a.u[f[i].base + (int64_t)ky * f[i].pitch + kx];
+      ph[i] = a.phi[(size_t)f[i].j * pp + kk];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc(pu[i], ph[i]);
+  }
+  for (; qi < q1; qi += 4) {
+    const FrameDesc fd = a.fpos[qi];
+    acc(a.u[fd.base + (int64_t)ky * fd.pitch + kx], a.phi[(size_t)fd.j * pp + kk]);
   }
   part[0][grp][lane] = nr;
   part[1][grp][lane] = ni;
@@ -157,7 +188,7 @@ hipError_t launch_init_probe(const InitProbeArgs& a, hipStream_t s) {
 
 hipError_t launch_probe_update(const ProbeArgs& a, hipStream_t s) {
   const int pp = a.p * a.p;
-  hipLaunchKernelGGL(k_probe_avg, dim3((pp + 255) / 256), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_probe_avg, dim3((pp + 63) / 64), dim3(256), 0, s, a);
   if (a.fmask) {
 #define ODP_PROJ(PP) \
   if (a.p == PP) hipLaunchKernelGGL((k_probe_project<PP>), dim3(1), dim3(Frame<PP>::T), 0, s, a);

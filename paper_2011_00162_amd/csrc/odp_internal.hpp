@@ -172,6 +172,7 @@ struct ProbeArgs {
   const float2* phi;         // F^{-1}(Z - Gamma) per frame
   const FrameDesc* frames;
   const int32_t* order;      // frames grouped by subdomain
+  const FrameDesc* fpos;     // frames[order[q]] by position q (one load per frame)
   const int32_t* sub_first;  // [D+1]
   int32_t D, p;
   float2* w;                 // shared probe w (out: w^{n+1})

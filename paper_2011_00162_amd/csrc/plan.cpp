@@ -1105,6 +1105,7 @@ int odp_probe_update(odp_plan* P, void* dev_state, hipStream_t s) {
   a.phi = P->W_<float2>(P->ws.psi);
   a.frames = P->W_<FrameDesc>(P->ws.frames);
   a.order = P->W_<int32_t>(P->ws.order);
+  a.fpos = P->W_<FrameDesc>(P->ws.fpos);
   a.sub_first = P->W_<int32_t>(P->ws.sub_first);
   a.D = P->D;
   a.p = P->p;
