@@ -6,8 +6,8 @@
 //  Delta_d^{n+1} = Delta_d^n + w_d^{n+1} - w^{n+1}                     (eq. admm_Delta)
 // with phi_j = F^{-1}(Z_j - Gamma_j) from the frame sweep and P_O = F^{-1} M F the
 // projection onto probes whose spectrum vanishes off the support mask M.
-// The frame sums run in FP64 in a fixed order (four interleaved ascending partial
-// sums per subdomain, added in order), so repeated runs agree bit for bit.
+// The frame sums run in FP64 in a fixed order (ascending over the frames of a subdomain),
+// so repeated runs agree bit for bit.
 #include <hip/hip_runtime.h>
 
 #include "fft_frame.hpp"
@@ -70,59 +70,49 @@ __global__ __launch_bounds__(Frame<P>::T) void k_probe_project(ProbeArgs a) {
   for (int r1 = 0; r1 < 16; ++r1) a.w[(F::N2 * r1 + r2) * P + col] = v[r1];
 }
 
-// w_d and Delta_d for 64 probe pixels of subdomain d: the four wavefronts take every
-// fourth frame of the subdomain (frame order ascending within each), and their FP64
-// partial sums are added in wavefront order.
+// w_d and Delta_d for 256 probe pixels of subdomain d, one per thread: the sums run over
+// the frames of d in ascending order, eight frames' loads in flight per step, so that a
+// workgroup reads 2 KB contiguous of each frame's phi and of its u window rows.
 __global__ __launch_bounds__(256) void k_probe_copies(ProbeArgs a) {
-  __shared__ double part[3][4][64];
   if (a.stop && a.stop[0].stopped) return;  // uniform over the workgroup
-  const int p = a.p, d = blockIdx.y, lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int k = blockIdx.x * 64 + lane;
+  constexpr int B = 8;
+  const int p = a.p, d = blockIdx.y;
+  const int k = blockIdx.x * 256 + threadIdx.x;
   const bool ok = k < p * p;
   const int kk = ok ? k : 0;
   const int ky = kk / p, kx = kk % p;
-  double nr = 0.0, ni = 0.0, den = 0.0;
-  const int q1 = a.sub_first[d + 1];
   const size_t pp = (size_t)p * p;
+  double nr = 0.0, ni = 0.0, den = 0.0;
   auto acc = [&](const float2 pu, const float2 ph) {
     nr += (double)pu.x * ph.x + (double)pu.y * ph.y;   // conj(S_j u) o phi
     ni += (double)pu.x * ph.y - (double)pu.y * ph.x;
     den += (double)pu.x * pu.x + (double)pu.y * pu.y;
   };
-  // four frames of this wavefront per step: their descriptors (one scalar load each, from
-  // the subdomain-grouped array) and then all eight vector loads are issued before the
-  // sums, which take the frames in ascending order
-  int qi = a.sub_first[d] + grp;
-  for (; qi + 12 < q1; qi += 16) {
-    FrameDesc f[4];
+  const int q1 = a.sub_first[d + 1];
+  int q = a.sub_first[d];
+  for (; q + B <= q1; q += B) {
+    FrameDesc f[B];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) f[i] = a.fpos[qi + 4 * i];
-    float2 pu[4], ph[4];
+    for (int i = 0; i < B; ++i) f[i] = a.fpos[q + i];   // workgroup-uniform: scalar loads
+    float2 pu[B], ph[B];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < B; ++i) {
       pu[i] = a.u[f[i].base + (int64_t)ky * f[i].pitch + kx];
       ph[i] = a.phi[(size_t)f[i].j * pp + kk];
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) acc(pu[i], ph[i]);
+    for (int i = 0; i < B; ++i) acc(pu[i], ph[i]);
   }
-  for (; qi < q1; qi += 4) {
-    const FrameDesc fd = a.fpos[qi];
+  for (; q < q1; ++q) {
+    const FrameDesc fd = a.fpos[q];
     acc(a.u[fd.base + (int64_t)ky * fd.pitch + kx], a.phi[(size_t)fd.j * pp + kk]);
   }
-  part[0][grp][lane] = nr;
-  part[1][grp][lane] = ni;
-  part[2][grp][lane] = den;
-  __syncthreads();
-  if (grp != 0 || !ok) return;
-  nr = ((part[0][0][lane] + part[0][1][lane]) + part[0][2][lane]) + part[0][3][lane];
-  ni = ((part[1][0][lane] + part[1][1][lane]) + part[1][2][lane]) + part[1][3][lane];
-  den = ((part[2][0][lane] + part[2][1][lane]) + part[2][2][lane]) + part[2][3][lane];
-  const size_t o = (size_t)d * p * p + k;
+  if (!ok) return;
+  const size_t o = (size_t)d * pp + k;
   const float2 w = a.w[k], dl = a.delta[o];
-  const double q = a.eta * den + a.mu;
-  const double wx = (a.eta * nr + a.mu * ((double)w.x - dl.x)) / q;
-  const double wy = (a.eta * ni + a.mu * ((double)w.y - dl.y)) / q;
+  const double qd = a.eta * den + a.mu;
+  const double wx = (a.eta * nr + a.mu * ((double)w.x - dl.x)) / qd;
+  const double wy = (a.eta * ni + a.mu * ((double)w.y - dl.y)) / qd;
   a.w_sub[o] = make_float2((float)wx, (float)wy);
   a.delta[o] = make_float2((float)((double)dl.x + wx - w.x), (float)((double)dl.y + wy - w.y));
 }
@@ -197,7 +187,7 @@ hipError_t launch_probe_update(const ProbeArgs& a, hipStream_t s) {
     ODP_PROJ(128)
 #undef ODP_PROJ
   }
-  hipLaunchKernelGGL(k_probe_copies, dim3((pp + 63) / 64, a.D), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_probe_copies, dim3((pp + 255) / 256, a.D), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
