@@ -1327,8 +1327,8 @@ int odp_plan_autotune(odp_plan* P, void* dev_scratch_state, int32_t iters, hipSt
       }
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   P->stop_measure = sm;
   P->stop_max_iter = smax;
   P->bal_period = bp;
@@ -1381,9 +1381,9 @@ int odp_graph_create(odp_plan* const* plans, void* const* states, int32_t n, int
   std::vector<hipEvent_t> ev(nb + 1, nullptr);
   auto cleanup = [&]() {
     for (hipEvent_t e : ev)
-      if (e) hipEventDestroy(e);
+      if (e) (void)hipEventDestroy(e);
     for (hipStream_t q : ss)
-      if (q) hipStreamDestroy(q);
+      if (q) (void)hipStreamDestroy(q);
   };
   for (int b = 0; b <= nb; ++b) {
     if (hipStreamCreateWithFlags(&ss[b], hipStreamNonBlocking) != hipSuccess ||
@@ -1414,19 +1414,19 @@ int odp_graph_create(odp_plan* const* plans, void* const* states, int32_t n, int
   const hipError_t ec = hipStreamEndCapture(cs, &g);
   cleanup();
   if (rc) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return rc;
   }
   if (ec != hipSuccess || !g) return fail(ODP_EHIP, "hipStreamEndCapture failed");
   hipGraphExec_t ex = nullptr;
   if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     return fail(ODP_EHIP, "hipGraphInstantiate failed");
   }
   odp_graph* G = new (std::nothrow) odp_graph();
   if (!G) {
-    hipGraphExecDestroy(ex);
-    hipGraphDestroy(g);
+    (void)hipGraphExecDestroy(ex);
+    (void)hipGraphDestroy(g);
     return fail(ODP_ENOMEM, "host allocation failed");
   }
   G->graph = g;
@@ -1443,8 +1443,8 @@ int odp_graph_launch(odp_graph* G, hipStream_t s) {
 
 void odp_graph_destroy(odp_graph* G) {
   if (!G) return;
-  if (G->exec) hipGraphExecDestroy(G->exec);
-  if (G->graph) hipGraphDestroy(G->graph);
+  if (G->exec) (void)hipGraphExecDestroy(G->exec);
+  if (G->graph) (void)hipGraphDestroy(G->graph);
   delete G;
 }
 
