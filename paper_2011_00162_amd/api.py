@@ -221,7 +221,10 @@ class Plan:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            lib().odp_plan_destroy(h)
+            try:
+                lib().odp_plan_destroy(h)
+            except (AttributeError, TypeError, ImportError):
+                pass   # interpreter shutdown: module state is gone and the process frees the plan
             self._h = None
 
     # ---- geometry exports (host, no device needed) ----
@@ -363,5 +366,8 @@ class Graph:
     def __del__(self):
         g = getattr(self, "_g", None)
         if g is not None and g.value:
-            lib().odp_graph_destroy(g)
+            try:
+                lib().odp_graph_destroy(g)
+            except (AttributeError, TypeError, ImportError):
+                pass   # interpreter shutdown
             self._g = None
