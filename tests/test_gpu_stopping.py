@@ -185,3 +185,44 @@ def test_batch_problems_stop_independently_also_in_a_graph():
             assert after[i] == stat[i] and same_u and same_g, i
         else:
             assert after[i]["iters"] > K and not same_u, i
+
+
+def _cap_freezes(plan, cap=2, extra=2):
+    """With the rule off but an iteration cap, a longer run stops at the cap and equals a
+    run of exactly that many iterations (statistics variants on both sides)."""
+    plan.set_stopping(odp.ODP_STOP_NONE, 0.0, cap)
+    st = plan.new_state()
+    plan.iterate(st, cap + extra)
+    assert [(s["iters"], s["stopped"]) for s in plan.stop_status(st)] == [(cap, True)] * plan.n_problems()
+    plan.set_stopping(odp.ODP_STOP_NONE, 0.0, 0)
+    ref = plan.new_state()
+    plan.iterate(ref, cap, stats=True)
+    assert same_state(st, ref)
+
+
+def test_cap_with_the_mfma_transform():
+    """The split-BF16 sweep's persistent loop skips a stopped problem's frames."""
+    spec = tiny_spec(n=192, p=64, step=16, jitter=2, dy=2, dx=2, radius=24, peak=1e4)
+    say("stop cap, split-BF16 transform")
+    P = oracle_problem(spec)
+    w, sf32, _ = rounded_inputs(P)
+    plan = odp.Plan(spec.n, spec.n, 64, P["pr"]["offsets"], P["pr"]["frame_sub"], r=P["r"],
+                    transform=odp.ODP_DFT_SPLIT_BF16)
+    plan.bind(dev_f32(sf32), dev_c64(w))
+    _cap_freezes(plan)
+
+
+def test_cap_with_five_to_eight_copies():
+    """Cells with five or more copies (the general pixel kernel) also stop."""
+    from oracle.geometry import build_geometry
+    spec = tiny_spec(n=96, p=32, step=8, jitter=1, radius=12, peak=1e4)
+    say("stop cap, six copies per pixel")
+    P = oracle_problem(spec)
+    pr = P["pr"]
+    pr["frame_sub"] = (np.arange(len(pr["offsets"])) % 6).astype(np.int32)
+    g = build_geometry(spec.n, spec.n, spec.p, pr["offsets"], pr["frame_sub"])
+    from oracle.od2p import subdomain_illumination
+    r = 0.5 * 0.1 * max(float(subdomain_illumination(g, pr["w"], d).max()) for d in range(g.D))
+    plan = gpu_plan(P, r=r)
+    assert plan.info.max_cover == 6
+    _cap_freezes(plan)
