@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libodp.so")
 ODP_OK, ODP_EINVAL, ODP_EGEOM, ODP_EHIP, ODP_ENOMEM, ODP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 ODP_FFT_F32, ODP_DFT_SPLIT_BF16 = 0, 1
 ODP_STOP_NONE, ODP_STOP_RF, ODP_STOP_RE = 0, 1, 2
+ODP_BALANCE_R, ODP_BALANCE_ETA = 1, 2
 
 # every symbol include/odp.h declares
 EXPORTS = [
@@ -25,7 +26,7 @@ EXPORTS = [
     "odp_batch_plan_create", "odp_batch_get_entry", "odp_batch_set_penalties", "odp_plan_get_tuning",
     "odp_plan_set_tuning", "odp_plan_autotune", "odp_graph_create", "odp_graph_launch", "odp_graph_destroy",
     "odp_plan_set_sweep_events", "odp_plan_set_stopping", "odp_state_get_stop_status", "odp_plan_set_balancing",
-    "odp_plan_workspace_bytes", "odp_state_bytes",
+    "odp_plan_workspace_bytes", "odp_state_bytes", "odp_plan_get_eta",
 ]
 
 
@@ -113,7 +114,8 @@ def lib() -> C.CDLL:
         "odp_plan_get_tuning": (C.c_int, [vp, C.POINTER(Tuning)]),
         "odp_plan_set_tuning": (C.c_int, [vp, i32, i32, i32, vp]),
         "odp_plan_set_stopping": (C.c_int, [vp, i32, C.c_double, i32]),
-        "odp_plan_set_balancing": (C.c_int, [vp, C.c_double, C.c_double, i32, i32]),
+        "odp_plan_set_balancing": (C.c_int, [vp, C.c_double, C.c_double, i32, i32, i32]),
+        "odp_plan_get_eta": (C.c_double, [vp]),
         "odp_plan_workspace_bytes": (C.c_size_t, [vp]),
         "odp_state_bytes": (C.c_size_t, [vp]),
         "odp_state_get_stop_status": (C.c_int, [vp, vp, vp, vp]),

@@ -9,8 +9,8 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from ._lib import (ODP_FFT_F32, ODP_STOP_NONE, BatchEntry, PlanInfo, Problem, StateLayout, StopStatus, Tuning,
-                   check, lib)
+from ._lib import (ODP_BALANCE_R, ODP_FFT_F32, ODP_STOP_NONE, BatchEntry, PlanInfo, Problem, StateLayout, StopStatus,
+                   Tuning, check, lib)
 
 
 def _stream(stream=None) -> C.c_void_p:
@@ -198,9 +198,15 @@ class Plan:
         iteration cap); applies to later iterations and graphs created afterwards."""
         check(lib().odp_plan_set_stopping(self._h, int(measure), float(tol), int(max_iter)))
 
-    def set_balancing(self, mu: float = 10.0, tau: float = 2.0, period: int = 0, until: int = 0) -> None:
-        """Overlap penalties by residual balancing every `period` iterations (0: off)."""
-        check(lib().odp_plan_set_balancing(self._h, float(mu), float(tau), int(period), int(until)))
+    def set_balancing(self, mu: float = 10.0, tau: float = 2.0, period: int = 0, until: int = 0,
+                      which: int = ODP_BALANCE_R) -> None:
+        """Penalties by residual balancing every `period` iterations (0: off): the overlap
+        penalties (ODP_BALANCE_R), the data penalty (ODP_BALANCE_ETA) or both."""
+        check(lib().odp_plan_set_balancing(self._h, float(mu), float(tau), int(period), int(until), int(which)))
+
+    def eta(self) -> float:
+        """The current data penalty (changed by balancing)."""
+        return float(lib().odp_plan_get_eta(self._h))
 
     def penalties(self) -> list[float]:
         """The overlap penalty r of each problem (changed by balancing)."""

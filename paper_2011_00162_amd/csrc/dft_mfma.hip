@@ -138,8 +138,10 @@ __device__ __forceinline__ void cmma(floatx4& re, floatx4& im, const CS& a, cons
 
 }  // namespace
 
-template <bool BLIND, bool STATS>
+// ST: 0 no statistics, 1 the iteration's measures, 2 also the frame residuals
+template <bool BLIND, int ST>
 __global__ __launch_bounds__(256, WGS_PER_CU) void k_sweep_dft64(SweepArgs a, DftTable dt, ProxC pc) {
+  constexpr bool STATS = ST > 0;
   __shared__ __attribute__((aligned(16))) __bf16 ft[4 * PL];   // F: re hi, re lo, im hi, im lo
   __shared__ __attribute__((aligned(16))) __bf16 xb[4 * PL];   // exchange planes, same order
   __shared__ double red[4];
@@ -261,7 +263,7 @@ __global__ __launch_bounds__(256, WGS_PER_CU) void k_sweep_dft64(SweepArgs a, Df
     }
 
     // prox and Gamma update at kr = 16w + n0, kc = 16 mt + 4g + i; xr/xi become t = z - Gamma
-    double mis = 0.0, gsum = 0.0;
+    double mis = 0.0, gsum = 0.0, gdel = 0.0, gnrm = 0.0;
     {
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt) {
@@ -284,20 +286,14 @@ __global__ __launch_bounds__(256, WGS_PER_CU) void k_sweep_dft64(SweepArgs a, Df
             const double ax = sqrt((double)X.x * X.x + (double)X.y * X.y);
             mis += fabs(ax - (double)sfv[i]);
             gsum += g_eps(ax, (double)sfv[i], (double)a.eps);
+            if (ST > 1) frame_terms(gv[i], gn[i], gdel, gnrm);
           }
         }
         gp[0] = make_float4(gn[0].x, gn[0].y, gn[1].x, gn[1].y);
         gp[1] = make_float4(gn[2].x, gn[2].y, gn[3].x, gn[3].y);
       }
     }
-    if (STATS) {
-      mis = block_sum<256>(mis, red);
-      gsum = block_sum<256>(gsum, red);
-      if (t == 0) {
-        a.part[2 * j] = mis;
-        a.part[2 * j + 1] = gsum;
-      }
-    }
+    if (STATS) frame_stats<256, (ST > 1)>(a.part + NFS * (size_t)j, mis, gsum, gdel, gnrm, red);
 
     // probe values of this lane's outputs (r' = 16w + 4g + i, c' = 16 nt + n0), fetched
     // before products 3 and 4
@@ -383,11 +379,13 @@ hipError_t launch_sweep_dft(int p, const SweepArgs& a, const DftTable& dt, hipSt
   constexpr int MAXG = WGS_PER_CU * 256;
   const int G = a.xcd_slice ? NXCD * std::min(MAXG / NXCD, (int)a.chunk) : std::min(MAXG, (int)a.J);
   const dim3 grid(G), blk(256);
-  const bool st = a.part != nullptr, bl = a.blind != 0;
-  if (bl && st) hipExtLaunchKernelGGL((k_sweep_dft64<true, true>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
-  else if (bl) hipExtLaunchKernelGGL((k_sweep_dft64<true, false>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
-  else if (st) hipExtLaunchKernelGGL((k_sweep_dft64<false, true>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
-  else hipExtLaunchKernelGGL((k_sweep_dft64<false, false>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
+  const bool bl = a.blind != 0;
+  const int st = a.part == nullptr ? 0 : (a.frame_res && !bl ? 2 : 1);
+  if (bl && st) hipExtLaunchKernelGGL((k_sweep_dft64<true, 1>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
+  else if (bl) hipExtLaunchKernelGGL((k_sweep_dft64<true, 0>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
+  else if (st == 2) hipExtLaunchKernelGGL((k_sweep_dft64<false, 2>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
+  else if (st) hipExtLaunchKernelGGL((k_sweep_dft64<false, 1>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
+  else hipExtLaunchKernelGGL((k_sweep_dft64<false, 0>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
   return hipGetLastError();
 }
 

@@ -39,9 +39,11 @@ __device__ __forceinline__ int sweep_pos(int32_t chunk, int xcd_slice) {
 // Each frame's output goes to its own slot of psi, so no two workgroups write
 // the same address; the pixel update pulls the covering frames in a fixed order.
 // ---------------------------------------------------------------------------
-template <int P, bool BLIND, bool STATS>
+// ST: 0 no statistics, 1 the iteration's measures, 2 also the frame residuals
+template <int P, bool BLIND, int ST>
 __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
   using F = Frame<P>;
+  constexpr bool STATS = ST > 0;
   __shared__ __align__(16) float2 lds[F::LDS];
   __shared__ __align__(16) float2 twl[F::N2 * TWL];   // stage-B twiddles, read from LDS so that no
                                        // wait on them also waits on the prefetches
@@ -93,7 +95,7 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
       gpre[e] = a.gamma[fbase + kr * P + kc];
     }
   }
-  double mis = 0.0, gsum = 0.0;
+  double mis = 0.0, gsum = 0.0, gdel = 0.0, gnrm = 0.0;
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     int kr, kc;
@@ -104,13 +106,14 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
     const float2 y = c_add(gpre[e], X);
     const float2 z = prox_stagm(y, sf, pc);
     const float2 g = c_sub(y, z);
-    gpre[e] = g;
-    v[e] = c_scale(c_sub(z, g), inv_p);   // both 1/p factors of the unitary pair applied here
     if (STATS) {
       const double ax = sqrt((double)X.x * X.x + (double)X.y * X.y);
       mis += fabs(ax - (double)sf);
       gsum += g_eps(ax, (double)sf, (double)a.eps);
+      if (ST > 1) frame_terms(gpre[e], g, gdel, gnrm);
     }
+    gpre[e] = g;
+    v[e] = c_scale(c_sub(z, g), inv_p);   // both 1/p factors of the unitary pair applied here
   }
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
@@ -118,14 +121,7 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
     F::freq(t, e, kr, kc);
     a.gamma[fbase + kr * P + kc] = gpre[e];
   }
-  if (STATS) {
-    mis = block_sum<F::T>(mis, red);
-    gsum = block_sum<F::T>(gsum, red);
-    if (t == 0) {
-      a.part[2 * j] = mis;
-      a.part[2 * j + 1] = gsum;
-    }
-  }
+  if (STATS) frame_stats<F::T, (ST > 1)>(a.part + NFS * (size_t)j, mis, gsum, gdel, gnrm, red);
   __syncthreads();  // stage-C reads of all threads done before inverse writes reuse LDS
   F::template inverse<TWL>(v, lds, twl, t);
   // the inverse returns each thread's 16 points to the positions it gathered; the 16
@@ -145,9 +141,10 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
 // K1 at p = 128: the same step on the two-half transform (Half128: 512 threads,
 // 77 KB of LDS, two frames per CU).  The prox of each half runs between that half's
 // forward and inverse stages B and C.
-template <bool BLIND, bool STATS>
+template <bool BLIND, int ST>
 __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_sweep128(SweepArgs a, ProxC pc) {
   using F = Half128;
+  constexpr bool STATS = ST > 0;
   constexpr int P = 128;
   __shared__ __align__(16) float2 lds[F::LDS];
   __shared__ __align__(16) float2 twl[F::N2 * TWL];
@@ -198,7 +195,7 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
     asm volatile("" ::: "memory");   // the second line's loads start after this transform
   }
 
-  double mis = 0.0, gsum = 0.0;
+  double mis = 0.0, gsum = 0.0, gdel = 0.0, gnrm = 0.0;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     F::half_fwd<TWL>(v, lds, twl, t, h);
@@ -223,13 +220,14 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
         const float2 y = c_add(gpre[i], X);
         const float2 z = prox_stagm(y, sf, pc);
         const float2 g = c_sub(y, z);
-        gpre[i] = g;
-        v[e] = c_scale(c_sub(z, g), inv_p);   // both 1/p factors of the unitary pair applied here
         if (STATS) {
           const double ax = sqrt((double)X.x * X.x + (double)X.y * X.y);
           mis += fabs(ax - (double)sf);
           gsum += g_eps(ax, (double)sf, (double)a.eps);
+          if (ST > 1) frame_terms(gpre[i], g, gdel, gnrm);
         }
+        gpre[i] = g;
+        v[e] = c_scale(c_sub(z, g), inv_p);   // both 1/p factors of the unitary pair applied here
       }
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
@@ -240,14 +238,7 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
     }
     F::half_inv<TWL>(v, lds, twl, t, h);
   }
-  if (STATS) {
-    mis = block_sum<F::T>(mis, red);
-    gsum = block_sum<F::T>(gsum, red);
-    if (t == 0) {
-      a.part[2 * j] = mis;
-      a.part[2 * j + 1] = gsum;
-    }
-  }
+  if (STATS) frame_stats<F::T, (ST > 1)>(a.part + NFS * (size_t)j, mis, gsum, gdel, gnrm, red);
   // inverse stage A and the output one line at a time; the second line's probe loads
   // are issued before the first line's stores (see the prox above)
   const float2* wo = a.w_out + woff;
@@ -276,25 +267,28 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
 hipError_t launch_sweep(int p, const SweepArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const ProxC pc = prox_coeffs(a.eps, a.eta);
   const dim3 grid(NXCD * a.chunk);
-  const bool st = a.part != nullptr, bl = a.blind != 0;
+  const bool bl = a.blind != 0;
+  const int st = a.part == nullptr ? 0 : (a.frame_res && !bl ? 2 : 1);
 #define ODP_SWEEP_GO(K, T) hipExtLaunchKernelGGL(K, grid, dim3(T), 0, s, ev0, ev1, 0, a, pc)
 #define ODP_SWEEP(PP)                                                                        \
   if (p == PP) {                                                                             \
     constexpr int T = Frame<PP>::T;                                                          \
-    if (bl && st) ODP_SWEEP_GO((k_sweep<PP, true, true>), T);                                \
-    else if (bl) ODP_SWEEP_GO((k_sweep<PP, true, false>), T);                                \
-    else if (st) ODP_SWEEP_GO((k_sweep<PP, false, true>), T);                                \
-    else ODP_SWEEP_GO((k_sweep<PP, false, false>), T);                                       \
+    if (bl && st) ODP_SWEEP_GO((k_sweep<PP, true, 1>), T);                                   \
+    else if (bl) ODP_SWEEP_GO((k_sweep<PP, true, 0>), T);                                    \
+    else if (st == 2) ODP_SWEEP_GO((k_sweep<PP, false, 2>), T);                              \
+    else if (st) ODP_SWEEP_GO((k_sweep<PP, false, 1>), T);                                   \
+    else ODP_SWEEP_GO((k_sweep<PP, false, 0>), T);                                           \
     return hipGetLastError();                                                                \
   }
   ODP_SWEEP(32)
   ODP_SWEEP(64)
   if (p == 128) {
     constexpr int T = Half128::T;
-    if (bl && st) ODP_SWEEP_GO((k_sweep128<true, true>), T);
-    else if (bl) ODP_SWEEP_GO((k_sweep128<true, false>), T);
-    else if (st) ODP_SWEEP_GO((k_sweep128<false, true>), T);
-    else ODP_SWEEP_GO((k_sweep128<false, false>), T);
+    if (bl && st) ODP_SWEEP_GO((k_sweep128<true, 1>), T);
+    else if (bl) ODP_SWEEP_GO((k_sweep128<true, 0>), T);
+    else if (st == 2) ODP_SWEEP_GO((k_sweep128<false, 2>), T);
+    else if (st) ODP_SWEEP_GO((k_sweep128<false, 1>), T);
+    else ODP_SWEEP_GO((k_sweep128<false, 0>), T);
     return hipGetLastError();
   }
 #undef ODP_SWEEP
@@ -491,12 +485,11 @@ __global__ __launch_bounds__(256) void k_stats_reduce(const double* frame_part, 
       for (int q = 0; q < NPS; ++q) v[q] += tile_part[NPS * (size_t)e + q];
     }
   } else {
-    for (int k = threadIdx.x; k < J; k += 256) {
-      v[0] += frame_part[2 * k];
-      v[1] += frame_part[2 * k + 1];
-    }
+    for (int k = threadIdx.x; k < J; k += 256)
+#pragma unroll
+      for (int q = 0; q < NFS; ++q) v[q] += frame_part[NFS * (size_t)k + q];
   }
-  const int nq = b < D ? NPS : 2;
+  const int nq = b < D ? NPS : NFS;
   for (int q = 0; q < nq; ++q) {
     const double t = block_sum<256>(v[q], sh);
     if (threadIdx.x == 0) scratch[NPS * (size_t)b + q] = t;
@@ -525,22 +518,29 @@ hipError_t launch_stats(const double* frame_part, int J, const double* tile_part
   return hipGetLastError();
 }
 
-// per problem (one thread each), its subdomains in ascending order
-__global__ void k_residual_sums(const double* scratch, const int32_t* prob, int n, double* out) {
+// per problem (one thread each), its subdomains in ascending order; thread n copies the
+// plan's frame sums
+__global__ void k_residual_sums(const double* scratch, const int32_t* prob, int n, int D, double* out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int D0 = prob[4 * i + 2], D = prob[4 * i + 3];
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int d = D0; d < D0 + D; ++d)
-    for (int k = 0; k < 4; ++k) v[k] += scratch[NPS * (size_t)d + 2 + k];
-  for (int k = 0; k < 4; ++k) out[4 * (size_t)i + k] = v[k];
+  if (i > n) return;
+  if (i == n) {
+    out[6 * (size_t)n] = scratch[NPS * (size_t)D + 2];
+    out[6 * (size_t)n + 1] = scratch[NPS * (size_t)D + 3];
+    return;
+  }
+  const int D0 = prob[4 * i + 2], Dp = prob[4 * i + 3];
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int d = D0; d < D0 + Dp; ++d)
+    for (int k = 0; k < 6; ++k) v[k] += scratch[NPS * (size_t)d + 2 + k];
+  for (int k = 0; k < 6; ++k) out[6 * (size_t)i + k] = v[k];
 }
 
-hipError_t launch_residual_sums(const double* tile_part, const int32_t* re_list, const int32_t* re_first, int D,
-                                const int32_t* prob, int n, double* scratch, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_stats_reduce, dim3(D), dim3(256), 0, s, (const double*)nullptr, 0, tile_part, re_list,
-                     re_first, D, scratch);
-  hipLaunchKernelGGL(k_residual_sums, dim3((n + 63) / 64), dim3(64), 0, s, scratch, prob, n, out);
+hipError_t launch_residual_sums(const double* frame_part, int J, const double* tile_part, const int32_t* re_list,
+                                const int32_t* re_first, int D, const int32_t* prob, int n, double* scratch,
+                                double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats_reduce, dim3(D + 1), dim3(256), 0, s, frame_part, J, tile_part, re_list, re_first, D,
+                     scratch);
+  hipLaunchKernelGGL(k_residual_sums, dim3((n + 64) / 64), dim3(64), 0, s, scratch, prob, n, D, out);
   return hipGetLastError();
 }
 
@@ -565,8 +565,8 @@ __global__ __launch_bounds__(256) void k_stop_check(StopArgs a) {
   const int J0 = a.prob[4 * i], J = a.prob[4 * i + 1], D0 = a.prob[4 * i + 2], D = a.prob[4 * i + 3];
   double s0 = 0.0, s1 = 0.0;
   for (int k = threadIdx.x; k < J; k += 256) {
-    s0 += a.frame_part[2 * (size_t)(J0 + k)];
-    s1 += a.frame_part[2 * (size_t)(J0 + k) + 1];
+    s0 += a.frame_part[NFS * (size_t)(J0 + k)];
+    s1 += a.frame_part[NFS * (size_t)(J0 + k) + 1];
   }
   s0 = block_sum<256>(s0, sh);
   s1 = block_sum<256>(s1, sh);

@@ -11,7 +11,8 @@ constexpr int MAXS = 8;                        // most subdomains over one pixel
 constexpr int MAXP = MAXS * (MAXS - 1) / 2;    // most pairs over one pixel
 constexpr int NPX = 2;                          // pixels per thread in the pixel-tile kernels
 constexpr int PULL_B = 4;                       // pull records per group (lists padded to a multiple)
-constexpr int NPS = 6;                          // pixel-update statistics per (tile, copy slot)
+constexpr int NPS = 8;                          // pixel-update statistics per (tile, copy slot)
+constexpr int NFS = 4;                          // frame-sweep statistics per frame
 constexpr int NXCD = 8;                        // MI355X accelerator complex dies
 
 // A cell is a rectangle of image pixels covered by the same set of subdomains
@@ -80,10 +81,12 @@ struct SweepArgs {
   int32_t J, chunk;          // frames, frames per XCD slice
   int32_t xcd_slice;         // 1: workgroup b takes slice b % 8 of the order; 0: order[b]
   float eps, eta;
-  double* part;              // [J][2] stats partials (L1 misfit, G_eps) or null
+  double* part;              // [J][NFS] statistics (L1 misfit, G_eps, |Gamma^{n+1} - Gamma^n|^2,
+                             //   |Gamma^{n+1}|^2) or null
   float2* psi;               // [J][p][p] per-frame output, natural spatial layout:
                              //   non-blind conj(w) o F^{-1}(z - Gamma), blind F^{-1}(z - Gamma)
   int blind;
+  int frame_res;             // 1: the statistics also sum the frame residuals (penalty rule)
   const StopStatus* stop;    // [n_problems] or null: frames of stopped problems are skipped
 };
 
@@ -122,6 +125,7 @@ struct PixelArgs {
   const float2* w_sub;       // blind: probe copies (the illumination is formed in the pull)
   float eta, gamma;          // (r is per cell)
   double* part;              // [n_tiles][MAXS][NPS] statistics (pixel_stats) or null
+  const double* dend;        // [p_sub] den (non-blind; the statistics weight |u|^2 by it)
   const StopStatus* stop;    // [n_problems] or null: tiles of stopped problems are skipped
 };
 
@@ -189,7 +193,7 @@ hipError_t launch_probe_update(const ProbeArgs& a, hipStream_t s);
 // once stopped) RF_i from its frames' partials and its sum of sqrt f, RE_i as the max
 // over its subdomains of sqrt(|du|^2 / |u|^2), G_i; then iters_i += 1 and the rule.
 struct StopArgs {
-  const double* frame_part;  // [J][2] (L1 misfit, G_eps) of the sweep
+  const double* frame_part;  // [J][NFS] of the sweep
   const double* sub_sums;    // [D][2] (|du|^2, |u|^2) per subdomain (k_stats_reduce)
   const int32_t* prob;       // [n][4] = (J0, J, D0, D)
   const double* sum_sf;      // problem i's sum of sqrt f at sum_sf[i * sum_sf_stride]
@@ -202,11 +206,13 @@ struct StopArgs {
 hipError_t launch_stop_check(const StopArgs& a, const double* tile_part, const int32_t* re_list,
                              const int32_t* re_first, int D, double* scratch, hipStream_t s);
 
-// Consensus residual sums of each problem for the penalty rule (per-subdomain sums from
-// the statistics reduction in scratch): out[4 i + k] = sum over its subdomains of
-// (|Lam^{n+1} - Lam^n|^2, (m-1)|du|^2, (m-1)|u^{n+1}|^2, |Lam^{n+1}|^2).
-hipError_t launch_residual_sums(const double* tile_part, const int32_t* re_list, const int32_t* re_first, int D,
-                                const int32_t* prob, int n, double* scratch, double* out, hipStream_t s);
+// Residual sums for the penalty rule (per-subdomain sums from the statistics reduction in
+// scratch): out[6 i + k] = sum over problem i's subdomains of (|Lam^{n+1} - Lam^n|^2,
+// (m-1)|du|^2, (m-1)|u^{n+1}|^2, |Lam^{n+1}|^2, den |u^n|^2, den |du|^2); then
+// out[6 n], out[6 n + 1] = the plan's |Gamma^{n+1} - Gamma^n|^2 and |Gamma^{n+1}|^2.
+hipError_t launch_residual_sums(const double* frame_part, int J, const double* tile_part, const int32_t* re_list,
+                                const int32_t* re_first, int D, const int32_t* prob, int n, double* scratch,
+                                double* out, hipStream_t s);
 hipError_t launch_scale(float2* x, int64_t n, float f, hipStream_t s);
 
 struct InitProbeArgs {       // w0 = (1/J) sum_j F^{-1}(sqrt f_j) of one problem

@@ -118,8 +118,8 @@ __device__ __forceinline__ float2 pixel_value(const PixelArgs& a, int m, float r
 
 // per copy group, NPS sums over the thread's pixels (the per-copy |du|^2 and |u|^2, then
 // the consensus residual terms over the copy's ordered pairs: |Lam^{n+1} - Lam^n|^2,
-// (m-1)|du|^2, (m-1)|u^{n+1}|^2, |Lam^{n+1}|^2), reduced in a fixed order into
-// part[tile][s][NPS]
+// (m-1)|du|^2, (m-1)|u^{n+1}|^2, |Lam^{n+1}|^2, then the frame constraint's terms
+// den |u^n|^2 and den |du|^2), reduced in a fixed order into part[tile][s][NPS]
 __device__ __forceinline__ void pixel_stats(const PixelArgs& a, int tile, int m, int tpg, double (&v)[NPS],
                                             double (*red)[8]) {
   const int g = min(tpg, 64);                    // lanes of one group inside a wavefront
@@ -142,10 +142,10 @@ __device__ __forceinline__ void pixel_stats(const PixelArgs& a, int tile, int m,
   }
 }
 
-// consensus residual terms of one pixel of copy s (the last four of pixel_stats)
+// residual terms of one pixel of copy s (pixel_stats' order; dd = its den)
 template <int NO>
 __device__ __forceinline__ void residual_terms(int m, float2 un, float2 uo, const float2* lo, const float2 (&dv)[NO],
-                                               double (&v)[NPS]) {
+                                               double dd, double (&v)[NPS]) {
 #pragma unroll
   for (int o = 0; o < NO; ++o)
     if (o < m - 1) {
@@ -159,6 +159,8 @@ __device__ __forceinline__ void residual_terms(int m, float2 un, float2 uo, cons
   v[1] += (double)un.x * un.x + (double)un.y * un.y;
   v[3] += (double)(m - 1) * (ex * ex + ey * ey);
   v[4] += (double)(m - 1) * ((double)un.x * un.x + (double)un.y * un.y);
+  v[6] += dd * ((double)uo.x * uo.x + (double)uo.y * uo.y);
+  v[7] += dd * (ex * ex + ey * ey);
 }
 
 // Tiles of cells with at most four copies: each wavefront lies inside one copy group
@@ -236,7 +238,7 @@ __global__ __launch_bounds__(256, BLIND ? 1 : 6) void k_pixel_uni(PixelArgs a) {
       lt[o] = lt_[o][h];
     }
     un[h] = pixel_value<BLIND, NO>(a, m, w.r, num[h], den[h], uo[h], rc[h], ut, lo, lt, dv[h]);
-    if (STATS && act[h]) residual_terms<NO>(m, un[h], uo[h], lo, dv[h], sv);
+    if (STATS && act[h]) residual_terms<NO>(m, un[h], uo[h], lo, dv[h], BLIND ? den[h] : a.dend[idx[h]], sv);
   }
   __syncthreads();  // every copy's reads of u^n and Lam^n precede the writes below
 #pragma unroll
@@ -319,7 +321,7 @@ __global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
       }
     }
     un[h] = pixel_value<BLIND, NO>(a, m, r, num[h], den[h], uo[h], rc[h], ut, lo, lt, dv[h]);
-    if (STATS && act[h]) residual_terms<NO>(m, un[h], uo[h], lo, dv[h], sv);
+    if (STATS && act[h]) residual_terms<NO>(m, un[h], uo[h], lo, dv[h], BLIND ? den[h] : a.dend[idx[h]], sv);
   }
   __syncthreads();  // every copy's reads of u^n and Lam^n precede the writes below
 #pragma unroll

@@ -96,7 +96,7 @@ struct odp_plan {
   double stop_tol = 0.0;
   bool stopping() const { return stop_measure != ODP_STOP_NONE || stop_max_iter > 0; }
   // overlap penalties by residual balancing (0 = off), host-driven every bal_period iterations
-  int32_t bal_period = 0, bal_until = 0;
+  int32_t bal_period = 0, bal_until = 0, bal_which = ODP_BALANCE_R;
   int64_t bal_count = 0;
   double bal_mu = 10.0, bal_tau = 2.0;
   bool balancing() const { return bal_period > 0; }
@@ -400,7 +400,7 @@ void layout(odp_plan* P) {
   P->ws.pull = take(sizeof(PullEntry) * n_pull);
   P->ws.den = take(sizeof(double) * P->p_sub);
   P->ws.rcp = take(sizeof(float) * P->p_sub);
-  P->ws.fpart = take(sizeof(double) * 2 * P->J);
+  P->ws.fpart = take(sizeof(double) * NFS * P->J);
   P->ws.tpart = take(sizeof(double) * NPS * MAXS * n_tiles);
   P->ws.stat_scratch = take(sizeof(double) * NPS * (P->D + 1));
   P->ws.misc = take(sizeof(double) * (2 + 2 * 1024 + 8));
@@ -761,6 +761,7 @@ int odp_plan_get_info(const odp_plan* P, odp_plan_info* o) {
 }
 
 size_t odp_plan_workspace_bytes(const odp_plan* P) { return P ? P->ws.bytes : 0; }
+double odp_plan_get_eta(const odp_plan* P) { return P ? P->eta : 0.0; }
 size_t odp_state_bytes(const odp_plan* P) { return P ? P->st.bytes : 0; }
 
 int odp_state_get_layout(const odp_plan* P, odp_state_layout* o) {
@@ -956,6 +957,7 @@ static SweepArgs sweep_args(const odp_plan* P, char* b, double* stats) {
   a.psi = P->W_<float2>(P->ws.psi);
   a.blind = P->blind;
   a.stop = P->stopping() ? reinterpret_cast<const StopStatus*>(b + P->st.stop) : nullptr;
+  a.frame_res = P->balancing() && (P->bal_which & ODP_BALANCE_ETA) ? 1 : 0;
   return a;
 }
 
@@ -978,38 +980,45 @@ static PixelArgs pixel_args(const odp_plan* P, char* b, double* stats) {
   a.eta = (float)P->eta;
   a.gamma = (float)P->gamma;
   a.part = stats || P->stopping() || P->balancing() ? P->W_<double>(P->ws.tpart) : nullptr;
+  a.dend = P->W_<double>(P->ws.den);
   a.stop = P->stopping() ? reinterpret_cast<const StopStatus*>(b + P->st.stop) : nullptr;
   return a;
 }
 
-// Residual balancing of the overlap penalties (He, Yang and Wang 2000; Boyd et al. 2011,
-// Sec. 3.4.1) after the iteration just issued: per problem, the normalised primal
-// consensus residual rp = ||pi u - v|| / ||pi u|| against the dual rd = ||pi du|| / ||Lam||;
-// r <- tau r when rp > mu rd, r <- r / tau when rd > mu rp, and the problem's scaled
-// multipliers Lam <- Lam r_old / r_new.  Reads the sums to the host (synchronises).
+// Residual balancing of the penalties (He, Yang and Wang 2000; Boyd et al. 2011, Sec.
+// 3.4.1) after the iteration just issued.  Overlap penalty r, per problem: the normalised
+// primal consensus residual rp = ||pi u - v|| / ||pi u|| against the dual rd = ||pi du|| /
+// ||Lam||.  Data penalty eta, for the whole plan: rp = ||Gamma^{n+1} - Gamma^n|| / ||A u^n||
+// against rd = ||A du|| / ||Gamma^{n+1}|| (||A x||^2 = sum den |x|^2).  A penalty q becomes
+// tau q when rp > mu rd and q / tau when rd > mu rp; its scaled multipliers (Lam or Gamma)
+// are multiplied by q_old / q_new.  Reads the sums to the host (synchronises).
 static int balance_penalties(odp_plan* P, char* b, hipStream_t s) {
   const int n = P->n_probes();
+  const bool do_r = (P->bal_which & ODP_BALANCE_R) != 0, do_eta = (P->bal_which & ODP_BALANCE_ETA) != 0;
   bool any_pairs = false;
   for (const odp_plan::Entry& e : P->batch) any_pairs = any_pairs || e.D >= 2;
-  if (!any_pairs) return ODP_OK;   // nothing to balance: no read, no synchronisation
+  if (!do_eta && !any_pairs) return ODP_OK;   // nothing to balance: no read, no synchronisation
   double* dev = P->W_<double>(P->ws.resid);
-  ODP_HIP(launch_residual_sums(P->W_<double>(P->ws.tpart), P->W_<int32_t>(P->ws.re_list),
-                               P->W_<int32_t>(P->ws.re_first), P->D, P->W_<int32_t>(P->ws.prob), n,
-                               P->W_<double>(P->ws.stat_scratch), dev, s));
-  std::vector<double> h((size_t)4 * n);
+  ODP_HIP(launch_residual_sums(P->W_<double>(P->ws.fpart), P->J, P->W_<double>(P->ws.tpart),
+                               P->W_<int32_t>(P->ws.re_list), P->W_<int32_t>(P->ws.re_first), P->D,
+                               P->W_<int32_t>(P->ws.prob), n, P->W_<double>(P->ws.stat_scratch), dev, s));
+  std::vector<double> h((size_t)6 * n + 2);
   ODP_HIP(hipMemcpyAsync(h.data(), dev, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
   ODP_HIP(hipStreamSynchronize(s));
+  auto factor = [&](double Pr, double S, double U, double L) {
+    if (!(U > 0.0 && L > 0.0)) return 1.0;
+    const double rp = std::sqrt(Pr / U), rd = std::sqrt(S / L);
+    if (rp > P->bal_mu * rd) return P->bal_tau;
+    if (rd > P->bal_mu * rp) return 1.0 / P->bal_tau;
+    return 1.0;
+  };
   std::vector<double> r(n);
   bool changed = false;
   for (int i = 0; i < n; ++i) {
     const odp_plan::Entry& e = P->batch[i];
     r[i] = e.r;
-    const double Pr = h[4 * i], S = h[4 * i + 1], U = h[4 * i + 2], L = h[4 * i + 3];
-    if (e.D < 2 || !(U > 0.0 && L > 0.0)) continue;
-    const double rp = std::sqrt(Pr / U), rd = std::sqrt(S / L);
-    double fac = 1.0;
-    if (rp > P->bal_mu * rd) fac = P->bal_tau;
-    else if (rd > P->bal_mu * rp) fac = 1.0 / P->bal_tau;
+    if (!do_r || e.D < 2) continue;
+    const double fac = factor(h[6 * i], h[6 * i + 1], h[6 * i + 2], h[6 * i + 3]);
     if (fac == 1.0) continue;
     r[i] = e.r * fac;
     changed = true;
@@ -1024,8 +1033,22 @@ static int balance_penalties(odp_plan* P, char* b, hipStream_t s) {
     if (l0 >= 0)
       ODP_HIP(launch_scale(reinterpret_cast<float2*>(b + P->st.lam) + l0, l1 - l0, (float)(1.0 / fac), s));
   }
+  if (do_eta) {
+    double U = 0.0, S = 0.0;
+    for (int i = 0; i < n; ++i) {
+      U += h[6 * i + 4];
+      S += h[6 * i + 5];
+    }
+    const double fac = factor(h[6 * n], S, U, h[6 * n + 1]);
+    if (fac != 1.0) {
+      P->eta *= fac;
+      ODP_HIP(launch_scale(reinterpret_cast<float2*>(b + P->st.gamma), (int64_t)P->J * P->p * P->p,
+                           (float)(1.0 / fac), s));
+      changed = true;
+    }
+  }
   if (!changed) return ODP_OK;
-  return set_penalties(P, r.data(), s);
+  return set_penalties(P, r.data(), s);   // the reciprocals follow eta and r
 }
 
 static int finish_stats(const odp_plan* P, double* stats, hipStream_t s) {
@@ -1149,11 +1172,16 @@ int odp_pixel_update(odp_plan* P, void* dev_state, double* dev_stats, hipStream_
   return ODP_OK;
 }
 
-int odp_plan_set_balancing(odp_plan* P, double mu, double tau, int32_t period, int32_t until) {
+int odp_plan_set_balancing(odp_plan* P, double mu, double tau, int32_t period, int32_t until, int32_t which) {
   if (!P) return fail(ODP_EINVAL, "null argument");
   if (period < 0 || until < 0) return fail(ODP_EINVAL, "negative period or limit");
   if (period > 0 && !(mu >= 1.0 && tau > 1.0 && std::isfinite(tau)))
     return fail(ODP_EINVAL, "need mu >= 1 and a finite tau > 1");
+  if (period > 0 && (which < 1 || which > (ODP_BALANCE_R | ODP_BALANCE_ETA)))
+    return fail(ODP_EINVAL, "which must select r, eta or both");
+  if (period > 0 && (which & ODP_BALANCE_ETA) && P->blind)
+    return fail(ODP_EUNSUPPORTED, "eta balancing is for known-probe plans");
+  P->bal_which = which;
   P->bal_period = period;
   P->bal_until = until;
   P->bal_mu = mu;

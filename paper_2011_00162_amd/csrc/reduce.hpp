@@ -25,4 +25,33 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
+// One frequency's terms of the frame constraint's residuals (penalty balancing):
+// |Gamma^{n+1} - Gamma^n|^2 and |Gamma^{n+1}|^2, each formed in FP32 (they only steer a
+// factor-of-tau decision) and added to FP64 sums.
+__device__ __forceinline__ void frame_terms(float2 g_old, float2 g_new, double& del, double& nrm) {
+  const float dx = g_new.x - g_old.x, dy = g_new.y - g_old.y;
+  del += (double)(dx * dx + dy * dy);
+  nrm += (double)(g_new.x * g_new.x + g_new.y * g_new.y);
+}
+
+// A frame's statistics, summed over the workgroup in a fixed order: out[0..3] = (L1
+// misfit, G_eps, |Gamma^{n+1} - Gamma^n|^2, |Gamma^{n+1}|^2); the last two are 0 unless
+// FRES (the frame residuals are formed only where a penalty rule reads them).
+template <int NT, bool FRES>
+__device__ __forceinline__ void frame_stats(double* out, double mis, double gsum, double del, double nrm,
+                                            double* sh) {
+  mis = block_sum<NT>(mis, sh);
+  gsum = block_sum<NT>(gsum, sh);
+  if (FRES) {
+    del = block_sum<NT>(del, sh);
+    nrm = block_sum<NT>(nrm, sh);
+  }
+  if (threadIdx.x == 0) {
+    out[0] = mis;
+    out[1] = gsum;
+    out[2] = FRES ? del : 0.0;
+    out[3] = FRES ? nrm : 0.0;
+  }
+}
+
 }  // namespace odp

@@ -121,3 +121,51 @@ def test_balancing_off_and_until():
     plan.iterate(c, 12)
     assert math.isclose(plan.penalties()[0], rh[-1], rel_tol=1e-12)
     assert rh[2] != P["r"] and rh[3:] == [rh[2]] * 9
+
+
+def _balanced_both(P, K, mu, which):
+    w, _, f = rounded_inputs(P)
+    tr, tre, eh = [], [], []
+    st, _, rh = balance.od2pm_run_balanced(P["geom"], w, f, P["eps"], P["eta"], P["r"], K, mu=mu, period=PERIOD,
+                                           trace=tr, trace_eta=tre, eta_hist=eh,
+                                           balance_r=bool(which & odp.ODP_BALANCE_R),
+                                           balance_eta=bool(which & odp.ODP_BALANCE_ETA))
+    return st, rh, eh, tr + tre
+
+
+@pytest.mark.parametrize("which", [2, 3], ids=["eta", "r_and_eta"])
+def test_data_penalty_follows_the_oracle(which):
+    # noise-free data: on Poisson data the iteration amplifies the FP32 rounding beyond the
+    # 1e-4 compared here within these 24 iterations, with or without balancing
+    spec = tiny_spec(n=160, p=32, step=8, jitter=2, dy=1, dx=4, radius=12, peak=None)
+    say("balance eta, which", which)
+    P = oracle_problem(spec)
+    K = 24
+    for mu in (10.0, 8.0, 6.0, 5.0, 4.0, 3.0, 2.0):
+        ost, rh, eh, tr = _balanced_both(P, K, mu, which)
+        if _clear(tr, mu) and len(set(eh)) > 1:
+            break
+    else:
+        pytest.fail("no mu with margin")
+    plan = gpu_plan(P)
+    plan.set_balancing(mu, 2.0, PERIOD, 0, which)
+    st = plan.new_state()
+    got_r, got_eta = [], []
+    for _ in range(K // PERIOD):
+        plan.iterate(st, PERIOD)
+        got_r.append(plan.penalties()[0])
+        got_eta.append(plan.eta())
+    say("balance eta/eta0", [e / P["eta"] for e in got_eta], "r/r0", [r / P["r"] for r in got_r], "mu", mu)
+    assert all(math.isclose(g, x, rel_tol=1e-12) for g, x in zip(got_eta, eh[PERIOD - 1::PERIOD])), (got_eta, eh)
+    assert all(math.isclose(g, x, rel_tol=1e-12) for g, x in zip(got_r, rh[PERIOD - 1::PERIOD])), (got_r, rh)
+    assert rel_list([host(t) for t in st.u_sub()], ost.u) <= 1e-4
+
+
+def test_data_penalty_refused_for_blind_plans():
+    spec = tiny_spec(n=128, p=32, step=8, jitter=1, dy=2, dx=2, radius=12, peak=1e4)
+    P = oracle_problem(spec)
+    mu = 0.5 * P["eta"] * max(len(fr) for fr in P["geom"].frames_of)
+    plan = gpu_plan(P, blind=True, mu=mu)
+    with pytest.raises(odp.OdpError):
+        plan.set_balancing(10.0, 2.0, 4, 0, odp.ODP_BALANCE_ETA)
+    plan.set_balancing(10.0, 2.0, 4, 0, odp.ODP_BALANCE_R)   # r stays available

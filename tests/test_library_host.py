@@ -204,16 +204,20 @@ def test_stopping_arguments_are_checked():
 def test_balancing_arguments_are_checked():
     plan = odp.Plan(**_plan_args())
     L = odp.lib()
-    assert L.odp_plan_set_balancing(None, 10.0, 2.0, 10, 0) == ODP_EINVAL
-    assert L.odp_plan_set_balancing(plan._h, 10.0, 2.0, -1, 0) == ODP_EINVAL      # negative period
-    assert L.odp_plan_set_balancing(plan._h, 10.0, 2.0, 10, -1) == ODP_EINVAL     # negative limit
-    assert L.odp_plan_set_balancing(plan._h, 0.5, 2.0, 10, 0) == ODP_EINVAL       # mu < 1
-    assert L.odp_plan_set_balancing(plan._h, 10.0, 1.0, 10, 0) == ODP_EINVAL      # tau <= 1
-    assert L.odp_plan_set_balancing(plan._h, 10.0, float("inf"), 10, 0) == ODP_EINVAL
-    assert L.odp_plan_set_balancing(plan._h, float("nan"), 2.0, 10, 0) == ODP_EINVAL
-    assert L.odp_plan_set_balancing(plan._h, 10.0, 2.0, 10, 500) == 0
-    assert L.odp_plan_set_balancing(plan._h, float("inf"), 2.0, 1, 0) == 0         # never triggers
-    assert L.odp_plan_set_balancing(plan._h, 0.0, 0.0, 0, 0) == 0                  # off: values unchecked
+    assert L.odp_plan_set_balancing(None, 10.0, 2.0, 10, 0, 1) == ODP_EINVAL
+    assert L.odp_plan_set_balancing(plan._h, 10.0, 2.0, -1, 0, 1) == ODP_EINVAL      # negative period
+    assert L.odp_plan_set_balancing(plan._h, 10.0, 2.0, 10, -1, 1) == ODP_EINVAL     # negative limit
+    assert L.odp_plan_set_balancing(plan._h, 0.5, 2.0, 10, 0, 1) == ODP_EINVAL       # mu < 1
+    assert L.odp_plan_set_balancing(plan._h, 10.0, 1.0, 10, 0, 1) == ODP_EINVAL      # tau <= 1
+    assert L.odp_plan_set_balancing(plan._h, 10.0, float("inf"), 10, 0, 1) == ODP_EINVAL
+    assert L.odp_plan_set_balancing(plan._h, float("nan"), 2.0, 10, 0, 1) == ODP_EINVAL
+    assert L.odp_plan_set_balancing(plan._h, 10.0, 2.0, 10, 500, 1) == 0
+    assert L.odp_plan_set_balancing(plan._h, float("inf"), 2.0, 1, 0, 1) == 0      # never triggers
+    assert L.odp_plan_set_balancing(plan._h, 0.0, 0.0, 0, 0, 1) == 0                  # off: values unchecked
+    assert L.odp_plan_set_balancing(plan._h, 10.0, 2.0, 10, 0, 0) == ODP_EINVAL       # nothing selected
+    assert L.odp_plan_set_balancing(plan._h, 10.0, 2.0, 10, 0, 4) == ODP_EINVAL
+    assert L.odp_plan_set_balancing(plan._h, 10.0, 2.0, 10, 0, 3) == 0                # r and eta
+    assert L.odp_plan_get_eta(plan._h) == plan.params["eta"] and L.odp_plan_get_eta(None) == 0.0
 
 
 def test_size_helpers_match_plan_info():
