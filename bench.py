@@ -342,8 +342,9 @@ def run_table1(args, torch, odp, synthetic):
     iterated until RF <= 1e-5 by the device-side stopping rule, with a cap of 5000
     iterations instead of the paper's 1000 (RF at iteration 1000 is reported too).  Two
     penalty choices per D: the fixed scale-free r, in graphs of 50 iterations (a stopped
-    problem's kernels return at once), and r by residual balancing (mu 10, tau 2, every 10
-    iterations; eager, since the rule reads residuals on the host).  Reports the
+    problem's kernels return at once), r by residual balancing, and r and eta by residual
+    balancing (mu 10, tau 2, every 10 iterations; eager, since the rule reads residuals on
+    the host).  Reports the
     iterations to the rule, the time to reach it (a second, uninterrupted run of that many
     iterations, same penalties) and the SNR of the merged image over the illuminated
     pixels."""
@@ -358,15 +359,16 @@ def run_table1(args, torch, odp, synthetic):
         sqrt_f = torch.from_numpy(np.sqrt(f)).float().cuda()
         w = torch.from_numpy(pr["w"].astype("complex64")).cuda()
         row = {"D": D, "paper_iters": PAPER_TABLE1_ITERS[D]}
-        for mode in ("fixed_r", "balanced_r"):
-            bal = mode == "balanced_r"
+        for mode, which in (("fixed_r", 0), ("balanced_r", odp.ODP_BALANCE_R),
+                            ("balanced_r_eta", odp.ODP_BALANCE_R | odp.ODP_BALANCE_ETA)):
+            bal = which != 0
             plan = odp.Plan(spec.n, spec.n, spec.p, pr["offsets"], pr["frame_sub"], eps=0.5, eta=eta, r=1.0)
             plan.bind(sqrt_f, w)
             r0 = 0.5 * eta * plan.illum_max()
             plan.set_params(r=r0)
             plan.set_stopping(odp.ODP_STOP_RF, tol, cap)
             if bal:
-                plan.set_balancing(10.0, 2.0, 10, 0)
+                plan.set_balancing(10.0, 2.0, 10, 0, which)
             st = plan.new_state()
             graph = None if bal else odp.Graph([plan], [st], chunk)
             status = plan.stop_status(st)[0]
@@ -381,21 +383,21 @@ def run_table1(args, torch, odp, synthetic):
                     rf_paper_cap = status["rf"]
             del graph
             n_it = status["iters"]
-            r_end = plan.penalties()[0]
+            r_end, eta_end = plan.penalties()[0], plan.eta()
             snr = _snr_illuminated(plan.merge(st).cpu().numpy().astype(np.complex128), pr["u_true"],
                                    pr["offsets"], pr["w"])
             # time to the rule: the same iterations again, uninterrupted (with balancing, its
             # checks and host reads included)
             plan.set_stopping(odp.ODP_STOP_NONE, 0.0, 0)
-            plan.set_params(r=r0)
+            plan.set_params(r=r0, eta=eta)
             if bal:
-                plan.set_balancing(10.0, 2.0, 10, 0)
+                plan.set_balancing(10.0, 2.0, 10, 0, which)
             st2 = plan.new_state()
             ms = _timed(torch, lambda: plan.iterate(st2, n_it), 1)
             row[mode] = {"iters_to_rule": n_it, "met": status["rf"] <= tol, "rf": status["rf"], "re": status["re"],
                          "rf_at_1000": rf_paper_cap, "ms_to_rule": ms, "ms_per_iter": ms / n_it,
-                         "r_over_r0": r_end / r0, "snr_db": snr}
-            print(f"[table1] D={D} {mode} iterations={n_it} RF={status['rf']:.3e} r/r0={r_end / r0:.4g} "
+                         "r_over_r0": r_end / r0, "eta_end": eta_end, "snr_db": snr}
+            print(f"[table1] D={D} {mode} iterations={n_it} RF={status['rf']:.3e} r/r0={r_end / r0:.4g} eta={eta_end:.4g} "
                   f"SNR={snr:.1f} dB {ms:.2f} ms", file=sys.stderr, flush=True)
             del plan, st, st2
         rows.append(row)
