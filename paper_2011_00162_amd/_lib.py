@@ -113,7 +113,7 @@ def lib() -> C.CDLL:
         "odp_batch_set_penalties": (C.c_int, [vp, vp, vp]),
         "odp_plan_get_tuning": (C.c_int, [vp, C.POINTER(Tuning)]),
         "odp_plan_set_tuning": (C.c_int, [vp, i32, i32, i32, vp]),
-        "odp_plan_set_stopping": (C.c_int, [vp, i32, C.c_double, i32]),
+        "odp_plan_set_stopping": (C.c_int, [vp, i32, C.c_double, i32, i32]),
         "odp_plan_set_balancing": (C.c_int, [vp, C.c_double, C.c_double, i32, i32, i32]),
         "odp_plan_get_eta": (C.c_double, [vp]),
         "odp_plan_workspace_bytes": (C.c_size_t, [vp]),

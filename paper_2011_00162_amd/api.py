@@ -193,10 +193,12 @@ class Plan:
     def set_tuning(self, transform: int, xcd_slice: int, tiling: int, stream=None) -> None:
         check(lib().odp_plan_set_tuning(self._h, int(transform), int(xcd_slice), int(tiling), _stream(stream)))
 
-    def set_stopping(self, measure: int = ODP_STOP_NONE, tol: float = 0.0, max_iter: int = 0) -> None:
+    def set_stopping(self, measure: int = ODP_STOP_NONE, tol: float = 0.0, max_iter: int = 0,
+                     every: int = 1) -> None:
         """Device-side stopping rule of Sec. 4 (ODP_STOP_RF / ODP_STOP_RE, tolerance,
-        iteration cap); applies to later iterations and graphs created afterwards."""
-        check(lib().odp_plan_set_stopping(self._h, int(measure), float(tol), int(max_iter)))
+        iteration cap), checked after every `every`-th iteration; applies to later
+        iterations and graphs created afterwards."""
+        check(lib().odp_plan_set_stopping(self._h, int(measure), float(tol), int(max_iter), int(every)))
 
     def set_balancing(self, mu: float = 10.0, tau: float = 2.0, period: int = 0, until: int = 0,
                       which: int = ODP_BALANCE_R) -> None:

@@ -577,7 +577,7 @@ __global__ __launch_bounds__(256) void k_stop_check(StopArgs a) {
     re = fmax(re, den > 0.0 ? sqrt(num / den) : 0.0);
   }
   const double rf = s0 / a.sum_sf[(size_t)i * a.sum_sf_stride];
-  const int it = st->iters + 1;
+  const int it = st->iters + a.n_add;
   const double m = a.measure == 1 ? rf : re;
   const bool met = a.measure != 0 && m <= a.tol;   // false for NaN
   st->iters = it;

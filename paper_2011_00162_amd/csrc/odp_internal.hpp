@@ -200,6 +200,7 @@ struct StopArgs {
   int32_t sum_sf_stride, n;
   int32_t measure;           // 0 none, 1 RF, 2 RE
   int32_t max_iter;          // 0: no cap
+  int32_t n_add;             // iterations since the previous check
   double tol;
   StopStatus* status;        // [n]
 };

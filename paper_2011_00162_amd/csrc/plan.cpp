@@ -14,6 +14,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -92,9 +93,17 @@ struct odp_plan {
   int ts = 0;
   int32_t xcd_slice = 2;
   // stopping rule (Sec. 4) evaluated on the device after every iteration
-  int32_t stop_measure = ODP_STOP_NONE, stop_max_iter = 0;
+  int32_t stop_measure = ODP_STOP_NONE, stop_max_iter = 0, stop_every = 1;
   double stop_tol = 0.0;
   bool stopping() const { return stop_measure != ODP_STOP_NONE || stop_max_iter > 0; }
+  // iterations issued per state since the rule was set or the state initialised; the rule
+  // is evaluated on every stop_every-th
+  mutable std::unordered_map<const void*, int64_t> stop_count;
+  bool stop_check(const void* state) const {
+    if (!stopping()) return false;
+    const auto it = stop_count.find(state);
+    return ((it == stop_count.end() ? 0 : it->second) + 1) % stop_every == 0;
+  }
   // overlap penalties by residual balancing (0 = off), host-driven every bal_period iterations
   int32_t bal_period = 0, bal_until = 0, bal_which = ODP_BALANCE_R;
   int64_t bal_count = 0;
@@ -926,6 +935,7 @@ int odp_state_init(const odp_plan* P, void* dev_state, const odp_c32* dev_w0, hi
   ODP_HIP(launch_fill(reinterpret_cast<float2*>(b + P->st.lam), P->n_lam, make_float2(0.f, 0.f), s));
   ODP_HIP(launch_fill(reinterpret_cast<float2*>(b + P->st.stop),
                       (int64_t)(sizeof(StopStatus) / sizeof(float2)) * P->n_probes(), make_float2(0.f, 0.f), s));
+  P->stop_count.erase(dev_state);
   if (P->blind) {
     const float2* w0 = reinterpret_cast<const float2*>(dev_w0);
     ODP_HIP(launch_copy(reinterpret_cast<float2*>(b + P->st.w), w0, (int64_t)pp, s));
@@ -953,7 +963,7 @@ static SweepArgs sweep_args(const odp_plan* P, char* b, double* stats) {
   a.xcd_slice = P->xcd_slice;
   a.eps = (float)P->eps;
   a.eta = (float)P->eta;
-  a.part = stats || P->stopping() || P->balancing() ? P->W_<double>(P->ws.fpart) : nullptr;
+  a.part = stats || P->balancing() || P->stop_check(b) ? P->W_<double>(P->ws.fpart) : nullptr;
   a.psi = P->W_<float2>(P->ws.psi);
   a.blind = P->blind;
   a.stop = P->stopping() ? reinterpret_cast<const StopStatus*>(b + P->st.stop) : nullptr;
@@ -979,7 +989,7 @@ static PixelArgs pixel_args(const odp_plan* P, char* b, double* stats) {
   a.w_sub = P->blind ? reinterpret_cast<const float2*>(b + P->st.w_sub) : nullptr;
   a.eta = (float)P->eta;
   a.gamma = (float)P->gamma;
-  a.part = stats || P->stopping() || P->balancing() ? P->W_<double>(P->ws.tpart) : nullptr;
+  a.part = stats || P->balancing() || P->stop_check(b) ? P->W_<double>(P->ws.tpart) : nullptr;
   a.dend = P->W_<double>(P->ws.den);
   a.stop = P->stopping() ? reinterpret_cast<const StopStatus*>(b + P->st.stop) : nullptr;
   return a;
@@ -1154,8 +1164,9 @@ int odp_pixel_update(odp_plan* P, void* dev_state, double* dev_stats, hipStream_
     int rc = finish_stats(P, dev_stats, s);
     if (rc) return rc;
   }
-  if (P->stopping()) {
+  if (P->stop_check(b)) {
     StopArgs sa;
+    sa.n_add = P->stop_every;
     sa.frame_part = P->W_<double>(P->ws.fpart);
     sa.sub_sums = nullptr;
     sa.prob = P->W_<int32_t>(P->ws.prob);
@@ -1169,6 +1180,7 @@ int odp_pixel_update(odp_plan* P, void* dev_state, double* dev_stats, hipStream_
     ODP_HIP(launch_stop_check(sa, P->W_<double>(P->ws.tpart), P->W_<int32_t>(P->ws.re_list),
                               P->W_<int32_t>(P->ws.re_first), P->D, P->W_<double>(P->ws.stat_scratch), s));
   }
+  if (P->stopping()) ++P->stop_count[b];
   return ODP_OK;
 }
 
@@ -1190,14 +1202,17 @@ int odp_plan_set_balancing(odp_plan* P, double mu, double tau, int32_t period, i
   return ODP_OK;
 }
 
-int odp_plan_set_stopping(odp_plan* P, int32_t measure, double tol, int32_t max_iter) {
+int odp_plan_set_stopping(odp_plan* P, int32_t measure, double tol, int32_t max_iter, int32_t every) {
   if (!P) return fail(ODP_EINVAL, "null argument");
   if (measure < ODP_STOP_NONE || measure > ODP_STOP_RE) return fail(ODP_EINVAL, "unknown stopping measure");
   if (measure != ODP_STOP_NONE && !(tol >= 0.0)) return fail(ODP_EINVAL, "tolerance must be non-negative");
   if (max_iter < 0) return fail(ODP_EINVAL, "negative iteration cap");
+  if (every < 1) return fail(ODP_EINVAL, "the check interval must be at least 1");
   P->stop_measure = measure;
   P->stop_tol = measure != ODP_STOP_NONE ? tol : 0.0;
   P->stop_max_iter = max_iter;
+  P->stop_every = every;
+  P->stop_count.clear();
   return ODP_OK;
 }
 
@@ -1387,9 +1402,12 @@ int odp_graph_create(odp_plan* const* plans, void* const* states, int32_t n, int
   *out = nullptr;
   for (int i = 0; i < n; ++i)
     if (!plans[i] || !states[i] || !plans[i]->wsp) return fail(ODP_EINVAL, "unbound plan or null state");
-  for (int i = 0; i < n; ++i)
+  for (int i = 0; i < n; ++i) {
     if (plans[i]->balancing())
       return fail(ODP_EUNSUPPORTED, "penalty balancing reads residuals on the host: not in a graph");
+    if (plans[i]->stopping() && n_iter % plans[i]->stop_every != 0)
+      return fail(ODP_EINVAL, "n_iter must be a multiple of the stopping check interval");
+  }
   // One capture stream forks into one stream per distinct plan (pairs of one plan share
   // its workspace and stay on one branch, in the given order): distinct plans touch
   // disjoint memory, so the graph holds independent chains of n_iter iterations that the

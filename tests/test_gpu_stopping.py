@@ -226,3 +226,37 @@ def test_cap_with_five_to_eight_copies():
     plan = gpu_plan(P, r=r)
     assert plan.info.max_cover == 6
     _cap_freezes(plan)
+
+
+def test_check_interval_stops_at_the_next_check():
+    """every = 4: the rule is read after iterations 4, 8, ...; the problem stops at the
+    first of those whose measure meets the tolerance, and the counts stay exact."""
+    spec = tiny_spec(n=128, p=32, step=8, jitter=1, dy=1, dx=2, radius=12, peak=1e4)
+    say("stop every 4")
+    P = oracle_problem(spec)
+    K, every = 24, 4
+    _, hist = _oracle_run(P, K)
+    checked = [hist[n]["RE"] for n in range(every - 1, K, every)]
+    tol, (mc,) = _pick_tol([checked], first=1, after=1)
+    n_stop = (mc + 1) * every
+    plan = gpu_plan(P)
+    plan.set_stopping(odp.ODP_STOP_RE, tol, 0, every)
+    st = plan.new_state()
+    plan.iterate(st, K)
+    s = plan.stop_status(st)[0]
+    assert (s["iters"], s["stopped"]) == (n_stop, True), (s, n_stop)
+    assert abs(s["re"] - hist[n_stop - 1]["RE"]) <= 1e-3 * hist[n_stop - 1]["RE"]
+    ost, _ = _oracle_run(P, n_stop)
+    assert rel_list([host(t) for t in st.u_sub()], ost.u) <= 1e-4
+    plan.set_stopping(odp.ODP_STOP_NONE, 0.0, 0)
+    ref = plan.new_state()
+    plan.iterate(ref, n_stop)          # the statistics variants change no bit of the iterate
+    assert same_state(st, ref)
+    plan.set_stopping(odp.ODP_STOP_RE, tol, 0, every)
+    # a graph needs a whole number of check intervals
+    with pytest.raises(odp.OdpError):
+        odp.Graph([plan], [plan.new_state()], 6)
+    b = plan.new_state()
+    odp.Graph([plan], [b], 8).launch()
+    torch.cuda.synchronize()
+    assert plan.stop_status(b)[0]["iters"] == 8

@@ -188,17 +188,19 @@ def test_initial_probe_arguments_are_checked():
 def test_stopping_arguments_are_checked():
     plan = odp.Plan(**_plan_args())
     L = odp.lib()
-    assert L.odp_plan_set_stopping(None, odp.ODP_STOP_RF, 1e-5, 1000) == ODP_EINVAL
-    assert L.odp_plan_set_stopping(plan._h, 3, 1e-5, 0) == ODP_EINVAL           # unknown measure
-    assert L.odp_plan_set_stopping(plan._h, -1, 1e-5, 0) == ODP_EINVAL
-    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_RE, -1e-3, 0) == ODP_EINVAL
-    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_RE, float("nan"), 0) == ODP_EINVAL
-    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_RE, 1e-3, -1) == ODP_EINVAL
+    assert L.odp_plan_set_stopping(None, odp.ODP_STOP_RF, 1e-5, 1000, 1) == ODP_EINVAL
+    assert L.odp_plan_set_stopping(plan._h, 3, 1e-5, 0, 1) == ODP_EINVAL           # unknown measure
+    assert L.odp_plan_set_stopping(plan._h, -1, 1e-5, 0, 1) == ODP_EINVAL
+    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_RE, -1e-3, 0, 1) == ODP_EINVAL
+    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_RE, float("nan"), 0, 1) == ODP_EINVAL
+    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_RE, 1e-3, -1, 1) == ODP_EINVAL
     # the paper's two rules and a bare cap (host-side settings: no device needed)
-    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_RF, 1e-5, 1000) == 0
-    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_RE, 1e-3, 200) == 0
-    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_NONE, float("nan"), 7) == 0
-    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_NONE, 0.0, 0) == 0
+    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_RF, 1e-5, 1000, 1) == 0
+    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_RE, 1e-3, 200, 1) == 0
+    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_NONE, float("nan"), 7, 1) == 0
+    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_NONE, 0.0, 0, 1) == 0
+    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_RE, 1e-3, 200, 0) == ODP_EINVAL   # check interval < 1
+    assert L.odp_plan_set_stopping(plan._h, odp.ODP_STOP_RE, 1e-3, 200, 10) == 0
 
 
 def test_balancing_arguments_are_checked():
