@@ -260,3 +260,33 @@ def test_check_interval_stops_at_the_next_check():
     odp.Graph([plan], [b], 8).launch()
     torch.cuda.synchronize()
     assert plan.stop_status(b)[0]["iters"] == 8
+
+
+def test_blind_re_rule_stops_where_the_oracle_does():
+    """Algorithm 3 with the RE rule (Sec. 4) read after each iteration, against the FP64
+    blind trajectory from the same start (the initial probe of the extended tests)."""
+    from oracle import blind
+    spec = tiny_spec(n=128, p=32, step=8, jitter=1, dy=2, dx=2, radius=12, peak=None)
+    say("stop blind RE")
+    P = oracle_problem(spec)
+    g = P["geom"]
+    w_true, sf32, f = rounded_inputs(P)
+    mu = 0.5 * P["eta"] * max(len(fr) for fr in g.frames_of)
+    plan = gpu_plan(P, blind=True, mu=mu)
+    w0 = plan.blind_initial_probe()
+    w0h = host(w0)
+    K = 16
+    _, hist = blind.od2bp_run(g, f, w0h, P["eps"], P["eta"], P["r"], mu, K)
+    tol, (m,) = _pick_tol([[h["RE"] for h in hist]])
+    plan.set_stopping(odp.ODP_STOP_RE, tol, 0)
+    st = plan.new_state(w0=w0)
+    plan.iterate(st, K)
+    s = plan.stop_status(st)[0]
+    assert (s["iters"], s["stopped"]) == (m + 1, True), (s, m)
+    assert abs(s["re"] - hist[m]["RE"]) <= 1e-3 * hist[m]["RE"]
+    ost, _ = blind.od2bp_run(g, f, w0h, P["eps"], P["eta"], P["r"], mu, m + 1)
+    assert rel(host(st.probe()), ost.w) <= 1e-4
+    plan.set_stopping(odp.ODP_STOP_NONE, 0.0, 0)
+    ref = plan.new_state(w0=w0)
+    plan.iterate(ref, m + 1)
+    assert same_state(st, ref)
