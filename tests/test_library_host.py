@@ -81,6 +81,9 @@ def _plan_args(**kw):
     (dict(r=0.0), ODP_EINVAL),
     (dict(p=48), ODP_EUNSUPPORTED),
     (dict(H=16), ODP_EINVAL),
+    (dict(blind=True, mu=0.0), ODP_EINVAL),                        # blind needs mu > 0
+    (dict(gamma=-1.0), ODP_EINVAL),
+    (dict(transform=odp.ODP_DFT_SPLIT_BF16), ODP_EUNSUPPORTED),     # the MFMA transform is for p = 64
 ])
 def test_plan_rejects_bad_parameters(kw, code):
     with pytest.raises(OdpError) as e:
@@ -228,3 +231,19 @@ def test_size_helpers_match_plan_info():
     assert L.odp_plan_workspace_bytes(plan._h) == plan.info.workspace_bytes > 0
     assert L.odp_state_bytes(plan._h) == plan.info.state_bytes > 0
     assert L.odp_plan_workspace_bytes(None) == 0 and L.odp_state_bytes(None) == 0
+
+
+def test_batches_hold_known_probe_problems_only():
+    items = [(s, pr) for (s, pr) in _batch_problems(8) if s.p == 64][:2]
+    probs = [dict(H=s.n, W=s.n, p=s.p, offsets=pr["offsets"], frame_sub=pr["frame_sub"], r=1.0) for s, pr in items]
+    probs[1].update(blind=True, mu=1.0)
+    with pytest.raises(OdpError) as e:
+        odp.Plan.batch(probs)
+    assert e.value.code == ODP_EUNSUPPORTED
+
+
+def test_eta_balancing_is_refused_for_blind_plans():
+    plan = odp.Plan(**_plan_args(blind=True, mu=1.0))
+    L = odp.lib()
+    assert L.odp_plan_set_balancing(plan._h, 10.0, 2.0, 4, 0, odp.ODP_BALANCE_ETA) == ODP_EUNSUPPORTED
+    assert L.odp_plan_set_balancing(plan._h, 10.0, 2.0, 4, 0, odp.ODP_BALANCE_R) == 0
