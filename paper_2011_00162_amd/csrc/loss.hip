@@ -149,60 +149,110 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
 
 // dL/du on every subdomain tile: pull over all frames covering the pixel (every
 // slot of the tile's cell holds a disjoint set of frames).  Pixels in no
-// subdomain are covered by no frame and stay 0 (cleared by the caller).
+// subdomain are covered by no frame and stay 0 (cleared by the caller).  The padded
+// pull lists are read PULL_B records at a time for both of the thread's pixels, so
+// their loads are in flight together; each pixel sums its frames in list order.
 __global__ __launch_bounds__(256) void k_grad_u(LossGradArgs a) {
   const int tile = blockIdx.x;
   const TileDesc td = a.tiles[tile];
   const CellDesc* cd = a.cells + td.cell;
   const int p = a.p;
   // tiles partition the covered pixels, so each pixel is written by one thread
+  int yi[NPX], xi[NPX];
+  bool act[NPX];
+  float2 g[NPX];
+#pragma unroll
   for (int h = 0; h < NPX; ++h) {
     const int i = threadIdx.x + 256 * h, tr = i / a.tile_cols, tc = i % a.tile_cols;
-    const bool act = tr < td.nr && tc < td.nc;
-    const int yi = cd->r0 + td.r0 + tr, xi = cd->c0 + td.c0 + tc;
-    float2 g = make_float2(0.f, 0.f);
-    const int64_t pix = (int64_t)yi * p + xi;
-    for (int s = 0; s < cd->m; ++s) {
-      const int k1 = a.tf_first[tile * MAXS + s + 1];
-      for (int k = a.tf_first[tile * MAXS + s]; k < k1; ++k) {
-        const PullEntry pe = a.pull[k];
-        const int dy = yi - pe.r, dx = xi - pe.c;
-        if (act && (unsigned)dy < (unsigned)p && (unsigned)dx < (unsigned)p)
-          g = c_add(g, c_mulc(a.phi[pe.base + pix], a.w[dy * p + dx]));
-      }
-    }
-    if (act) a.grad_u[(int64_t)yi * a.W + xi] = g;
+    act[h] = tr < td.nr && tc < td.nc;
+    yi[h] = cd->r0 + td.r0 + tr;
+    xi[h] = cd->c0 + td.c0 + tc;
+    g[h] = make_float2(0.f, 0.f);
   }
+  for (int s = 0; s < cd->m; ++s) {
+    const int k1 = a.tf_first[tile * MAXS + s + 1];
+    for (int k = a.tf_first[tile * MAXS + s]; k < k1; k += PULL_B) {
+      PullEntry pe[PULL_B];
+#pragma unroll
+      for (int b = 0; b < PULL_B; ++b) pe[b] = a.pull[k + b];   // lists padded to PULL_B
+      float2 ph[NPX][PULL_B], ww[NPX][PULL_B];
+#pragma unroll
+      for (int h = 0; h < NPX; ++h)
+#pragma unroll
+        for (int b = 0; b < PULL_B; ++b) {
+          const int dy = yi[h] - pe[b].r, dx = xi[h] - pe[b].c;
+          const bool in = act[h] && (unsigned)dy < (unsigned)p && (unsigned)dx < (unsigned)p;
+          ph[h][b] = in ? a.phi[pe[b].base + (int64_t)yi[h] * p + xi[h]] : make_float2(0.f, 0.f);
+          ww[h][b] = in ? a.w[dy * p + dx] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+      for (int h = 0; h < NPX; ++h)
+#pragma unroll
+        for (int b = 0; b < PULL_B; ++b) g[h] = c_add(g[h], c_mulc(ph[h][b], ww[h][b]));
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < NPX; ++h)
+    if (act[h]) a.grad_u[(int64_t)yi[h] * a.W + xi[h]] = g[h];
 }
 
-// dL/dw partial sums over frame chunks (FP64), then a fixed-order final sum.
+// dL/dw partial sums over frame chunks (FP64; eight frames' loads in flight per step,
+// summed in frame order), then a fixed-order final sum.
 __global__ __launch_bounds__(256) void k_grad_w_part(LossGradArgs a) {
+  constexpr int B = 8;
   const int p = a.p, k = blockIdx.x * 256 + threadIdx.x, chunk = blockIdx.y;
   if (k >= p * p) return;
   const int ky = k / p, kx = k % p;
   const int j0 = chunk * a.frames_per_chunk;
   const int j1 = min(a.J, j0 + a.frames_per_chunk);
   double gx = 0.0, gy = 0.0;
-  for (int j = j0; j < j1; ++j) {
-    const float2 uu = a.u[((int64_t)a.offsets[2 * j] + ky) * a.W + a.offsets[2 * j + 1] + kx];
-    const float2 ph = a.phi[(size_t)j * p * p + k];
+  auto acc = [&](const float2 uu, const float2 ph) {
     gx += (double)uu.x * ph.x + (double)uu.y * ph.y;     // conj(u) * phi
     gy += (double)uu.x * ph.y - (double)uu.y * ph.x;
+  };
+  int j = j0;
+  for (; j + B <= j1; j += B) {
+    int oy[B], ox[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      oy[i] = a.offsets[2 * (j + i)];
+      ox[i] = a.offsets[2 * (j + i) + 1];
+    }
+    float2 uu[B], ph[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      uu[i] = a.u[((int64_t)oy[i] + ky) * a.W + ox[i] + kx];
+      ph[i] = a.phi[(size_t)(j + i) * p * p + k];
+    }
+#pragma unroll
+    for (int i = 0; i < B; ++i) acc(uu[i], ph[i]);
   }
+  for (; j < j1; ++j)
+    acc(a.u[((int64_t)a.offsets[2 * j] + ky) * a.W + a.offsets[2 * j + 1] + kx], a.phi[(size_t)j * p * p + k]);
   a.wpart[2 * ((size_t)chunk * p * p + k)] = gx;
   a.wpart[2 * ((size_t)chunk * p * p + k) + 1] = gy;
 }
 
+// the chunks' partial sums per probe pixel: the four wavefronts of a workgroup take every
+// fourth chunk for the same 64 pixels, added in wavefront order
 __global__ __launch_bounds__(256) void k_grad_w_final(LossGradArgs a) {
-  const int p = a.p, k = blockIdx.x * 256 + threadIdx.x;
-  if (k < p * p) {
-    double gx = 0.0, gy = 0.0;
-    for (int c = 0; c < a.n_chunks; ++c) {
+  __shared__ double part[2][4][64];
+  const int p = a.p, lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int k = blockIdx.x * 64 + lane;
+  const bool ok = k < p * p;
+  double gx = 0.0, gy = 0.0;
+  if (ok)
+    for (int c = grp; c < a.n_chunks; c += 4) {
       gx += a.wpart[2 * ((size_t)c * p * p + k)];
       gy += a.wpart[2 * ((size_t)c * p * p + k) + 1];
     }
-    a.grad_w[k] = make_float2((float)gx, (float)gy);
-  }
+  part[0][grp][lane] = gx;
+  part[1][grp][lane] = gy;
+  __syncthreads();
+  if (grp != 0 || !ok) return;
+  gx = ((part[0][0][lane] + part[0][1][lane]) + part[0][2][lane]) + part[0][3][lane];
+  gy = ((part[1][0][lane] + part[1][1][lane]) + part[1][2][lane]) + part[1][3][lane];
+  a.grad_w[k] = make_float2((float)gx, (float)gy);
 }
 
 __global__ __launch_bounds__(256) void k_loss_total(const double* frame_loss, int J, double* out) {
@@ -243,7 +293,7 @@ hipError_t launch_loss_grads(const LossGradArgs& a, hipStream_t s) {
   if (a.grad_w) {
     const int nb = (a.p * a.p + 255) / 256;
     hipLaunchKernelGGL(k_grad_w_part, dim3(nb, a.n_chunks), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_grad_w_final, dim3(nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_grad_w_final, dim3((a.p * a.p + 63) / 64), dim3(256), 0, s, a);
   }
   return hipGetLastError();
 }

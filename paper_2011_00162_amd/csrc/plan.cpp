@@ -90,6 +90,7 @@ struct odp_plan {
     std::vector<PullEntry> pull;             // frames whose window meets the tile, ascending id
   };
   TileSet tsets[3];
+  int64_t covered = 0;  // image pixels in some subdomain (the tiles partition them)
   int ts = 0;
   int32_t xcd_slice = 2;
   // stopping rule (Sec. 4) evaluated on the device after every iteration
@@ -343,6 +344,8 @@ int build_geometry(odp_plan* P) {
   P->chunk = (J + NXCD - 1) / NXCD;
   static const int shapes[3][2] = {{16, 32}, {8, 64}, {32, 16}};
   for (int k = 0; k < 3; ++k) build_tiles(P, shapes[k][0], shapes[k][1], P->tsets[k]);
+  P->covered = 0;
+  for (const TileDesc& td : P->tsets[0].tiles) P->covered += (int64_t)td.nr * td.nc;
   P->ts = 0;
   // twiddle table tw[i][k] = W_p^{i k} = exp(-2 pi i i k / p), i < p/16, k < 16, FP64 on the host
   const int n2 = p / 16;
@@ -1274,7 +1277,9 @@ int odp_amp_loss(const odp_plan* P, const odp_c32* u, const odp_c32* w, double* 
   ODP_HIP(launch_loss(P->p, la, grad, s));
   ODP_HIP(launch_loss_total(la.frame_loss, P->J, loss_out, s));
   if (!grad) return ODP_OK;
-  if (grad_u) ODP_HIP(launch_fill(reinterpret_cast<float2*>(grad_u), (int64_t)P->H * P->W, make_float2(0.f, 0.f), s));
+  // pixels in no tile are covered by no frame: their gradient is 0 (the tiles write the rest)
+  if (grad_u && P->covered < (int64_t)P->H * P->W)
+    ODP_HIP(launch_fill(reinterpret_cast<float2*>(grad_u), (int64_t)P->H * P->W, make_float2(0.f, 0.f), s));
   LossGradArgs ga;
   ga.u = la.u;
   ga.W = P->W;

@@ -71,3 +71,27 @@ def test_gradient_at_truth_vanishes():
     loss, gu, gw = plan2.amp_loss(dev_c64(u), dev_c64(w))
     assert host(loss)[0] < 1e-9 * float((sf.double() ** 2).sum())
     assert float(gu.abs().max()) < 1e-4 and float(gw.abs().max()) < 1e-3
+
+
+def test_gradient_is_zero_where_no_frame_reaches():
+    """A 300 x 300 image scanned only over its top-left 256 x 256: the pixels no window
+    reaches get dL/du = 0 (the library clears what its tiles do not cover)."""
+    say("amplitude loss, uncovered border")
+    n, p = 300, 128
+    off, grid = synthetic.raster_offsets(256, p, 32, 0, None)
+    sub = synthetic.block_partition(grid, 1, 1)
+    rng = np.random.default_rng(4)
+    u = ((1 + 0.2 * rng.standard_normal((n, n))) * np.exp(0.3j * rng.standard_normal((n, n)))).astype(
+        np.complex64).astype(np.complex128)
+    w = synthetic.make_probe(p, 48.0, 0.01).astype(np.complex64).astype(np.complex128)
+    f = ops.intensities(u * (1 + 0.05 * rng.standard_normal((n, n))), w, off)
+    sf32 = np.sqrt(f).astype(np.float32)
+    f = sf32.astype(np.float64) ** 2
+    plan = odp.Plan(n, n, p, off, sub, r=1.0)
+    plan.bind(dev_f32(sf32), dev_c64(w))
+    loss, gu, gw = plan.amp_loss(dev_c64(u), dev_c64(w))
+    L, gu_o, gw_o = amploss.grad(u, w, off, f)
+    gu = host(gu)
+    assert np.all(gu[256:, :] == 0) and np.all(gu[:, 256:] == 0)
+    assert rel(gu, gu_o) <= 1e-5 and rel(host(gw), gw_o) <= 1e-5
+    assert abs(host(loss)[0] - L) <= 1e-5 * L
