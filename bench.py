@@ -29,6 +29,7 @@ HBM_PEAK_GBS = 8000.0
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 DFT_FLOPS_PER_FRAME = 4 * 4 * 3 * 2 * 64 ** 3     # per frame-iteration of the split-BF16 DFT sweep
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_sweep_c2_pmc.md")
+PMC_SUMMARY_C5 = os.path.join(ROOT, "profiles", "k_sweep128_c5_pmc.md")
 KERNEL_SOURCES = ["paper_2011_00162_amd/csrc/kernels.hip", "paper_2011_00162_amd/csrc/fft_frame.hpp",
                   "paper_2011_00162_amd/csrc/prox.hpp", "paper_2011_00162_amd/csrc/odp_internal.hpp"]
 
@@ -41,11 +42,11 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per sweep launch from the committed PMC summary, if it matches the kernel source."""
-    if not os.path.exists(PMC_SUMMARY):
+def measured_traffic(path=PMC_SUMMARY):
+    """HBM bytes per sweep launch from a committed PMC summary, if it matches the kernel source."""
+    if not os.path.exists(path):
         return None
-    txt = open(PMC_SUMMARY).read()
+    txt = open(path).read()
     m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
     m_bytes = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     if not (m_hash and m_bytes) or m_hash.group(1) != kernel_hash():
@@ -306,7 +307,8 @@ def run_c5(args, torch, odp, synthetic):
         alg = 20.0 * J * spec.p ** 2 + 16.0 * plan.info.p_sub
         out[mode] = {"value": J / (ms / 1e3), "ms_per_step": ms, "sweep_ms": sweep,
                      "sweep_roofline": {"bound": "hbm", "achieved": alg / (sweep / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
-                                        "unit": "GB/s", "frac": alg / (sweep / 1e3) / 1e9 / HBM_PEAK_GBS}}
+                                        "unit": "GB/s", "frac": alg / (sweep / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                        "traffic": measured_traffic(PMC_SUMMARY_C5) if not blind else None}}
         del plan, st
     return {"metric": "ADMM frame-iters/s, 2048^2 / 6561 frames of 128^2, 8x8 subdomains",
             "value": out["blind"]["value"], "unit": "frame-iters/s", "n_gpus": 1, "steps": args.steps,
