@@ -42,13 +42,14 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(path=PMC_SUMMARY):
-    """HBM bytes per sweep launch from a committed PMC summary, if it matches the kernel source."""
+def measured_traffic(path=PMC_SUMMARY, key="traffic_bytes_per_launch"):
+    """HBM bytes per sweep launch (the line ``key``) from a committed PMC summary, if it
+    matches the kernel source."""
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
-    m_bytes = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    m_bytes = re.search(key + r":\s*([0-9.eE+]+)", txt)
     if not (m_hash and m_bytes) or m_hash.group(1) != kernel_hash():
         return None
     return float(m_bytes.group(1))
@@ -313,7 +314,9 @@ def run_c5(args, torch, odp, synthetic):
         out[mode] = {"value": J / (ms / 1e3), "ms_per_step": ms, "sweep_ms": sweep,
                      "sweep_roofline": {"bound": "hbm", "achieved": alg / (sweep / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
                                         "unit": "GB/s", "frac": alg / (sweep / 1e3) / 1e9 / HBM_PEAK_GBS,
-                                        "traffic": measured_traffic(PMC_SUMMARY_C5) if not blind else None}}
+                                        "traffic": measured_traffic(
+                                            PMC_SUMMARY_C5,
+                                            "traffic_bytes_per_launch" + ("_blind" if blind else ""))}}
         del plan, st
     return {"metric": "ADMM frame-iters/s, 2048^2 / 6561 frames of 128^2, 8x8 subdomains",
             "value": out["blind"]["value"], "unit": "frame-iters/s", "n_gpus": 1, "steps": args.steps,
