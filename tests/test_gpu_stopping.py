@@ -187,15 +187,15 @@ def test_batch_problems_stop_independently_also_in_a_graph():
             assert after[i]["iters"] > K and not same_u, i
 
 
-def _cap_freezes(plan, cap=2, extra=2):
+def _cap_freezes(plan, cap=2, extra=2, w0=None):
     """With the rule off but an iteration cap, a longer run stops at the cap and equals a
     run of exactly that many iterations (statistics variants on both sides)."""
     plan.set_stopping(odp.ODP_STOP_NONE, 0.0, cap)
-    st = plan.new_state()
+    st = plan.new_state(w0=w0)
     plan.iterate(st, cap + extra)
     assert [(s["iters"], s["stopped"]) for s in plan.stop_status(st)] == [(cap, True)] * plan.n_problems()
     plan.set_stopping(odp.ODP_STOP_NONE, 0.0, 0)
-    ref = plan.new_state()
+    ref = plan.new_state(w0=w0)
     plan.iterate(ref, cap, stats=True)
     assert same_state(st, ref)
 
@@ -210,6 +210,18 @@ def test_cap_with_the_mfma_transform():
                     transform=odp.ODP_DFT_SPLIT_BF16)
     plan.bind(dev_f32(sf32), dev_c64(w))
     _cap_freezes(plan)
+
+
+@pytest.mark.parametrize("blind", [False, True], ids=["known_probe", "blind"])
+def test_cap_with_the_two_half_transform(blind):
+    """The p = 128 sweep (one frame per workgroup, two half passes) and, blind, the probe
+    copies skip a stopped problem's frames too."""
+    spec = tiny_spec(n=256, p=128, step=32, jitter=2, dy=2, dx=2, radius=48, peak=1e3)
+    say("stop cap, p = 128, blind", blind)
+    P = oracle_problem(spec)
+    mu = 0.5 * P["eta"] * max(len(fr) for fr in P["geom"].frames_of) if blind else 0.0
+    plan = gpu_plan(P, blind=blind, mu=mu)
+    _cap_freezes(plan, w0=plan.blind_initial_probe() if blind else None)
 
 
 def test_cap_with_five_to_eight_copies():
