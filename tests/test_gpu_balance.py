@@ -71,6 +71,34 @@ def test_single_problem_penalties_follow_the_oracle():
     assert rel_list([host(t) for t in st.u_sub()], ost.u) <= 1e-4
 
 
+@pytest.mark.parametrize("p,transform", [(64, odp.ODP_FFT_F32), (64, odp.ODP_DFT_SPLIT_BF16), (128, odp.ODP_FFT_F32)],
+                         ids=["p64_fft", "p64_split_bf16", "p128_two_half"])
+def test_penalties_follow_the_oracle_with_the_larger_frame_sweeps(p, transform):
+    """The residual sums come from the statistics variants of every sweep kernel."""
+    q = p // 4
+    spec = tiny_spec(n=3 * p, p=p, step=q, jitter=2, dy=2, dx=2, radius=3 * p // 8, peak=None)
+    say("balance single, p", p, "transform", transform)
+    P = oracle_problem(spec)
+    K = 24
+    mu, [(ost, rh, _)] = _pick_mu([P], K)
+    w, sf32, _ = rounded_inputs(P)
+    plan = odp.Plan(spec.n, spec.n, p, P["pr"]["offsets"], P["pr"]["frame_sub"], eps=P["eps"], eta=P["eta"],
+                    r=P["r"], transform=transform)
+    plan.bind(dev_f32(sf32), dev_c64(w))
+    plan.set_balancing(mu, 2.0, PERIOD, 0)
+    st = plan.new_state()
+    got = []
+    for _ in range(K // PERIOD):
+        plan.iterate(st, PERIOD)
+        got.append(plan.penalties()[0])
+    want = rh[PERIOD - 1::PERIOD]
+    say("balance r/r0", [g / P["r"] for g in got], "mu", mu)
+    assert all(math.isclose(g, x, rel_tol=1e-12) for g, x in zip(got, want)), (got, want)
+    assert len(set(got)) > 1
+    # the K-iteration reconstruction bound
+    assert rel_list([host(t) for t in st.u_sub()], ost.u) <= 1e-3
+
+
 def test_batch_penalties_adapt_per_problem_and_graphs_refuse():
     say("balance batch")
     specs = [tiny_spec(n=128, p=32, step=8, jitter=1, dy=2, dx=2, radius=12, peak=1e4, seed=41),
