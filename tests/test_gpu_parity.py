@@ -273,3 +273,21 @@ def test_held_pixels_stay_one():
     u = host(st.u_sub()[0])
     assert np.any(den == 0)
     assert np.all(u[den == 0] == 1.0)
+
+
+def test_zero_iterations_leave_the_state_and_negative_counts_are_refused():
+    from paper_2011_00162_amd._lib import ODP_EINVAL
+    from tests.gpu_util import same_state
+    spec = tiny_spec(n=128, p=32, step=8, jitter=1, dy=2, dx=2, radius=12, peak=1e4)
+    say("zero iterations")
+    P = oracle_problem(spec)
+    plan = gpu_plan(P)
+    a, b = plan.new_state(), plan.new_state()
+    plan.iterate(a, 1)
+    c = a.clone()
+    assert plan.iterate(a, 0, stats=True) is None
+    assert same_state(a, c) and not same_state(a, b)
+    with pytest.raises(odp.OdpError) as e:
+        plan.iterate(a, -1)
+    assert e.value.code == ODP_EINVAL
+    assert same_state(a, c)

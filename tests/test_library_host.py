@@ -107,6 +107,22 @@ def test_plan_rejects_bad_geometry():
     assert e.value.code == ODP_EGEOM
 
 
+def test_degenerate_scans_are_refused():
+    """No frames, a window with a negative offset, an empty batch: refused on the host."""
+    a = _plan_args()
+    with pytest.raises(OdpError) as e:
+        odp.Plan(**{**a, "offsets": np.zeros((0, 2), np.int32), "frame_sub": np.zeros(0, np.int32)})
+    assert e.value.code == ODP_EINVAL
+    off = a["offsets"].copy()
+    off[0, 1] = -1
+    with pytest.raises(OdpError) as e:
+        odp.Plan(**{**a, "offsets": off})
+    assert e.value.code == ODP_EGEOM
+    with pytest.raises(OdpError) as e:
+        odp.Plan.batch([])
+    assert e.value.code == ODP_EINVAL
+
+
 def test_one_subdomain_needs_no_overlap_penalty():
     a = _plan_args(r=0.0, frame_sub=np.zeros(len(_plan_args()["offsets"]), np.int32))
     plan = odp.Plan(**a)
