@@ -93,6 +93,10 @@ def gpu_leg(args, torch, odp, synthetic, transform=0):
     plan.bind(sqrt_f, w)
     r = 0.5 * eta * plan.illum_max()
     plan.set_params(r=r)
+    # frame order and pixel tiling as the library's autotuner picks them (on a scratch
+    # state, before the timed region); the transform stays the one this leg measures
+    tune = plan.autotune(plan.new_state(), iters=20)
+    plan.set_tuning(transform, tune.xcd_slice, tune.tiling)
     state = plan.new_state()
     info = plan.info
 
@@ -120,7 +124,8 @@ def gpu_leg(args, torch, odp, synthetic, transform=0):
     alg_bytes = 20.0 * J * p * p + 16.0 * info.p_sub
     return dict(J=J, n=n, p=p, D=info.D, total_ms=total_ms, sweep_avg_ms=sweep_avg_ms,
                 sweep_median_ms=sweep_ms[len(sweep_ms) // 2], alg_bytes=alg_bytes, r=r, eta=eta, eps=eps,
-                p_sub=info.p_sub, n_pairs=info.n_pairs)
+                p_sub=info.p_sub, n_pairs=info.n_pairs,
+                tuning={"xcd_slice": tune.xcd_slice, "tiling": tune.tiling, "tile": [tune.tile_rows, tune.tile_cols]})
 
 
 def cpu_leg(args, torch, odp, synthetic):
@@ -484,7 +489,7 @@ def main() -> int:
             "workload": "non-blind OD2Pm, 512x512 image, 64x64 disk probe (R=24, phase 0.02 r^2), raster step 16 "
                         "+-2 px jitter, 841 frames, Poisson peak 1e4, 4x4 subdomains, eps=0.5, eta=0.1, "
                         "r=0.5*eta*max(diag A*A)",
-            "transform": "fft_f32",
+            "transform": "fft_f32", "tuning": g["tuning"],
             "frames": g["J"], "probe": g["p"], "image": g["n"], "subdomains": g["D"], "pairs": g["n_pairs"],
         },
         "transforms": {
