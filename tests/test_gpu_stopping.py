@@ -302,3 +302,16 @@ def test_blind_re_rule_stops_where_the_oracle_does():
     ref = plan.new_state(w0=w0)
     plan.iterate(ref, m + 1)
     assert same_state(st, ref)
+
+
+def test_autotune_restores_the_rule():
+    """The autotuner times whole iterations with the rule off and puts it back."""
+    spec = tiny_spec(n=128, p=32, step=8, jitter=1, dy=2, dx=2, radius=12, peak=1e4)
+    say("stop rule across autotune")
+    P = oracle_problem(spec)
+    plan = gpu_plan(P)
+    plan.set_stopping(odp.ODP_STOP_NONE, 0.0, 3)
+    plan.autotune(plan.new_state(), iters=2)
+    st = plan.new_state()
+    plan.iterate(st, 5)
+    assert [(s["iters"], s["stopped"]) for s in plan.stop_status(st)] == [(3, True)]
