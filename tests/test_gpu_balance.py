@@ -197,3 +197,16 @@ def test_data_penalty_refused_for_blind_plans():
     with pytest.raises(odp.OdpError):
         plan.set_balancing(10.0, 2.0, 4, 0, odp.ODP_BALANCE_ETA)
     plan.set_balancing(10.0, 2.0, 4, 0, odp.ODP_BALANCE_R)   # r stays available
+
+
+def test_autotune_leaves_the_penalties_and_restores_balancing():
+    spec = tiny_spec(n=128, p=32, step=8, jitter=1, dy=2, dx=2, radius=12, peak=1e4)
+    say("balancing across autotune")
+    P = oracle_problem(spec)
+    plan = gpu_plan(P)
+    plan.set_balancing(1.0, 2.0, 1, 0)              # mu = 1: every check changes r
+    plan.autotune(plan.new_state(), iters=2)
+    assert plan.penalties() == [P["r"]]             # timed with balancing off
+    st = plan.new_state()
+    plan.iterate(st, 1)
+    assert plan.penalties() != [P["r"]]             # and on again afterwards
