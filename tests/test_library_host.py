@@ -263,3 +263,18 @@ def test_eta_balancing_is_refused_for_blind_plans():
     L = odp.lib()
     assert L.odp_plan_set_balancing(plan._h, 10.0, 2.0, 4, 0, odp.ODP_BALANCE_ETA) == ODP_EUNSUPPORTED
     assert L.odp_plan_set_balancing(plan._h, 10.0, 2.0, 4, 0, odp.ODP_BALANCE_R) == 0
+
+
+def test_benchmark_reads_measured_traffic_only_for_the_current_kernels(tmp_path):
+    """A PMC summary's traffic is used only while its kernel-source hash matches; the
+    known-probe and blind lines are read by their own keys."""
+    import bench
+    good = tmp_path / "good.md"
+    good.write_text("traffic_bytes_per_launch: 1.5e+09\ntraffic_bytes_per_launch_blind: 2.5e+09\n"
+                    f"kernel_source_sha256_16: {bench.kernel_hash()}\n")
+    assert bench.measured_traffic(str(good)) == 1.5e9
+    assert bench.measured_traffic(str(good), "traffic_bytes_per_launch_blind") == 2.5e9
+    stale = tmp_path / "stale.md"
+    stale.write_text("traffic_bytes_per_launch: 1.5e+09\nkernel_source_sha256_16: 0000000000000000\n")
+    assert bench.measured_traffic(str(stale)) is None
+    assert bench.measured_traffic(str(tmp_path / "missing.md")) is None
