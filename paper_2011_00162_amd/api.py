@@ -253,8 +253,11 @@ class Plan:
         return self._geom
 
     # ---- device side ----
-    def bind(self, sqrt_f: torch.Tensor, w: torch.Tensor, stream=None) -> "Plan":
-        """w: [p, p] probe, or [n, p, p] probes of a batch plan (one per problem)."""
+    def bind(self, sqrt_f: torch.Tensor, w: torch.Tensor, stream=None,
+             workspace: torch.Tensor | None = None) -> "Plan":
+        """w: [p, p] probe, or [n, p, p] probes of a batch plan (one per problem).
+        workspace: optional uint8 device buffer of at least info.workspace_bytes,
+        256-byte aligned (allocated here when omitted)."""
         i = self.info
         if sqrt_f.dtype != torch.float32 or tuple(sqrt_f.shape) != (i.J, i.p, i.p):
             raise ValueError("sqrt_f must be float32 [J, p, p]")
@@ -262,7 +265,11 @@ class Plan:
             _c64(w, (self.n_problems(), i.p, i.p))
         else:
             _c64(w, (i.p, i.p))
-        self.workspace = torch.empty(i.workspace_bytes, dtype=torch.uint8, device=sqrt_f.device)
+        if workspace is None:
+            workspace = torch.empty(i.workspace_bytes, dtype=torch.uint8, device=sqrt_f.device)
+        elif workspace.dtype != torch.uint8 or workspace.numel() < i.workspace_bytes:
+            raise ValueError("workspace must be uint8 with at least workspace_bytes elements")
+        self.workspace = workspace
         check(lib().odp_plan_bind(self._h, _ptr(self.workspace), _ptr(sqrt_f), _ptr(w), _stream(stream)))
         self._keep = (sqrt_f, w)
         return self

@@ -518,21 +518,21 @@ hipError_t launch_stats(const double* frame_part, int J, const double* tile_part
   return hipGetLastError();
 }
 
-// per problem (one thread each), its subdomains in ascending order; thread n copies the
-// plan's frame sums
-__global__ void k_residual_sums(const double* scratch, const int32_t* prob, int n, int D, double* out) {
+// per problem (one thread each): its subdomains' sums in ascending order, then its frames'
+// residual sums in ascending frame order
+__global__ void k_residual_sums(const double* scratch, const double* frame_part, const int32_t* prob, int n,
+                                double* out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i > n) return;
-  if (i == n) {
-    out[6 * (size_t)n] = scratch[NPS * (size_t)D + 2];
-    out[6 * (size_t)n + 1] = scratch[NPS * (size_t)D + 3];
-    return;
-  }
-  const int D0 = prob[4 * i + 2], Dp = prob[4 * i + 3];
-  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (i >= n) return;
+  const int J0 = prob[4 * i], Jp = prob[4 * i + 1], D0 = prob[4 * i + 2], Dp = prob[4 * i + 3];
+  double v[NRES] = {};
   for (int d = D0; d < D0 + Dp; ++d)
     for (int k = 0; k < 6; ++k) v[k] += scratch[NPS * (size_t)d + 2 + k];
-  for (int k = 0; k < 6; ++k) out[6 * (size_t)i + k] = v[k];
+  for (int j = J0; j < J0 + Jp; ++j) {
+    v[6] += frame_part[NFS * (size_t)j + 2];
+    v[7] += frame_part[NFS * (size_t)j + 3];
+  }
+  for (int k = 0; k < NRES; ++k) out[NRES * (size_t)i + k] = v[k];
 }
 
 hipError_t launch_residual_sums(const double* frame_part, int J, const double* tile_part, const int32_t* re_list,
@@ -540,7 +540,7 @@ hipError_t launch_residual_sums(const double* frame_part, int J, const double* t
                                 double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_stats_reduce, dim3(D + 1), dim3(256), 0, s, frame_part, J, tile_part, re_list, re_first, D,
                      scratch);
-  hipLaunchKernelGGL(k_residual_sums, dim3((n + 64) / 64), dim3(64), 0, s, scratch, prob, n, D, out);
+  hipLaunchKernelGGL(k_residual_sums, dim3((n + 63) / 64), dim3(64), 0, s, scratch, frame_part, prob, n, out);
   return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@ constexpr int NPX = 2;                          // pixels per thread in the pixe
 constexpr int PULL_B = 4;                       // pull records per group (lists padded to a multiple)
 constexpr int NPS = 8;                          // pixel-update statistics per (tile, copy slot)
 constexpr int NFS = 4;                          // frame-sweep statistics per frame
+constexpr int NRES = 8;                         // penalty-rule residual sums per problem (launch_residual_sums)
 constexpr int NXCD = 8;                        // MI355X accelerator complex dies
 
 // A cell is a rectangle of image pixels covered by the same set of subdomains
@@ -207,10 +208,11 @@ struct StopArgs {
 hipError_t launch_stop_check(const StopArgs& a, const double* tile_part, const int32_t* re_list,
                              const int32_t* re_first, int D, double* scratch, hipStream_t s);
 
-// Residual sums for the penalty rule (per-subdomain sums from the statistics reduction in
-// scratch): out[6 i + k] = sum over problem i's subdomains of (|Lam^{n+1} - Lam^n|^2,
-// (m-1)|du|^2, (m-1)|u^{n+1}|^2, |Lam^{n+1}|^2, den |u^n|^2, den |du|^2); then
-// out[6 n], out[6 n + 1] = the plan's |Gamma^{n+1} - Gamma^n|^2 and |Gamma^{n+1}|^2.
+// Residual sums for the penalty rule, NRES per problem: out[NRES i + k], k < 6 = the sums
+// over problem i's subdomains (from the per-subdomain statistics reduction in scratch) of
+// (|Lam^{n+1} - Lam^n|^2, (m-1)|du|^2, (m-1)|u^{n+1}|^2, |Lam^{n+1}|^2, den |u^n|^2,
+// den |du|^2); k = 6, 7 = the sums over problem i's frames of |Gamma^{n+1} - Gamma^n|^2 and
+// |Gamma^{n+1}|^2.  out holds NRES * n doubles.
 hipError_t launch_residual_sums(const double* frame_part, int J, const double* tile_part, const int32_t* re_list,
                                 const int32_t* re_first, int D, const int32_t* prob, int n, double* scratch,
                                 double* out, hipStream_t s);

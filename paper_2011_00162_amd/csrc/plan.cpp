@@ -131,6 +131,9 @@ struct odp_plan {
   struct {
     size_t u_sub, gamma, lam, w, w_sub, delta, stop, bytes;
   } st{};
+  // bumped by every call that rewrites launch arguments or device tables a captured graph
+  // holds (penalties, reciprocals, tiling and placement, rebinding); graphs record it
+  uint64_t gen = 0;
   // bound state
   char* wsp = nullptr;
   const float* sqrt_f = nullptr;
@@ -422,7 +425,7 @@ void layout(odp_plan* P) {
   P->ws.wpart = take(sizeof(double) * 2 * pp * LOSS_CHUNKS);
   P->ws.dft = take(sizeof(uint16_t) * P->dft.size() + 16);
   P->ws.prob = take(sizeof(int32_t) * 4 * P->n_probes());
-  P->ws.resid = take(sizeof(double) * 4 * P->n_probes());
+  P->ws.resid = take(sizeof(double) * NRES * P->n_probes());
   P->ws.bytes = o;
   size_t s = 0;
   auto stake = [&](size_t bytes) {
@@ -592,6 +595,7 @@ int upload_tiles(odp_plan* P, hipStream_t s) {
 
 // per-problem overlap penalties: cell descriptors carry r; reciprocals rebuilt
 int set_penalties(odp_plan* P, const double* r, hipStream_t s) {
+  ++P->gen;
   for (int i = 0; i < P->n_probes(); ++i) P->batch[i].r = r[i];
   for (CellDesc& cd : P->cells) cd.r = (float)P->batch[cd.probe].r;
   if (!P->wsp) return ODP_OK;
@@ -822,6 +826,7 @@ int odp_plan_get_cover(const odp_plan* P, int32_t* cover) {
 int odp_plan_bind(odp_plan* P, void* dev_ws, const float* dev_sqrt_f, const odp_c32* dev_w, hipStream_t s) {
   if (!P || !dev_ws || !dev_sqrt_f || !dev_w) return fail(ODP_EINVAL, "null argument");
   if (reinterpret_cast<uintptr_t>(dev_ws) & 255) return fail(ODP_EINVAL, "workspace must be 256-byte aligned");
+  ++P->gen;
   P->wsp = static_cast<char*>(dev_ws);
   P->sqrt_f = dev_sqrt_f;
   const size_t pp = (size_t)P->p * P->p;
@@ -1015,9 +1020,15 @@ static int balance_penalties(odp_plan* P, char* b, hipStream_t s) {
   ODP_HIP(launch_residual_sums(P->W_<double>(P->ws.fpart), P->J, P->W_<double>(P->ws.tpart),
                                P->W_<int32_t>(P->ws.re_list), P->W_<int32_t>(P->ws.re_first), P->D,
                                P->W_<int32_t>(P->ws.prob), n, P->W_<double>(P->ws.stat_scratch), dev, s));
-  std::vector<double> h((size_t)6 * n + 2);
+  std::vector<double> h((size_t)NRES * n);
   ODP_HIP(hipMemcpyAsync(h.data(), dev, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+  // a problem stopped by its rule (this iteration included) keeps its state: its penalty and
+  // multipliers stay as they are, and its sums (stale once it skips iterations) are left out
+  std::vector<StopStatus> stop(P->stopping() ? n : 0);
+  if (!stop.empty())
+    ODP_HIP(hipMemcpyAsync(stop.data(), b + P->st.stop, sizeof(StopStatus) * n, hipMemcpyDeviceToHost, s));
   ODP_HIP(hipStreamSynchronize(s));
+  auto running = [&](int i) { return stop.empty() || !stop[i].stopped; };
   auto factor = [&](double Pr, double S, double U, double L) {
     if (!(U > 0.0 && L > 0.0)) return 1.0;
     const double rp = std::sqrt(Pr / U), rd = std::sqrt(S / L);
@@ -1029,9 +1040,10 @@ static int balance_penalties(odp_plan* P, char* b, hipStream_t s) {
   bool changed = false;
   for (int i = 0; i < n; ++i) {
     const odp_plan::Entry& e = P->batch[i];
+    const double* hi = &h[(size_t)NRES * i];
     r[i] = e.r;
-    if (!do_r || e.D < 2) continue;
-    const double fac = factor(h[6 * i], h[6 * i + 1], h[6 * i + 2], h[6 * i + 3]);
+    if (!do_r || e.D < 2 || !running(i)) continue;
+    const double fac = factor(hi[0], hi[1], hi[2], hi[3]);
     if (fac == 1.0) continue;
     r[i] = e.r * fac;
     changed = true;
@@ -1047,16 +1059,33 @@ static int balance_penalties(odp_plan* P, char* b, hipStream_t s) {
       ODP_HIP(launch_scale(reinterpret_cast<float2*>(b + P->st.lam) + l0, l1 - l0, (float)(1.0 / fac), s));
   }
   if (do_eta) {
-    double U = 0.0, S = 0.0;
+    // eta is shared by the plan's problems: decided on the running ones' sums, applied to
+    // the running ones' multipliers Gamma (a stopped problem keeps its Gamma; it reads eta
+    // again only through a new state)
+    double U = 0.0, S = 0.0, Pr = 0.0, L = 0.0;
     for (int i = 0; i < n; ++i) {
-      U += h[6 * i + 4];
-      S += h[6 * i + 5];
+      if (!running(i)) continue;
+      const double* hi = &h[(size_t)NRES * i];
+      U += hi[4];
+      S += hi[5];
+      Pr += hi[6];
+      L += hi[7];
     }
-    const double fac = factor(h[6 * n], S, U, h[6 * n + 1]);
+    const double fac = factor(Pr, S, U, L);
     if (fac != 1.0) {
       P->eta *= fac;
-      ODP_HIP(launch_scale(reinterpret_cast<float2*>(b + P->st.gamma), (int64_t)P->J * P->p * P->p,
-                           (float)(1.0 / fac), s));
+      const int64_t pp = (int64_t)P->p * P->p;
+      for (int i = 0; i < n; ++i) {
+        if (!running(i)) continue;
+        const odp_plan::Entry& e = P->batch[i];
+        // consecutive running problems share one launch
+        int k = i;
+        while (k + 1 < n && running(k + 1)) ++k;
+        const int64_t j0 = e.J0, j1 = (int64_t)P->batch[k].J0 + P->batch[k].J;
+        ODP_HIP(launch_scale(reinterpret_cast<float2*>(b + P->st.gamma) + j0 * pp, (j1 - j0) * pp,
+                             (float)(1.0 / fac), s));
+        i = k;
+      }
       changed = true;
     }
   }
@@ -1324,6 +1353,7 @@ int odp_plan_set_tuning(odp_plan* P, int32_t transform, int32_t xcd_slice, int32
     return fail(ODP_EUNSUPPORTED, "the split-BF16 DFT transform is built for p = 64");
   if (tiling < 0 || tiling > 2) return fail(ODP_EINVAL, "tiling must be 0, 1 or 2");
   if (xcd_slice < 0 || xcd_slice > 2) return fail(ODP_EINVAL, "xcd_slice must be 0, 1 or 2");
+  if (transform != P->transform || xcd_slice != P->xcd_slice || tiling != P->ts) ++P->gen;
   P->transform = transform;
   const bool moved = tiling != P->ts || (xcd_slice == 2) != (P->xcd_slice == 2);
   P->xcd_slice = xcd_slice;
@@ -1398,6 +1428,7 @@ int odp_plan_autotune(odp_plan* P, void* dev_scratch_state, int32_t iters, hipSt
 struct odp_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  std::vector<std::pair<const odp_plan*, uint64_t>> plans;   // each plan's generation at capture
 };
 
 extern "C" {
@@ -1482,12 +1513,17 @@ int odp_graph_create(odp_plan* const* plans, void* const* states, int32_t n, int
   }
   G->graph = g;
   G->exec = ex;
+  for (int i = 0; i < n; ++i) G->plans.emplace_back(plans[i], plans[i]->gen);
   *out = G;
   return ODP_OK;
 }
 
 int odp_graph_launch(odp_graph* G, hipStream_t s) {
   if (!G) return fail(ODP_EINVAL, "null graph");
+  for (const auto& pg : G->plans)
+    if (pg.first->gen != pg.second)
+      return fail(ODP_EINVAL, "stale graph: a plan's penalties, tuning or binding changed after capture; "
+                              "create the graph again");
   ODP_HIP(hipGraphLaunch(G->exec, s));
   return ODP_OK;
 }

@@ -210,3 +210,50 @@ def test_autotune_leaves_the_penalties_and_restores_balancing():
     st = plan.new_state()
     plan.iterate(st, 1)
     assert plan.penalties() != [P["r"]]             # and on again afterwards
+
+
+def _eight_problem_batch():
+    """Eight small known-probe problems with subdomain pairs (the residual sums hold NRES
+    doubles per problem, so eight problems reach well past any alignment padding)."""
+    specs = [tiny_spec(n=96 + 16 * (i % 3), p=32, step=8, jitter=1, dy=1 + i % 2, dx=2, radius=12,
+                       peak=None if i % 2 else 1e4, seed=60 + i) for i in range(8)]
+    Ps = [oracle_problem(s) for s in specs]
+    plan = odp.Plan.batch([dict(H=P["pr"]["spec"].n, W=P["pr"]["spec"].n, p=32, offsets=P["pr"]["offsets"],
+                                frame_sub=P["pr"]["frame_sub"], r=P["r"]) for P in Ps])
+    return Ps, plan
+
+
+def test_residual_sums_stay_inside_the_workspace():
+    """Balancing r and eta on eight problems writes every problem's residual sums inside the
+    workspace: a guard region right after workspace_bytes keeps its fill pattern."""
+    say("balance: workspace guard, 8 problems")
+    Ps, plan = _eight_problem_batch()
+    nb = plan.info.workspace_bytes
+    buf = torch.full((nb + 4096,), 0xA5, dtype=torch.uint8, device="cuda")
+    plan.bind(dev_f32(np.concatenate([rounded_inputs(P)[1] for P in Ps])),
+              dev_c64(np.stack([rounded_inputs(P)[0] for P in Ps])), workspace=buf)
+    plan.set_balancing(1.0, 2.0, 1, 0, odp.ODP_BALANCE_R | odp.ODP_BALANCE_ETA)   # mu = 1: checks act
+    st = plan.new_state()
+    plan.iterate(st, 6)
+    torch.cuda.synchronize()
+    assert bool((buf[nb:] == 0xA5).all()), "residual sums written past the workspace"
+    assert plan.eta() != 0.1 and len(set(plan.penalties())) > 1
+    assert all(bool(torch.isfinite(torch.view_as_real(t)).all()) for t in st.u_sub())
+
+
+def test_stopped_problems_take_no_part_in_balancing():
+    """After every problem of a batch has met its iteration cap, further balanced iterations
+    change neither the penalties nor any bit of the state (r and eta both balanced)."""
+    say("balance: stopped problems frozen")
+    Ps, plan = _eight_problem_batch()
+    plan.bind(dev_f32(np.concatenate([rounded_inputs(P)[1] for P in Ps])),
+              dev_c64(np.stack([rounded_inputs(P)[0] for P in Ps])))
+    plan.set_stopping(odp.ODP_STOP_NONE, 0.0, 4)
+    plan.set_balancing(1.0, 2.0, 1, 0, odp.ODP_BALANCE_R | odp.ODP_BALANCE_ETA)
+    st = plan.new_state()
+    plan.iterate(st, 4)
+    assert all(s["stopped"] for s in plan.stop_status(st))
+    r0, eta0, frozen = plan.penalties(), plan.eta(), st.clone()
+    plan.iterate(st, 4)
+    assert plan.penalties() == r0 and plan.eta() == eta0
+    assert same_state(st, frozen)

@@ -137,3 +137,30 @@ def test_per_problem_penalties():
     it = items[0]
     ost, _ = od2pm_run(it["g"], it["w"], it["f"], 0.5, 0.1, r[0], 4)
     assert rel_list(_member_u(plan, st, 0), ost.u) <= 1e-4
+
+
+def test_graph_refused_once_stale():
+    """A graph keeps its plans' launch arguments and tables from capture: after a penalty,
+    tuning or autotune change on one of them, launching it is refused until it is made again."""
+    say("stale graph")
+    items = _uneven_problems()[:2]
+    plan = _batch(items)
+    st = plan.new_state()
+    g = odp.Graph([plan], [st], 2)
+    g.launch()
+    plan.set_penalties([it["r"] * 2.0 for it in items])
+    with pytest.raises(odp.OdpError, match="stale"):
+        g.launch()
+    g = odp.Graph([plan], [st], 2)
+    g.launch()
+    t = plan.tuning()
+    plan.set_tuning(t.transform, t.xcd_slice, t.tiling)     # unchanged: still valid
+    g.launch()
+    plan.set_tuning(t.transform, t.xcd_slice, (t.tiling + 1) % 3)
+    with pytest.raises(odp.OdpError, match="stale"):
+        g.launch()
+    g = odp.Graph([plan], [st], 2)
+    plan.autotune(plan.new_state(), iters=1)
+    with pytest.raises(odp.OdpError, match="stale"):
+        g.launch()
+    torch.cuda.synchronize()
