@@ -242,6 +242,7 @@ def run_c4(args, torch, odp, synthetic):
     eta = 0.1
     plans, states, info = [], [], {}
     total_frames = 0
+    max_cover = 0
     alg = 0.0                            # algorithmic HBM bytes of one iteration of every problem
     for p, group in sorted(groups.items()):
         probs, sfs, ws = [], [], []
@@ -254,6 +255,7 @@ def run_c4(args, torch, odp, synthetic):
             probs.append(dict(H=s.n, W=s.n, p=p, offsets=pr["offsets"], frame_sub=pr["frame_sub"], eps=0.5,
                               eta=eta, r=1.0))
         plan = odp.Plan.batch(probs)
+        max_cover = max(max_cover, plan.info.max_cover)
         plan.bind(torch.from_numpy(np.concatenate(sfs)).cuda(), torch.from_numpy(np.stack(ws)).cuda())
         plan.set_penalties([0.5 * eta * plan.entry(i).illum_max for i in range(len(group))])
         scratch = plan.new_state()
@@ -287,8 +289,10 @@ def run_c4(args, torch, odp, synthetic):
                          "achieved": alg / (ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_iteration": alg},
             "config": {"workload": "64 non-blind problems: image 256..1024, probe 64 or 128, step p*U(0.25,0.5), "
-                                   "2x2..6x6 subdomains, Poisson 1e3..1e5; 100 iterations per graph replay",
-                       "frames": total_frames, "groups": info}}
+                                   "g x g subdomains with g drawn from 2..6 (capped at the scan's positions per axis), "
+                                   "Poisson 1e3..1e5; 100 iterations per graph replay",
+                       "frames": total_frames, "groups": info,
+                       "grids": [s.dy for s in specs], "max_cover": max_cover}}
 
 
 def run_c5(args, torch, odp, synthetic):

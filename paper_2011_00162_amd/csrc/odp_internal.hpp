@@ -7,7 +7,7 @@
 
 namespace odp {
 
-constexpr int MAXS = 8;                        // most subdomains over one pixel
+constexpr int MAXS = 16;                       // most subdomains over one pixel
 constexpr int MAXP = MAXS * (MAXS - 1) / 2;    // most pairs over one pixel
 constexpr int NPX = 2;                          // pixels per thread in the pixel-tile kernels
 constexpr int PULL_B = 4;                       // pull records per group (lists padded to a multiple)
@@ -118,7 +118,8 @@ struct PixelArgs {
   const CellDesc* cells;
   const TileDesc* tiles;
   int32_t n_tiles, p, tile_cols;
-  int32_t n_uni;             // tiles [0, n_uni) belong to cells with at most 4 copies
+  int32_t n_uni;             // tiles [0, n_uni) belong to cells with at most 4 copies, the rest to
+                             // cells with 5 to MAXS
   const WaveRec* waves;      // [n_uni][4]
   const float2* psi;         // per-frame outputs of the sweep
   const int32_t* tf_first;   // [n_tiles*MAXS + 1]: frames of slot s overlapping tile t

@@ -121,12 +121,12 @@ __device__ __forceinline__ float2 pixel_value(const PixelArgs& a, int m, float r
 // (m-1)|du|^2, (m-1)|u^{n+1}|^2, |Lam^{n+1}|^2, then the frame constraint's terms
 // den |u^n|^2 and den |du|^2), reduced in a fixed order into part[tile][s][NPS]
 __device__ __forceinline__ void pixel_stats(const PixelArgs& a, int tile, int m, int tpg, double (&v)[NPS],
-                                            double (*red)[8]) {
+                                            double (*red)[MAXS]) {
   const int g = min(tpg, 64);                    // lanes of one group inside a wavefront
   for (int o = g >> 1; o > 0; o >>= 1)
 #pragma unroll
     for (int k = 0; k < NPS; ++k) v[k] += __shfl_xor(v[k], o, 64);
-  const int chunk = threadIdx.x / g;             // 256 / g <= 8 chunks, tpg / g per group
+  const int chunk = threadIdx.x / g;             // 256 / g <= MAXS chunks, tpg / g per group
   if ((threadIdx.x & (g - 1)) == 0)
 #pragma unroll
     for (int k = 0; k < NPS; ++k) red[k][chunk] = v[k];
@@ -169,7 +169,7 @@ __device__ __forceinline__ void residual_terms(int m, float2 un, float2 uo, cons
 // a 512 x 512 problem with 4 x 4 subdomains resident at once.
 template <bool STATS, bool BLIND>
 __global__ __launch_bounds__(256, BLIND ? 1 : 6) void k_pixel_uni(PixelArgs a) {
-  __shared__ double red[NPS][8];
+  __shared__ double red[NPS][MAXS];
   constexpr int NO = 3;                          // partner copies at most
   const int tile = blockIdx.x;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -254,13 +254,17 @@ __global__ __launch_bounds__(256, BLIND ? 1 : 6) void k_pixel_uni(PixelArgs a) {
 }
 
 // log2 of the copy groups of a cell with m copies (m rounded up to a power of two)
-__device__ __forceinline__ int copy_groups_log2(int m) { return m <= 1 ? 0 : m <= 2 ? 1 : m <= 4 ? 2 : 3; }
+__device__ __forceinline__ int copy_groups_log2(int m) {
+  return m <= 1 ? 0 : m <= 2 ? 1 : m <= 4 ? 2 : m <= 8 ? 3 : 4;
+}
 
-// Tiles of cells with five to eight copies (tiles [n_uni, n_tiles)): the copy index
-// varies inside a wavefront, so the descriptors come from the cell, per lane.
+// Tiles of cells with five to MAXS copies (tiles [n_uni, n_tiles)): the copy index
+// varies inside a wavefront, so the descriptors come from the cell, per lane.  A thread
+// keeps v - Lam for each of its up to MAXS - 1 partners until the barrier; the partners'
+// iterate n is read partner by partner.
 template <bool STATS, bool BLIND>
 __global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
-  __shared__ double red[NPS][8];
+  __shared__ double red[NPS][MAXS];
   constexpr int NO = MAXS - 1;
   const int tile = a.n_uni + blockIdx.x;
   const TileDesc td = a.tiles[tile];

@@ -149,9 +149,10 @@ namespace {
 
 // Cut every cell into tiles and list, per (tile, subdomain slot), the slot's frames
 // whose window meets the tile (ascending id).  A cell with m copies per pixel gets
-// tiles of 512 / m' pixels (m' = m rounded up to a power of two), so one workgroup
-// of 256 threads, two pixels per thread, holds every copy of its pixels: width
-// min(cols, 512 / m'), height the rest (rows x cols = 512 is the shape for m = 1).
+// tiles of 512 / m' pixels (m' = m rounded up to a power of two, at most MAXS = 16: 32
+// pixels), so one workgroup of 256 threads, two pixels per thread, holds every copy of
+// its pixels: width min(cols, 512 / m'), height the rest (rows x cols = 512 is the shape
+// for m = 1).
 void build_tiles(const odp_plan* P, int rows, int cols, odp_plan::TileSet& T) {
   const int p = P->p, D = P->D;
   T.rows = rows;

@@ -208,7 +208,10 @@ def batch_specs(count: int = 64, seed: int = 4) -> list[ProblemSpec]:
 
     Per problem: image side uniform over {256,384,...,1024}; probe 64 or 128 (coin
     flip); step = round(p*U(0.25,0.5)); g x g subdomains with g in {2..6}; Poisson
-    peak log-uniform in [1e3, 1e5]; 100 iterations.
+    peak log-uniform in [1e3, 1e5]; 100 iterations.  A grid with more blocks than the
+    scan has positions per axis cannot give every subdomain a frame (frame-first
+    partition), so g is capped at that count; no other draw is changed.  With
+    step >= p/4 a pixel then lies in at most 4 x 4 = 16 subdomains.
     """
     specs = []
     for i, child in enumerate(np.random.SeedSequence(seed).spawn(count)):
@@ -219,11 +222,7 @@ def batch_specs(count: int = 64, seed: int = 4) -> list[ProblemSpec]:
         g = int(rng.integers(2, 7))
         peak = float(10.0 ** rng.uniform(3.0, 5.0))
         radius, quad = (24.0, 0.02) if p == 64 else (48.0, 0.01)
-        # each block spans at least ceil(p/step) scan positions per axis, so that only
-        # neighbouring subdomains overlap (at most 4 copies of a pixel), as in the
-        # paper's stripe and two-subdomain decompositions
-        k = len(raster_positions(n, p, step))
-        g = max(1, min(g, k // -(-p // step)))
+        g = min(g, len(raster_positions(n, p, step)))
         specs.append(ProblemSpec(f"c4_{i:02d}", n=n, sigma=8.0, p=p, radius=radius, quad=quad,
                                  step=step, jitter=0, dy=g, dx=g, peak=peak, iters=100,
                                  seed=child))

@@ -156,7 +156,7 @@ def test_one_iteration_from_random_state(name, spec, eta):
 def _interleaved(P, D, eta):
     """Frame j goes to subdomain j mod D: every subdomain spans the image, so a pixel
     lies in up to D subdomains (D = 3 leaves an idle copy group of four, D > 4 takes
-    the path for five to eight copies)."""
+    the path for five to sixteen copies)."""
     pr = P["pr"]
     spec = pr["spec"]
     pr["frame_sub"] = (np.arange(len(pr["offsets"])) % D).astype(np.int32)
@@ -167,7 +167,7 @@ def _interleaved(P, D, eta):
     return P
 
 
-@pytest.mark.parametrize("D", [3, 5, 8])
+@pytest.mark.parametrize("D", [3, 5, 8, 12, 16])
 def test_one_iteration_many_copies(D):
     say("one iteration, interleaved subdomains", D)
     eta = 0.3

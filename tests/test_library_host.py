@@ -30,7 +30,8 @@ def test_library_exports_every_declared_symbol():
 
 def _specs():
     s = [synthetic.CONFIGS[k] for k in ("c1", "c2", "c5")]
-    s += synthetic.batch_specs(64)[:6]
+    b = synthetic.batch_specs(64)
+    s += b[:6] + [b[7], b[14], b[26]]     # 7 and 26: 16 copies of some pixels; 14: 9
     s.append(synthetic.ProblemSpec("paper256", n=256, sigma=4, p=64, radius=24, quad=0.02, step=8,
                                    jitter=0, dy=1, dx=2, peak=None, iters=1, seed=0))
     s.append(synthetic.ProblemSpec("narrow", n=200, sigma=4, p=32, radius=12, quad=0.02, step=6,
@@ -55,6 +56,22 @@ def test_geometry_bit_exact_against_oracle(spec):
     areas = [(rc[2] - rc[0]) * (rc[3] - rc[1]) for (_, _, rc) in og.pairs]
     assert plan.info.n_lam == 2 * sum(areas)
     assert plan.info.p_sub == int(sizes.sum())
+
+
+def test_every_batch_draw_plans_as_drawn():
+    """Config 4's 64 draws keep their g x g grids (capped only where the scan has fewer
+    positions than blocks); every one makes a plan, whose largest cover, up to 16
+    subdomains over a pixel, is the oracle's."""
+    covers = []
+    for spec in synthetic.batch_specs(64):
+        pr = synthetic.draw_problem(spec)
+        ky, kx = pr["grid"]
+        assert 2 <= spec.dy <= 6 or spec.dy == ky, spec
+        og = build_geometry(spec.n, spec.n, spec.p, pr["offsets"], pr["frame_sub"])
+        plan = odp.Plan(spec.n, spec.n, spec.p, pr["offsets"], pr["frame_sub"], r=1.0)
+        assert plan.info.max_cover == int(cover_count(og).max()) <= 16
+        covers.append(plan.info.max_cover)
+    assert max(covers) == 16 and sum(c > 8 for c in covers) >= 9
 
 
 def test_c2_and_c5_pair_counts():
