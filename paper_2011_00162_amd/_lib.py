@@ -22,6 +22,7 @@ EXPORTS = [
     "odp_plan_get_rects", "odp_plan_get_pairs", "odp_plan_get_cover", "odp_plan_bind",
     "odp_plan_illum_max", "odp_plan_set_params", "odp_forward", "odp_adjoint", "odp_prox_stagm",
     "odp_state_init", "odp_admm_iterate", "odp_frame_sweep", "odp_probe_update", "odp_blind_initial_probe",
+    "odp_blind_initial_probe_static",
     "odp_pixel_update", "odp_merge", "odp_amp_loss", "odp_last_error", "odp_version",
     "odp_batch_plan_create", "odp_batch_get_entry", "odp_batch_set_penalties", "odp_plan_get_tuning",
     "odp_plan_set_tuning", "odp_plan_autotune", "odp_graph_create", "odp_graph_launch", "odp_graph_destroy",
@@ -105,6 +106,7 @@ def lib() -> C.CDLL:
         "odp_plan_set_sweep_events": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), i32, i32]),
         "odp_probe_update": (C.c_int, [vp, vp, vp]),
         "odp_blind_initial_probe": (C.c_int, [vp, vp, vp]),
+        "odp_blind_initial_probe_static": (C.c_int, [vp, i32, i32, vp, vp]),
         "odp_pixel_update": (C.c_int, [vp, vp, vp, vp]),
         "odp_merge": (C.c_int, [vp, vp, vp, vp]),
         "odp_amp_loss": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),

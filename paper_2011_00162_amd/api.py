@@ -48,6 +48,21 @@ def prox_stagm(y: torch.Tensor, sqrt_f: torch.Tensor, eps: float, lam: float,
     return z
 
 
+def blind_initial_probe_static(sqrt_f: torch.Tensor, out: torch.Tensor | None = None,
+                               stream=None) -> torch.Tensor:
+    """w0 = (1/J) sum_j F*(sqrt f_j) from amplitudes [J, p, p] without a plan
+    (odp_blind_initial_probe_static: no workspace, the library's static scratch)."""
+    if sqrt_f.dtype != torch.float32 or sqrt_f.dim() != 3 or sqrt_f.shape[1] != sqrt_f.shape[2]:
+        raise ValueError("sqrt_f must be float32 [J, p, p]")
+    if not sqrt_f.is_contiguous():
+        raise ValueError("sqrt_f must be contiguous")
+    J, p = int(sqrt_f.shape[0]), int(sqrt_f.shape[1])
+    out = torch.empty((p, p), dtype=torch.complex64, device=sqrt_f.device) if out is None else out
+    _c64(out, (p, p))
+    check(lib().odp_blind_initial_probe_static(_ptr(sqrt_f), J, p, _ptr(out), _stream(stream)))
+    return out
+
+
 @dataclass
 class Geometry:
     rects: np.ndarray      # [D,4] (r0, c0, r1, c1)

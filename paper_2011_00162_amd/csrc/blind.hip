@@ -10,6 +10,9 @@
 // so repeated runs agree bit for bit.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <mutex>
+
 #include "fft_frame.hpp"
 #include "odp_internal.hpp"
 
@@ -174,6 +177,73 @@ hipError_t launch_init_probe(const InitProbeArgs& a, hipStream_t s) {
   ODP_INIT(128)
 #undef ODP_INIT
   return hipGetLastError();
+}
+
+// ---- the initial probe with no plan and no workspace ------------------------------
+// The chunk partial sums ([n_chunks][p][p] FP64) and the twiddle table of p ([p/16][16]
+// float2) of launch_init_probe_static live in one file-scope device array.  Each device
+// holds its own copy until the process ends; every call on a device shares it and
+// leaves its contents behind (each call rewrites all it reads, so nothing needs clearing).
+static __device__ __align__(256) double scratch[STATIC_SCRATCH_DOUBLES];
+
+// tw[i][k] = exp(-2 pi i i k / p) for i < p/16, k < 16, from an FP64 sincospi
+__global__ __launch_bounds__(128) void k_twiddles(float2* tw, int p) {
+  const int t = threadIdx.x;
+  if (t >= p) return;
+  double s, c;
+  sincospi(2.0 * (double)((t / 16) * (t % 16)) / (double)p, &s, &c);
+  tw[t] = make_float2((float)c, (float)-s);
+}
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.  In host
+// code the array's name is only a stand-in for the device symbol, never an address.
+hipError_t scratch_address(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+bool static_scratch_fits(int J, int p) {
+  if (J < 1 || p < 16 || p > STATIC_MAXP) return false;
+  const int n_chunks = std::min(STATIC_CHUNKS, J);
+  return (size_t)n_chunks * p * p + (size_t)p <= STATIC_SCRATCH_DOUBLES;
+}
+
+hipError_t launch_init_probe_static(const float* sqrt_f, int J, int p, float2* w, hipStream_t s) {
+  double* base = nullptr;
+  hipError_t e = scratch_address(&base);
+  if (e != hipSuccess) return e;
+  InitProbeArgs a;
+  a.sqrt_f = sqrt_f;
+  a.J = J;
+  a.p = p;
+  // the same chunking as the plan's entry point, so both sum in the same order
+  a.n_chunks = std::min(STATIC_CHUNKS, std::max(1, J));
+  a.frames_per_chunk = (J + a.n_chunks - 1) / a.n_chunks;
+  a.n_chunks = (J + a.frames_per_chunk - 1) / a.frames_per_chunk;
+  a.part = base;
+  float2* tw = reinterpret_cast<float2*>(base + (size_t)STATIC_CHUNKS * STATIC_MAXP * STATIC_MAXP);
+  a.tw = tw;
+  a.w = w;
+  hipLaunchKernelGGL(k_twiddles, dim3(1), dim3(128), 0, s, tw, p);
+  return launch_init_probe(a, s);
 }
 
 hipError_t launch_probe_update(const ProbeArgs& a, hipStream_t s) {

@@ -229,6 +229,15 @@ struct InitProbeArgs {       // w0 = (1/J) sum_j F^{-1}(sqrt f_j) of one problem
 };
 hipError_t launch_init_probe(const InitProbeArgs& a, hipStream_t s);
 
+// The initial probe from the amplitudes alone, its scratch in a static device array:
+// at most STATIC_CHUNKS frame chunks of p x p FP64 partial sums plus the twiddle table,
+// for p <= STATIC_MAXP (4 MiB + 1 KiB per device).
+constexpr int STATIC_CHUNKS = 32;
+constexpr int STATIC_MAXP = 128;
+constexpr size_t STATIC_SCRATCH_DOUBLES = (size_t)STATIC_CHUNKS * STATIC_MAXP * STATIC_MAXP + STATIC_MAXP;
+bool static_scratch_fits(int J, int p);
+hipError_t launch_init_probe_static(const float* sqrt_f, int J, int p, float2* w, hipStream_t s);
+
 struct LossArgs {
   const float2* u;           // image [H][W]
   int32_t H, W;

@@ -1161,6 +1161,19 @@ int odp_blind_initial_probe(const odp_plan* P, odp_c32* w_out, hipStream_t s) {
   return ODP_OK;
 }
 
+int odp_blind_initial_probe_static(const float* dev_sqrt_f, int32_t J, int32_t p, odp_c32* w_out,
+                                   hipStream_t s) {
+  if (!dev_sqrt_f || !w_out) return fail(ODP_EINVAL, "null argument");
+  if (J < 1) return fail(ODP_EINVAL, "J must be at least 1");
+  if (p > STATIC_MAXP)
+    return fail(ODP_ENOMEM, "p = " + std::to_string(p) + " exceeds the static scratch (p <= " +
+                                std::to_string(STATIC_MAXP) + ")");
+  if (p != 32 && p != 64 && p != 128) return fail(ODP_EUNSUPPORTED, "p must be 32, 64 or 128");
+  if (!static_scratch_fits(J, p)) return fail(ODP_ENOMEM, "the problem exceeds the static scratch");
+  ODP_HIP(launch_init_probe_static(dev_sqrt_f, J, p, reinterpret_cast<float2*>(w_out), s));
+  return ODP_OK;
+}
+
 int odp_probe_update(odp_plan* P, void* dev_state, hipStream_t s) {
   if (!P || !dev_state) return fail(ODP_EINVAL, "null argument");
   if (!P->wsp) return fail(ODP_EINVAL, "plan is not bound");
