@@ -1,14 +1,19 @@
 #!/usr/bin/env python3
-"""Throughput of the OD2Pm ADMM frame sweep on one MI355X.
+"""Throughput of the OD2BP / OD2Pm ADMM frame sweep on one MI355X.
 
-One step = one full ADMM iteration of Algorithm 2 over the whole synthetic scan:
-the frame sweep (gather, 2-D FFT, ST-AGM prox, Gamma update, inverse FFT,
-overlap-add) followed by the pixel update (u, Lam and the consensus v).
-Workload: 512 x 512 complex image, 64 x 64 disk probe, raster step 16 with +-2 px
-jitter (29 x 29 = 841 frames), Poisson noise at peak 1e4 photons, 4 x 4 subdomains.
+One step = one full ADMM iteration over the whole synthetic scan: the frame sweep
+(gather, 2-D FFT, ST-AGM prox, Gamma update, inverse FFT, per-frame handoff), the
+probe step (blind: shared probe, probe copies, multipliers) and the pixel update
+(u, Lam and the consensus v).
+Default workload (the precision + blind-recovery configuration): 2048 x 2048 complex
+image, 128 x 128 probe recovered blind from a flat disk of radius 40, raster step 24
+(81 x 81 = 6561 frames), 8 x 8 subdomains, Poisson noise at peak 1e4 photons.  The
+512 x 512 / 841-frame workload (64 x 64 probe, 4 x 4 subdomains), where both frame
+transforms run, is reported beside it under "c2".
 Inputs are resident in HBM before the timed region starts.
 
-Prints one JSON line.  Options: --steps K --warmup W --gpus 1 (one GPU only).
+Prints one JSON line.  Options: --steps K --warmup W --gpus 1 (one GPU only);
+--workload c2|c3|c4|table1 for the other lines.
 """
 from __future__ import annotations
 
@@ -31,6 +36,7 @@ DFT_FLOPS_PER_FRAME = 4 * 4 * 3 * 2 * 64 ** 3     # per frame-iteration of the s
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_sweep_c2_pmc.md")
 PMC_SUMMARY_C5 = os.path.join(ROOT, "profiles", "k_sweep128_c5_pmc.md")
 PMC_SUMMARY_C3 = os.path.join(ROOT, "profiles", "loss_c3_pmc.md")
+C5_SUBS_CHECKED = (0, 3, 36)      # a corner, an edge and an interior subdomain of the 8 x 8 grid
 LOSS_SOURCES = ["paper_2011_00162_amd/csrc/loss.hip", "paper_2011_00162_amd/csrc/fft_frame.hpp",
                 "paper_2011_00162_amd/csrc/reduce.hpp", "paper_2011_00162_amd/csrc/odp_internal.hpp"]
 KERNEL_SOURCES = ["paper_2011_00162_amd/csrc/kernels.hip", "paper_2011_00162_amd/csrc/fft_frame.hpp",
@@ -104,31 +110,42 @@ def gpu_leg(args, torch, odp, synthetic, transform=0):
     info = plan.info
 
     plan.iterate(state, args.warmup)
-    # event pairs recorded by the sweep kernel itself at its start and end
-    # (hipExtLaunchKernelGGL on the launch stream) on every stride-th iteration of the
-    # timed region (each recording costs a few microseconds of serialisation, so about 20
-    # samples are taken); record() once here only creates the events
-    stride = max(1, args.steps // 20)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps // stride)]
-    for a, b in ev:
+    total_ms = time_iterations(torch, plan, state, args.steps)
+    sweep_avg, sweep_med = sweep_event_ms(torch, plan, state, min(args.steps, 50))
+    alg_bytes = 20.0 * J * p * p + 16.0 * info.p_sub
+    return dict(J=J, n=n, p=p, D=info.D, total_ms=total_ms, sweep_avg_ms=sweep_avg,
+                sweep_median_ms=sweep_med, alg_bytes=alg_bytes, r=r, eta=eta, eps=eps,
+                p_sub=info.p_sub, n_pairs=info.n_pairs,
+                tuning={"xcd_slice": tune.xcd_slice, "tiling": tune.tiling, "tile": [tune.tile_rows, tune.tile_cols]})
+
+
+def time_iterations(torch, plan, state, steps):
+    """GPU time of `steps` back-to-back iterations (one odp_admm_iterate call, no events
+    inside), in ms."""
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    plan.iterate(state, steps)
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1)
+
+
+def sweep_event_ms(torch, plan, state, n):
+    """Average and median duration of the frame-sweep kernel over n further iterations, from
+    event pairs the kernel itself records at its start and end on its launch stream
+    (hipExtLaunchKernelGGL through odp_plan_set_sweep_events).  A separate pass after the
+    timed region: each recording serialises the queue for a few microseconds."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for a, b in ev:          # record() once creates the events
         a.record()
         b.record()
     torch.cuda.synchronize()
-    plan.set_sweep_events(ev, stride)
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0.record()
-    plan.iterate(state, args.steps)     # the timed region: K iterations (sweep, pixel update)
-    t1.record()
+    plan.set_sweep_events(ev, 1)
+    plan.iterate(state, n)
     torch.cuda.synchronize()
-    total_ms = t0.elapsed_time(t1)
-    sweep_ms = sorted(a.elapsed_time(b) for a, b in ev)
-    sweep_avg_ms = sum(sweep_ms) / len(sweep_ms)
-    alg_bytes = 20.0 * J * p * p + 16.0 * info.p_sub
-    return dict(J=J, n=n, p=p, D=info.D, total_ms=total_ms, sweep_avg_ms=sweep_avg_ms,
-                sweep_median_ms=sweep_ms[len(sweep_ms) // 2], alg_bytes=alg_bytes, r=r, eta=eta, eps=eps,
-                p_sub=info.p_sub, n_pairs=info.n_pairs,
-                tuning={"xcd_slice": tune.xcd_slice, "tiling": tune.tiling, "tile": [tune.tile_rows, tune.tile_cols]})
+    ms = sorted(a.elapsed_time(b) for a, b in ev)
+    return sum(ms) / len(ms), ms[len(ms) // 2]
 
 
 def cpu_leg(args, torch, odp, synthetic):
@@ -186,20 +203,6 @@ def _timed(torch, fn, steps):
     b.record()
     torch.cuda.synchronize()
     return a.elapsed_time(b) / steps
-
-
-def _sweep_ms(torch, plan, state, steps, probe=False):
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    torch.cuda.synchronize()
-    for a, b in ev:
-        a.record()
-        plan.frame_sweep(state)
-        b.record()
-        if probe:
-            plan.probe_update(state)
-        plan.pixel_update(state)
-    torch.cuda.synchronize()
-    return sum(a.elapsed_time(b) for a, b in ev) / steps
 
 
 def run_c3(args, torch, odp, synthetic):
@@ -295,9 +298,32 @@ def run_c4(args, torch, odp, synthetic):
                        "grids": [s.dy for s in specs], "max_cover": max_cover}}
 
 
+C5_WORKLOAD = ("blind OD2BP, 2048x2048 image, 128x128 probe (truth: disk R=48, phase 0.01 r^2; start: flat disk "
+               "R=40), raster step 24 (81x81 = 6561 frames), 8x8 subdomains (210 pairs), Poisson peak 1e4, eps=0.5, "
+               "eta=0.1, r=0.5*eta*max(diag A*A), mu=0.5*eta*max_d J_d")
+
+
+def c5_transforms(odp):
+    """The frame transforms a p = 128 plan accepts (name, id)."""
+    out = [("fft_f32", odp.ODP_FFT_F32)]
+    if getattr(odp, "ODP_HYBRID_MFMA", None) is not None:
+        out.append(("hybrid_split_bf16_mfma", odp.ODP_HYBRID_MFMA))
+    return out
+
+
+def c5_plan(odp, spec, pr, sqrt_f, w, blind, transform=0, eta=0.1):
+    import numpy as np
+    plan = odp.Plan(spec.n, spec.n, spec.p, pr["offsets"], pr["frame_sub"], eps=0.5, eta=eta, r=1.0, mu=1.0,
+                    blind=blind, transform=transform)
+    plan.bind(sqrt_f, w)
+    mu = 0.5 * eta * max(int(np.sum(pr["frame_sub"] == d)) for d in range(plan.info.D))
+    plan.set_params(r=0.5 * eta * plan.illum_max(), mu=mu)
+    return plan
+
+
 def run_c5(args, torch, odp, synthetic):
-    """2048^2, p=128, 6561 frames, 8x8 subdomains: blind (Alg. 3) and non-blind sweeps."""
-    import math
+    """2048^2, p = 128, 6561 frames, 8 x 8 subdomains: the blind run (Alg. 3) and the same
+    scan with the probe known (Alg. 2), for every frame transform a p = 128 plan has."""
     import numpy as np
     spec = synthetic.CONFIGS["c5"]
     pr = synthetic.draw_problem(spec)
@@ -310,35 +336,117 @@ def run_c5(args, torch, odp, synthetic):
         mean_energy, spec.init_radius)
     w0 = torch.from_numpy(w0.astype("complex64")).cuda()
     w_true = torch.from_numpy(pr["w"].astype("complex64")).cuda()
-    eta = 0.1
-    out = {}
     J = len(pr["offsets"])
-    for mode in ("nonblind", "blind"):
-        blind = mode == "blind"
-        plan = odp.Plan(spec.n, spec.n, spec.p, pr["offsets"], pr["frame_sub"], eps=0.5, eta=eta, r=1.0,
-                        mu=1.0, blind=blind)
-        plan.bind(sqrt_f, w0 if blind else w_true)
-        mu = 0.5 * eta * max(int(np.sum(pr["frame_sub"] == d)) for d in range(plan.info.D))
-        plan.set_params(r=0.5 * eta * plan.illum_max(), mu=mu)
-        st = plan.new_state(w0=w0 if blind else None)
-        plan.iterate(st, args.warmup)
-        ms = _timed(torch, lambda: plan.iterate(st, 1), args.steps)
-        sweep = _sweep_ms(torch, plan, st, min(args.steps, 20), probe=blind)
-        alg = 20.0 * J * spec.p ** 2 + 16.0 * plan.info.p_sub
-        out[mode] = {"value": J / (ms / 1e3), "ms_per_step": ms, "sweep_ms": sweep,
-                     "sweep_roofline": {"bound": "hbm", "achieved": alg / (sweep / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
-                                        "unit": "GB/s", "frac": alg / (sweep / 1e3) / 1e9 / HBM_PEAK_GBS,
-                                        "traffic": measured_traffic(
-                                            PMC_SUMMARY_C5,
-                                            "traffic_bytes_per_launch" + ("_blind" if blind else ""))}}
+    out = {}
+    for tname, tr in c5_transforms(odp):
+        for mode in ("blind", "known_probe"):
+            blind = mode == "blind"
+            plan = c5_plan(odp, spec, pr, sqrt_f, w0 if blind else w_true, blind, tr)
+            scratch = plan.new_state(w0=w0 if blind else None)
+            tune = plan.autotune(scratch, iters=3)
+            plan.set_tuning(tr, tune.xcd_slice, tune.tiling)
+            del scratch
+            st = plan.new_state(w0=w0 if blind else None)
+            plan.iterate(st, args.warmup)
+            ms = time_iterations(torch, plan, st, args.steps) / args.steps
+            sweep_avg, sweep_med = sweep_event_ms(torch, plan, st, min(args.steps, 20))
+            alg = 20.0 * J * spec.p ** 2 + 16.0 * plan.info.p_sub
+            key = "traffic_bytes_per_launch" + ("_blind" if blind else "")
+            out.setdefault(tname, {})[mode] = {
+                "value": J / (ms / 1e3), "ms_per_step": ms,
+                "tuning": {"xcd_slice": tune.xcd_slice, "tile": [tune.tile_rows, tune.tile_cols]},
+                "sweep_ms": sweep_avg, "sweep_median_ms": sweep_med, "sweep_algorithmic_bytes": alg,
+                "sweep_roofline": {"bound": "hbm", "achieved": alg / (sweep_avg / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": alg / (sweep_avg / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                   "traffic": measured_traffic(PMC_SUMMARY_C5, key) if tr == 0 else None}}
+            del plan, st
+            torch.cuda.empty_cache()
+    return dict(J=J, p_sub=None, out=out)
+
+
+def c5_cpu_leg(args, torch, odp, synthetic):
+    """The FP64 oracle (single thread) on --cpu-iters-c5 full blind iterations of the same
+    workload from Step 0, from inputs it makes itself (its own forward model and the seeded
+    Poisson counts), and the GPU's error against it: after those iterations, and one
+    iteration from the GPU's next iterate against the oracle evaluated on three subdomains
+    (oracle.local)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import blind, local, operators as ops
+    from oracle.geometry import build_geometry
+    from oracle.od2p import merge, subdomain_illumination
+
+    spec = synthetic.CONFIGS["c5"]
+    pr = synthetic.draw_problem(spec)
+    w_true = pr["w"].astype(np.complex64).astype(np.complex128)
+    f0 = ops.intensities(pr["u_true"], w_true, pr["offsets"])
+    f = synthetic.poisson_counts(f0, spec.peak, pr["rng_poisson"])
+    del f0
+    sf32 = np.sqrt(f).astype(np.float32)
+    f = sf32.astype(np.float64) ** 2
+    g = build_geometry(spec.n, spec.n, spec.p, pr["offsets"], pr["frame_sub"])
+    w0 = (synthetic.make_probe(spec.p, spec.init_radius, 0.0) * synthetic.problems.blind_init_amplitude(
+        float(np.mean(np.sum(f, axis=(1, 2)))), spec.init_radius)).astype(np.complex64).astype(np.complex128)
+    eps, eta = 0.5, 0.1
+    r = 0.5 * eta * max(float(subdomain_illumination(g, w0, d).max()) for d in range(g.D))
+    mu = 0.5 * eta * max(len(fr) for fr in g.frames_of)
+    K = args.cpu_iters_c5
+    with threadpool_limits(limits=1):
+        t = time.perf_counter()
+        ost, _ = blind.od2bp_run(g, f, w0, eps, eta, r, mu, K)
+        dt = time.perf_counter() - t
+    u_or = merge(g, ost.u)
+    den = [subdomain_illumination(g, ost.w_sub[d], d) for d in range(g.D)]
+    sqrt_f = torch.from_numpy(sf32).cuda()
+    subs = list(C5_SUBS_CHECKED)
+    errs = {}
+    for tname, tr in c5_transforms(odp):
+        plan = c5_plan(odp, spec, pr, sqrt_f, torch.from_numpy(w0.astype(np.complex64)).cuda(), True, tr)
+        st = plan.new_state(w0=torch.from_numpy(w0.astype(np.complex64)).cuda())
+        plan.iterate(st, K)
+        torch.cuda.synchronize()
+        u = [t_.cpu().numpy().astype(np.complex128) for t_ in st.u_sub()]
+        e = {"iters": K,
+             "u_weighted": float(np.sqrt(sum(np.sum(dd * np.abs(a - b) ** 2) for a, b, dd in zip(u, ost.u, den))
+                                         / sum(np.sum(dd * np.abs(b) ** 2) for b, dd in zip(ost.u, den)))),
+             "merged_u": float(np.linalg.norm(plan.merge(st).cpu().numpy() - u_or) / np.linalg.norm(u_or)),
+             "w": float(np.linalg.norm(st.probe().cpu().numpy() - ost.w) / np.linalg.norm(ost.w)),
+             "w_sub": float(np.linalg.norm(st.probe_copies().cpu().numpy() - np.stack(ost.w_sub))
+                            / np.linalg.norm(np.stack(ost.w_sub)))}
+        # one iteration from the GPU's iterate K + 1, against the oracle on three subdomains
+        plan.iterate(st, 1)
+        torch.cuda.synchronize()
+        u_n = [t_.cpu().numpy().astype(np.complex128) for t_ in st.u_sub()]
+        lam_n = {k: v.cpu().numpy().astype(np.complex128) for k, v in st.lam().items()}
+        js = sorted({int(j) for d in subs for j in g.frames_of[d]})
+        G = st.gamma()[torch.tensor(js, device="cuda")].cpu().numpy().astype(np.complex128)
+        gam_n = {j: G[k] for k, j in enumerate(js)}
+        ws_n = list(st.probe_copies().cpu().numpy().astype(np.complex128))
+        dl_n = list(st.probe_multipliers().cpu().numpy().astype(np.complex128))
+        plan.iterate(st, 1)
+        torch.cuda.synchronize()
+        want = local.od2bp_step_local(g, f, u_n, lam_n, gam_n, ws_n, dl_n, eps, eta, r, mu, subs)
+        num = ref = 0.0
+        for d in subs:
+            dd = subdomain_illumination(g, want["w_sub"][d], d)
+            a = st.u_sub()[d].cpu().numpy().astype(np.complex128)
+            num += np.sum(dd * np.abs(a - want["u"][d]) ** 2)
+            ref += np.sum(dd * np.abs(want["u"][d]) ** 2)
+        Gn = st.gamma()[torch.tensor(js, device="cuda")].cpu().numpy()
+        e[f"one_iteration_from_iterate_{K + 1}"] = {
+            "subdomains": subs, "u_weighted": float(np.sqrt(num / ref)),
+            "gamma": float(np.linalg.norm(Gn - np.stack([want["gamma"][j] for j in js]))
+                           / np.linalg.norm(np.stack([want["gamma"][j] for j in js]))),
+            "w": float(np.linalg.norm(st.probe().cpu().numpy() - want["w"]) / np.linalg.norm(want["w"]))}
+        errs[tname] = e
         del plan, st
-    return {"metric": "ADMM frame-iters/s, 2048^2 / 6561 frames of 128^2, 8x8 subdomains",
-            "value": out["blind"]["value"], "unit": "frame-iters/s", "n_gpus": 1, "steps": args.steps,
-            "warmup": args.warmup, "ms_per_step": out["blind"]["ms_per_step"], "higher_is_better": True,
-            "dtype": "f32", "data": "synthetic",
-            "config": {"workload": "blind OD2BP, 2048x2048, probe 128 (init disk R=40), step 24, 8x8 subdomains, "
-                                   "Poisson 1e4"},
-            "modes": out}
+        torch.cuda.empty_cache()
+    return dict(value=g.J * K / dt, unit="frame-iters/s", cores=1, kind="oracle",
+                sample=f"{K} OD2BP iterations (Alg. 3) of the full 2048x2048 / 6561-frame blind workload from Step 0 "
+                       f"(FP64 NumPy, single thread) in {dt:.1f} s on {cpu_model()} ({os.cpu_count()} logical CPUs)",
+                rel_err_gpu_vs_oracle=errs)
+
 
 # iterations to RF <= 1e-5 that the paper reports for its stripes on its own 512^2 image
 # and zone-plate probe (Sec. 4.2(2), Table 1); context only, the data differ
@@ -434,15 +542,50 @@ def run_table1(args, torch, odp, synthetic):
             "rows": rows}
 
 
+def c2_report(args, torch, odp, synthetic):
+    """The 512 x 512 / 841-frame workload with both frame transforms (FP32 FFT and the
+    split-BF16 DFT-as-GEMM on MFMA) and, unless --no-cpu-baseline, the oracle's
+    single-thread rate and both transforms' errors against it after --cpu-iters iterations."""
+    g = gpu_leg(args, torch, odp, synthetic)
+    gd = gpu_leg(args, torch, odp, synthetic, transform=odp.ODP_DFT_SPLIT_BF16)
+    value = g["J"] * args.steps / (g["total_ms"] / 1e3)
+    achieved = g["alg_bytes"] / (g["sweep_avg_ms"] / 1e3) / 1e9
+    dft_tf = DFT_FLOPS_PER_FRAME * gd["J"] / (gd["sweep_avg_ms"] / 1e3) / 1e12
+    out = {
+        "workload": "non-blind OD2Pm, 512x512 image, 64x64 disk probe (R=24, phase 0.02 r^2), raster step 16 "
+                    "+-2 px jitter, 841 frames, Poisson peak 1e4, 4x4 subdomains (42 pairs), eps=0.5, eta=0.1, "
+                    "r=0.5*eta*max(diag A*A)",
+        "tuning": g["tuning"], "frames": g["J"], "probe": g["p"], "image": g["n"], "subdomains": g["D"],
+        "transforms": {
+            "fft_f32": {"value": value, "ms_per_step": g["total_ms"] / args.steps, "sweep_ms": g["sweep_avg_ms"],
+                        "sweep_roofline": {"bound": "hbm", "kernel": "k_sweep<64>", "achieved": achieved,
+                                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                                           "traffic": measured_traffic(),
+                                           "algorithmic_bytes_per_launch": g["alg_bytes"]}},
+            "dft_split_bf16": {"value": gd["J"] * args.steps / (gd["total_ms"] / 1e3),
+                               "ms_per_step": gd["total_ms"] / args.steps, "sweep_ms": gd["sweep_avg_ms"],
+                               # 4 complex 64^3 products per frame, each 4 real products in 3 split terms
+                               "sweep_roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": BF16_MFMA_PEAK_TFLOPS,
+                                                  "achieved": dft_tf, "frac": dft_tf / BF16_MFMA_PEAK_TFLOPS}},
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_leg(args, torch, odp, synthetic)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-iters", type=int, default=60)
+    ap.add_argument("--cpu-iters", type=int, default=60, help="oracle iterations of the 512^2 rel-error check")
+    ap.add_argument("--cpu-iters-c5", type=int, default=3, help="oracle iterations timed on the 2048^2 workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "table1"],
-                    help="c2 (default, the metric's workload); c3 loss+gradient; c4 64-problem batch; c5 blind; "
+    ap.add_argument("--no-c2", action="store_true", help="leave out the 512^2 workload (profiling runs)")
+    ap.add_argument("--workload", default="c5", choices=["c5", "c2", "c3", "c4", "table1"],
+                    help="c5 (default: 2048^2 blind, the metric's line, with the 512^2 workload beside it); "
+                         "c2 512^2 alone; c3 loss+gradient; c4 64-problem batch; "
                          "table1 iterations to RF <= 1e-5 against the number of stripes (context)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (scales the HBM counters)")
@@ -471,61 +614,53 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if args.workload != "c2":
-        run = {"c3": run_c3, "c4": run_c4, "c5": run_c5, "table1": run_table1}[args.workload]
+    if args.workload in ("c3", "c4", "table1"):
+        run = {"c3": run_c3, "c4": run_c4, "table1": run_table1}[args.workload]
         print(json.dumps(run(args, torch, odp, synthetic)), flush=True)
         return 0
-    g = gpu_leg(args, torch, odp, synthetic)
-    gd = gpu_leg(args, torch, odp, synthetic, transform=odp.ODP_DFT_SPLIT_BF16)
-    ms_per_step = g["total_ms"] / args.steps
-    value = g["J"] * args.steps / (g["total_ms"] / 1e3)
-    achieved = g["alg_bytes"] / (g["sweep_avg_ms"] / 1e3) / 1e9
-    traffic = measured_traffic()
+    if args.workload == "c2":
+        c2 = c2_report(args, torch, odp, synthetic)
+        t = c2["transforms"]["fft_f32"]
+        print(json.dumps({"metric": METRIC, "value": t["value"], "unit": "frame-iters/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": t["ms_per_step"],
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                          "data": "synthetic", "config": {"workload": c2["workload"]}, "c2": c2}), flush=True)
+        return 0
+
+    c5 = run_c5(args, torch, odp, synthetic)
+    head = c5["out"]["fft_f32"]["blind"]
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["value"],
         "unit": "frame-iters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {
-            "workload": "non-blind OD2Pm, 512x512 image, 64x64 disk probe (R=24, phase 0.02 r^2), raster step 16 "
-                        "+-2 px jitter, 841 frames, Poisson peak 1e4, 4x4 subdomains, eps=0.5, eta=0.1, "
-                        "r=0.5*eta*max(diag A*A)",
-            "transform": "fft_f32", "tuning": g["tuning"],
-            "frames": g["J"], "probe": g["p"], "image": g["n"], "subdomains": g["D"], "pairs": g["n_pairs"],
-        },
-        "transforms": {
-            "fft_f32": {"value": value, "ms_per_step": ms_per_step, "sweep_ms": g["sweep_avg_ms"]},
-            "dft_split_bf16": {
-                "value": gd["J"] * args.steps / (gd["total_ms"] / 1e3),
-                "ms_per_step": gd["total_ms"] / args.steps, "sweep_ms": gd["sweep_avg_ms"],
-                # 4 complex 64^3 products per frame, each 4 real products in 3 split terms
-                "sweep_roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": BF16_MFMA_PEAK_TFLOPS,
-                                   "achieved": DFT_FLOPS_PER_FRAME * gd["J"] / (gd["sweep_avg_ms"] / 1e3) / 1e12,
-                                   "frac": DFT_FLOPS_PER_FRAME * gd["J"] / (gd["sweep_avg_ms"] / 1e3) / 1e12
-                                   / BF16_MFMA_PEAK_TFLOPS}},
-        },
+        "config": {"workload": C5_WORKLOAD, "mode": "blind", "transform": "fft_f32", "frames": c5["J"],
+                   "probe": 128, "image": 2048, "subdomains": 64, "pairs": 210},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_sweep<64> (frame sweep)",
-            "achieved": achieved,
+            "kernel": "k_sweep128<true, 0> (blind frame sweep)",
+            "achieved": head["sweep_roofline"]["achieved"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": g["alg_bytes"],
-            "avg_launch_ms": g["sweep_avg_ms"],
+            "frac": head["sweep_roofline"]["frac"],
+            "traffic": head["sweep_roofline"]["traffic"],
+            "algorithmic_bytes_per_launch": head["sweep_algorithmic_bytes"],
+            "avg_launch_ms": head["sweep_ms"],
         },
+        "transforms": c5["out"],
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_leg(args, torch, odp, synthetic)
+        out["cpu_baseline"] = c5_cpu_leg(args, torch, odp, synthetic)
+    if not args.no_c2:
+        out["c2"] = c2_report(args, torch, odp, synthetic)
     print(json.dumps(out), flush=True)
     return 0
 

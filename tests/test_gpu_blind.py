@@ -8,7 +8,10 @@ import torch
 
 import synthetic
 from oracle import blind
-from tests.gpu_util import dev_c64, gpu_plan, host, rel, rel_list, rounded_inputs
+from oracle import operators as ops
+from oracle.od2p import subdomain_illumination
+from tests.gpu_util import (dev_c64, elem_err, gamma_elem_err, gpu_plan, host, oracle_to_state, rel,
+                            rel_list, rounded_inputs, u_elem_err, u_weighted_rel, u_weights)
 from tests.oracle_problems import oracle_problem, tiny_spec
 
 pytestmark = pytest.mark.gpu
@@ -32,14 +35,44 @@ def _blind_setup(spec, mu_scale=0.5, gamma=0.0, mask=None):
     return P, f, g, w0, mu, plan, st
 
 
-def _compare(st, ost, tol):
-    e_u = rel_list([host(t) for t in st.u_sub()], ost.u)
-    e_w = rel(host(st.probe()), ost.w)
-    e_ws = rel(host(st.probe_copies()), np.stack(ost.w_sub))
-    e_g = rel(host(st.gamma()), ost.gamma)
-    dl = np.stack(ost.delta)
-    e_d = rel(host(st.probe_multipliers()), dl) / 50 if np.linalg.norm(dl) > 0 else 0.0  # small differences
-    errs = dict(u=e_u, w=e_w, w_sub=e_ws, gamma=e_g, delta_over_50=e_d)
+def _y(g, st):
+    """y_j = Gamma_j^n + F(w_d^n o S_j u_d^n), the prox argument of Alg. 3 Step 1 (eq. blind_Z)."""
+    from oracle.od2p import local_offsets
+    X = np.empty_like(st.gamma)
+    for d in range(g.D):
+        X[g.frames_of[d]] = ops.forward(st.u[d], st.w_sub[d], local_offsets(g, d))
+    return st.gamma + X
+
+
+def _compare(st, ost, tol, P=None, f=None, y=None, gamma_p=0.0):
+    """Norm errors of the blind state: u in the illumination-weighted norm ||A_d du|| /
+    ||A_d u|| (the U-step divides by the new copy's illumination, eq. blind_U), and in the
+    plain norm where every pixel is lit; Delta^{n+1} = Delta^n + w_d - w (eq. admm_Delta)
+    at the scale of its operands ||Delta|| + ||w_d||.  With y given (one iteration), also
+    element by element: Gamma with the prox's conditioning, u through the U-step's
+    numerator, Delta at its operands' scale."""
+    g = P["geom"] if P is not None else None
+    got_u = [host(t) for t in st.u_sub()]
+    dl, ws = np.stack(ost.delta), np.stack(ost.w_sub)
+    errs = dict(w=rel(host(st.probe()), ost.w), w_sub=rel(host(st.probe_copies()), ws),
+                gamma=rel(host(st.gamma()), ost.gamma),
+                delta=float(np.linalg.norm(host(st.probe_multipliers()) - dl)
+                            / (np.linalg.norm(dl) + np.linalg.norm(ws))))
+    if g is not None:
+        den = [subdomain_illumination(g, ost.w_sub[d], d) for d in range(g.D)]
+        errs["u_weighted"] = u_weighted_rel(got_u, ost.u, den)
+        if all(np.all(a > 0) for a in den):
+            errs["u"] = rel_list(got_u, ost.u)
+        if y is not None:
+            wts = u_weights(g, lambda d: ost.w_sub[d], P["eta"], P["r"], gamma_p)
+            errs["u_elem"] = u_elem_err(got_u, ost.u, wts)
+            errs["gamma_elem"] = gamma_elem_err(host(st.gamma()), ost.gamma, y, np.sqrt(f), P["eps"], P["eta"])
+            # w_d and Delta come from inverse transforms of the frames (eq. blind_W): rms floor
+            errs["w_sub_elem"] = elem_err(host(st.probe_copies()), ws, np.abs(ws), floor="rms")
+            errs["delta_elem"] = elem_err(host(st.probe_multipliers()), dl, np.abs(dl) + np.abs(ws), floor="rms")
+    else:
+        errs["u"] = rel_list(got_u, ost.u)
+    say("blind errors", errs)
     assert max(errs.values()) <= tol, errs
 
 
@@ -49,12 +82,13 @@ def test_blind_iterations_parity(gamma):
     say("blind parity gamma", gamma)
     P, f, g, w0, mu, plan, st = _blind_setup(spec, gamma=gamma)
     stats = host(plan.iterate(st, 1, stats=True))
+    y = _y(g, blind.init_state(g, w0))
     ost, hist = blind.od2bp_run(g, f, w0, P["eps"], P["eta"], P["r"], mu, 1, gamma_p=gamma)
-    _compare(st, ost, 1e-5)
+    _compare(st, ost, 1e-5, P, f, y, gamma)
     assert abs(stats[0, 0] - hist[0]["RF"]) <= 1e-5 * hist[0]["RF"]
     plan.iterate(st, 9)
     ost, _ = blind.od2bp_run(g, f, w0, P["eps"], P["eta"], P["r"], mu, 9, gamma_p=gamma, state=ost)
-    _compare(st, ost, 1e-3)   # K-iteration reconstruction bound
+    _compare(st, ost, 1e-3, P)   # K-iteration reconstruction bound
 
 
 def test_blind_with_support_mask():
@@ -64,11 +98,12 @@ def test_blind_with_support_mask():
     mask = ((k[:, None] ** 2 + k[None, :] ** 2) <= 10 ** 2).astype(np.uint8)
     P, f, g, w0, mu, plan, st = _blind_setup(spec, mask=mask)
     plan.iterate(st, 1)
+    y = _y(g, blind.init_state(g, w0))
     ost, _ = blind.od2bp_run(g, f, w0, P["eps"], P["eta"], P["r"], mu, 1, mask=mask)
-    _compare(st, ost, 1e-5)
+    _compare(st, ost, 1e-5, P, f, y)
     plan.iterate(st, 2)
     ost, _ = blind.od2bp_run(g, f, w0, P["eps"], P["eta"], P["r"], mu, 2, mask=mask, state=ost)
-    _compare(st, ost, 1e-3)   # K-iteration reconstruction bound
+    _compare(st, ost, 1e-3, P)   # K-iteration reconstruction bound
     # the shared probe's spectrum vanishes off the support
     spec_w = np.fft.fft2(host(st.probe()), norm="ortho")
     assert np.abs(spec_w[mask == 0]).max() <= 1e-5 * np.abs(spec_w).max()
@@ -80,40 +115,61 @@ def test_blind_p64_single_run():
     P, f, g, w0, mu, plan, st = _blind_setup(spec)
     plan.iterate(st, 5)
     ost, _ = blind.od2bp_run(g, f, w0, P["eps"], P["eta"], P["r"], mu, 5)
-    _compare(st, ost, 1e-3)   # K-iteration reconstruction bound
+    _compare(st, ost, 1e-3, P)   # K-iteration reconstruction bound
+
+
+def _rounded(ost):
+    """The oracle state rounded to complex64, as it is loaded into the GPU state."""
+    c = ost.copy()
+    r = lambda x: x.astype(np.complex64).astype(np.complex128)
+    c.u = [r(a) for a in c.u]
+    c.gamma = r(c.gamma)
+    c.lam = {k: r(v) for k, v in c.lam.items()}
+    c.w, c.w_sub, c.delta = r(c.w), [r(a) for a in c.w_sub], [r(a) for a in c.delta]
+    return c
+
+
+def _load(ost, st):
+    oracle_to_state(ost, st)
+    st.probe().copy_(torch.from_numpy(ost.w.astype(np.complex64)))
+    st.probe_copies().copy_(torch.from_numpy(np.stack(ost.w_sub).astype(np.complex64)))
+    st.probe_multipliers().copy_(torch.from_numpy(np.stack(ost.delta).astype(np.complex64)))
+    torch.cuda.synchronize()
 
 
 def test_blind_p128_parity():
-    """p = 128 (the blind workload's probe size).  The U-step divides by the probe copy's
-    illumination; with a disk probe the frame corners light some pixels at 1e-6 of the
-    maximum, where the division amplifies rounding differences without bound, so u is
-    compared on the pixels lit at >= 1e-3 of the maximum (all of them in the p = 32
-    test above).  Gamma = y - Prox(y) is a difference of nearly equal spectra at p = 128
-    (relative cancellation of about 1e-4 in FP32), so it gets the K-iteration bound."""
-    from oracle.od2p import subdomain_illumination
+    """p = 128 (the blind workload's probe size).
+
+    Step 0 -> 1: the flat initial disk's spectrum F(w0) has near-zeros (its Airy rings);
+    about 4 % of the frequencies lie near 1e-7 of the spectrum's maximum, below what an
+    FP32 transform resolves, and there Gamma^1 = (|y| - sqrt f) sign(y) / (1 + eta) takes
+    its phase from sign(y): numerically a tie.  Gamma is therefore compared element by
+    element with the prox's conditioning (tests.gpu_util.gamma_elem_err), and u, the
+    probe copies and Delta, which inherit the tie's resolution, only after K iterations.
+    One iteration from an advanced state (the oracle's third iterate, loaded into the GPU
+    state) has no such ties and is held to the operator bound on every output."""
     spec = tiny_spec(n=256, p=128, step=16, jitter=2, dy=2, dx=2, radius=48, peak=1e4)
     say("blind p128")
     P, f, g, w0, mu, plan, st = _blind_setup(spec)
-    lit = [subdomain_illumination(g, w0, d) for d in range(g.D)]
-    lit = [a >= 1e-3 * a.max() for a in lit]
-
-    def check(ost, tol_u):
-        got = [host(t) for t in st.u_sub()]
-        num = sum(np.sum(np.abs(got[d][lit[d]] - ost.u[d][lit[d]]) ** 2) for d in range(g.D))
-        den = sum(np.sum(np.abs(ost.u[d][lit[d]]) ** 2) for d in range(g.D))
-        errs = dict(u_lit=float(np.sqrt(num / den)), w=rel(host(st.probe()), ost.w),
-                    w_sub=rel(host(st.probe_copies()), np.stack(ost.w_sub)), gamma=rel(host(st.gamma()), ost.gamma))
-        say("blind p128 errors", errs)
-        assert errs["u_lit"] <= tol_u, errs
-        assert max(errs["w"], errs["w_sub"], errs["gamma"]) <= 1e-3, errs
-
+    eps, eta, r = P["eps"], P["eta"], P["r"]
     stats = host(plan.iterate(st, 1, stats=True))
-    ost, hist = blind.od2bp_run(g, f, w0, P["eps"], P["eta"], P["r"], mu, 1)
-    check(ost, 1e-4)
+    ost, hist = blind.od2bp_run(g, f, w0, eps, eta, r, mu, 1)
+    y0 = _y(g, blind.init_state(g, w0))
+    e_g = gamma_elem_err(host(st.gamma()), ost.gamma, y0, np.sqrt(f), eps, eta)
+    say("step 0 -> 1: Gamma element-wise", e_g)
+    assert e_g <= 1e-5
     assert abs(stats[0, 0] - hist[0]["RF"]) <= 1e-5 * hist[0]["RF"]
     plan.iterate(st, 4)
-    ost, _ = blind.od2bp_run(g, f, w0, P["eps"], P["eta"], P["r"], mu, 4, state=ost)
-    check(ost, 1e-3)   # K-iteration reconstruction bound
+    ost, _ = blind.od2bp_run(g, f, w0, eps, eta, r, mu, 4, state=ost)
+    _compare(st, ost, 1e-3, P)   # K-iteration reconstruction bound
+    # one iteration from the oracle's third iterate
+    o3, _ = blind.od2bp_run(g, f, w0, eps, eta, r, mu, 3)
+    o3 = _rounded(o3)
+    st2 = plan.new_state(w0=dev_c64(w0))
+    _load(o3, st2)
+    plan.iterate(st2, 1)
+    o4, _ = blind.od2bp_step(g, f, o3, eps, eta, r, mu)
+    _compare(st2, o4, 1e-5, P, f, _y(g, o3))
 
 
 @pytest.mark.parametrize("n,p,step,rad", [(128, 32, 8, 12), (192, 64, 16, 24), (256, 128, 32, 48)], ids=["p32", "p64", "p128"])
