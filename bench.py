@@ -175,7 +175,8 @@ def cpu_leg(args, torch, odp, synthetic):
     u_or = merge(g, st.u)
     # the GPU path on the identical data and iteration count, both transforms
     errs = {}
-    for name, tr in (("fft_f32", odp.ODP_FFT_F32), ("dft_split_bf16", odp.ODP_DFT_SPLIT_BF16)):
+    for name, tr in (("fft_f32", odp.ODP_FFT_F32), ("dft_split_bf16", odp.ODP_DFT_SPLIT_BF16),
+                     ("hybrid_split_bf16_mfma", odp.ODP_HYBRID_MFMA)):
         plan = odp.Plan(spec.n, spec.n, spec.p, pr["offsets"], pr["frame_sub"], eps=eps, eta=eta, r=r,
                         transform=tr)
         plan.bind(torch.from_numpy(sf32).cuda(), torch.from_numpy(w.astype(np.complex64)).cuda())
@@ -548,6 +549,7 @@ def c2_report(args, torch, odp, synthetic):
     single-thread rate and both transforms' errors against it after --cpu-iters iterations."""
     g = gpu_leg(args, torch, odp, synthetic)
     gd = gpu_leg(args, torch, odp, synthetic, transform=odp.ODP_DFT_SPLIT_BF16)
+    gh = gpu_leg(args, torch, odp, synthetic, transform=odp.ODP_HYBRID_MFMA)
     value = g["J"] * args.steps / (g["total_ms"] / 1e3)
     achieved = g["alg_bytes"] / (g["sweep_avg_ms"] / 1e3) / 1e9
     dft_tf = DFT_FLOPS_PER_FRAME * gd["J"] / (gd["sweep_avg_ms"] / 1e3) / 1e12
@@ -567,6 +569,8 @@ def c2_report(args, torch, odp, synthetic):
                                # 4 complex 64^3 products per frame, each 4 real products in 3 split terms
                                "sweep_roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": BF16_MFMA_PEAK_TFLOPS,
                                                   "achieved": dft_tf, "frac": dft_tf / BF16_MFMA_PEAK_TFLOPS}},
+            "hybrid_split_bf16_mfma": {"value": gh["J"] * args.steps / (gh["total_ms"] / 1e3),
+                                       "ms_per_step": gh["total_ms"] / args.steps, "sweep_ms": gh["sweep_avg_ms"]},
         },
     }
     if not args.no_cpu_baseline:

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libodp.so")
 
 ODP_OK, ODP_EINVAL, ODP_EGEOM, ODP_EHIP, ODP_ENOMEM, ODP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-ODP_FFT_F32, ODP_DFT_SPLIT_BF16 = 0, 1
+ODP_FFT_F32, ODP_DFT_SPLIT_BF16, ODP_HYBRID_MFMA = 0, 1, 2
 ODP_STOP_NONE, ODP_STOP_RF, ODP_STOP_RE = 0, 1, 2
 ODP_BALANCE_R, ODP_BALANCE_ETA = 1, 2
 

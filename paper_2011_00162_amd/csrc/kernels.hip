@@ -7,6 +7,7 @@
 #include <hip/hip_ext.h>
 
 #include "fft_frame.hpp"
+#include "fft_mfma.hpp"
 #include "odp_internal.hpp"
 #include "prox.hpp"
 #include "reduce.hpp"
@@ -39,10 +40,12 @@ __device__ __forceinline__ int sweep_pos(int32_t chunk, int xcd_slice) {
 // Each frame's output goes to its own slot of psi, so no two workgroups write
 // the same address; the pixel update pulls the covering frames in a fixed order.
 // ---------------------------------------------------------------------------
-// ST: 0 no statistics, 1 the iteration's measures, 2 also the frame residuals
-template <int P, bool BLIND, int ST>
+// ST: 0 no statistics, 1 the iteration's measures, 2 also the frame residuals.
+// MF: radix-16 stages on the matrix cores (FrameMF, split BF16), else Frame's FP32 stages.
+template <int P, bool MF, bool BLIND, int ST>
 __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
   using F = Frame<P>;
+  using M = FrameMF<P>;    // instantiated only when MF
   constexpr bool STATS = ST > 0;
   __shared__ __align__(16) float2 lds[F::LDS];
   __shared__ __align__(16) float2 twl[F::N2 * TWL];   // stage-B twiddles, read from LDS so that no
@@ -59,16 +62,23 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
   const int col = F::a_col(t), r2 = F::a_r2(t);
   const float inv_p = 1.0f / (float)P;
 
+  // the thread's 16 spatial positions (the inverse returns its values to the same ones)
+  auto prow = [&](int e) { if constexpr (MF) return M::row(t, e); else return F::N2 * e + r2; };
+  auto pcol = [&](int e) { if constexpr (MF) return M::col(t, e); else return col; };
   float2 v[16];
 #pragma unroll
-  for (int r1 = 0; r1 < 16; ++r1) {
-    const int row = F::N2 * r1 + r2;
-    v[r1] = c_mul(a.u[fd.base + (int64_t)row * fd.pitch + col], w[row * P + col]);
+  for (int e = 0; e < 16; ++e) {
+    const int row = prow(e), c = pcol(e);
+    v[e] = c_mul(a.u[fd.base + (int64_t)row * fd.pitch + c], w[row * P + c]);
   }
-  // the stage-B twiddles go to LDS after the gather's loads are issued, so waiting for
-  // this copy overlaps their latency; visible after the first barrier of forward_bc
-  if (t < F::N2 * 16) twl[(t >> 4) * TWL + (t & 15)] = a.tw[t];
-  F::forward_a(v, lds, a.tw, t);
+  if constexpr (MF) {
+    M::forward_a(v, lds, a.mft, t);
+  } else {
+    // the stage-B twiddles go to LDS after the gather's loads are issued, so waiting for
+    // this copy overlaps their latency; visible after the first barrier of forward_bc
+    if (t < F::N2 * 16) twl[(t >> 4) * TWL + (t & 15)] = a.tw[t];
+    F::forward_a(v, lds, a.tw, t);
+  }
   // The thread's amplitudes (and, for P <= 64, multipliers) are fetched now, while
   // stages B and C run: between stages A and C the thread holds no frame data in
   // registers.  At P = 128 (1024 threads, 128 VGPRs) only the amplitudes fit.
@@ -83,7 +93,8 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
     if (PRE >= 1) spre[e] = a.sqrt_f[fbase + kr * P + kc];
     if (PRE >= 2) gpre[e] = a.gamma[fbase + kr * P + kc];
   }
-  F::template forward_bc<TWL>(v, lds, twl, t);
+  if constexpr (MF) M::forward_bc(v, lds, a.mft, t);
+  else F::template forward_bc<TWL>(v, lds, twl, t);
 
   // all 16 multipliers are read before any is written back, so the loads are in
   // flight together (the stores could otherwise alias later loads for the compiler)
@@ -123,19 +134,20 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
   }
   if (STATS) frame_stats<F::T, (ST > 1)>(a.part + NFS * (size_t)j, mis, gsum, gdel, gnrm, red);
   __syncthreads();  // stage-C reads of all threads done before inverse writes reuse LDS
-  F::template inverse<TWL>(v, lds, twl, t);
+  if constexpr (MF) M::inverse(v, lds, a.mft, t);
+  else F::template inverse<TWL>(v, lds, twl, t);
   // the inverse returns each thread's 16 points to the positions it gathered; the 16
   // probe values are read before any output is written, so they are in flight together
   if (!BLIND) {
     const float2* wo = a.w_out + woff;
     float2 wk[16];
 #pragma unroll
-    for (int r1 = 0; r1 < 16; ++r1) wk[r1] = wo[(F::N2 * r1 + r2) * P + col];
+    for (int e = 0; e < 16; ++e) wk[e] = wo[prow(e) * P + pcol(e)];
 #pragma unroll
-    for (int r1 = 0; r1 < 16; ++r1) v[r1] = c_mulc(v[r1], wk[r1]);
+    for (int e = 0; e < 16; ++e) v[e] = c_mulc(v[e], wk[e]);
   }
 #pragma unroll
-  for (int r1 = 0; r1 < 16; ++r1) a.psi[fbase + (F::N2 * r1 + r2) * P + col] = v[r1];
+  for (int e = 0; e < 16; ++e) a.psi[fbase + prow(e) * P + pcol(e)] = v[e];
 }
 
 // K1 at p = 128: the same step on the two-half transform (Half128: 512 threads,
@@ -270,18 +282,23 @@ hipError_t launch_sweep(int p, const SweepArgs& a, hipStream_t s, hipEvent_t ev0
   const bool bl = a.blind != 0;
   const int st = a.part == nullptr ? 0 : (a.frame_res && !bl ? 2 : 1);
 #define ODP_SWEEP_GO(K, T) hipExtLaunchKernelGGL(K, grid, dim3(T), 0, s, ev0, ev1, 0, a, pc)
-#define ODP_SWEEP(PP)                                                                        \
-  if (p == PP) {                                                                             \
+#define ODP_SWEEP(PP, MF)                                                                    \
+  {                                                                                          \
     constexpr int T = Frame<PP>::T;                                                          \
-    if (bl && st) ODP_SWEEP_GO((k_sweep<PP, true, 1>), T);                                   \
-    else if (bl) ODP_SWEEP_GO((k_sweep<PP, true, 0>), T);                                    \
-    else if (st == 2) ODP_SWEEP_GO((k_sweep<PP, false, 2>), T);                              \
-    else if (st) ODP_SWEEP_GO((k_sweep<PP, false, 1>), T);                                   \
-    else ODP_SWEEP_GO((k_sweep<PP, false, 0>), T);                                           \
+    if (bl && st) ODP_SWEEP_GO((k_sweep<PP, MF, true, 1>), T);                               \
+    else if (bl) ODP_SWEEP_GO((k_sweep<PP, MF, true, 0>), T);                                \
+    else if (st == 2) ODP_SWEEP_GO((k_sweep<PP, MF, false, 2>), T);                          \
+    else if (st) ODP_SWEEP_GO((k_sweep<PP, MF, false, 1>), T);                               \
+    else ODP_SWEEP_GO((k_sweep<PP, MF, false, 0>), T);                                       \
     return hipGetLastError();                                                                \
   }
-  ODP_SWEEP(32)
-  ODP_SWEEP(64)
+  if (a.mft) {   // radix-16 stages on the matrix cores (hybrid transform)
+    if (p == 64) ODP_SWEEP(64, true)
+    if (p == 128) ODP_SWEEP(128, true)
+    return hipErrorInvalidValue;
+  }
+  if (p == 32) ODP_SWEEP(32, false)
+  if (p == 64) ODP_SWEEP(64, false)
   if (p == 128) {
     constexpr int T = Half128::T;
     if (bl && st) ODP_SWEEP_GO((k_sweep128<true, 1>), T);

@@ -74,6 +74,7 @@ struct SweepArgs {
   const float2* w_out;       // the same probe, read again for the output multiply
   int w_per_sub;             // 1: w indexed by subdomain (blind)
   const float2* tw;          // twiddle table W_p^{i k}, [p/16][16]
+  const uint4* mft;          // hybrid transform: split-BF16 radix-16 matrices (fft_mfma.hpp), else null
   float2* gamma;             // [J][p][p]
   const float* sqrt_f;       // [J][p][p]
   const FrameDesc* frames;

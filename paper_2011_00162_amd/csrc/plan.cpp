@@ -122,11 +122,13 @@ struct odp_plan {
   std::vector<int> cuts_r, cuts_c;         // cell cuts
   std::vector<float2> tw;
   std::vector<uint16_t> dft;               // split-BF16 DFT matrix planes (transform = DFT)
+  std::vector<uint16_t> mft;               // split-BF16 radix-16 stage matrices (hybrid transform)
   int32_t chunk = 0;
   // workspace layout (byte offsets)
   struct {
     size_t tw, w, frames, fpos, order, sub_first, offsets, rects, usub_off, cells, tiles, waves, re_list, re_first,
-        tf_first, pull, den, rcp, fpart, tpart, stat_scratch, misc, pmax, psi, fmask, wpart, dft, prob, resid, bytes;
+        tf_first, pull, den, rcp, fpart, tpart, stat_scratch, misc, pmax, psi, fmask, wpart, dft, mft, prob, resid,
+        bytes;
   } ws{};
   struct {
     size_t u_sub, gamma, lam, w, w_sub, delta, stop, bytes;
@@ -379,6 +381,34 @@ int build_geometry(odp_plan* P) {
         P->dft[3 * pp + o] = bf16_rne((float)(im - bf16_value(ih)));
       }
   }
+  // hybrid transform (fft_mfma.hpp): for every residue q < p/16 the 16-point stage
+  // matrix M_q[k][r] = W_p^{q k} W_16^{r k} (and its conjugate transpose for the
+  // inverse), FP64 on the host, as MFMA A operands per lane l = 16 g + n0: row m = n0,
+  // element e = 2 s + c at input r = 4 g + s, part c; the real-output row holds
+  // (Re M, -Im M) and the imaginary-output row (Im M, Re M); each split hi + lo.
+  if (p == 64 || p == 128) {
+    const int nq = p / 16;
+    P->mft.assign((size_t)2 * nq * 64 * 4 * 8, 0);
+    for (int dir = 0; dir < 2; ++dir)
+      for (int q = 0; q < nq; ++q)
+        for (int l = 0; l < 64; ++l) {
+          const int g = l >> 4, m = l & 15;
+          for (int e = 0; e < 8; ++e) {
+            const int r = 4 * g + (e >> 1), c = e & 1;
+            // forward M[m][r]; inverse M^H[m][r] = conj(M[r][m])
+            const int kk = dir == 0 ? m : r, rr = dir == 0 ? r : m;
+            const double a = -2.0 * M_PI * ((double)(q * kk) / (double)p + (double)((rr * kk) % 16) / 16.0);
+            const double mr = std::cos(a), mi = dir == 0 ? std::sin(a) : -std::sin(a);
+            const double vre = c == 0 ? mr : -mi, vim = c == 0 ? mi : mr;
+            const size_t o = (((size_t)(dir * nq + q) * 64 + l) * 4) * 8 + e;
+            const uint16_t h0 = bf16_rne((float)vre), h1 = bf16_rne((float)vim);
+            P->mft[o] = h0;
+            P->mft[o + 8] = bf16_rne((float)(vre - bf16_value(h0)));
+            P->mft[o + 16] = h1;
+            P->mft[o + 24] = bf16_rne((float)(vim - bf16_value(h1)));
+          }
+        }
+  }
   return ODP_OK;
 }
 
@@ -425,6 +455,7 @@ void layout(odp_plan* P) {
   P->ws.fmask = take(sizeof(float) * pp);
   P->ws.wpart = take(sizeof(double) * 2 * pp * LOSS_CHUNKS);
   P->ws.dft = take(sizeof(uint16_t) * P->dft.size() + 16);
+  P->ws.mft = take(sizeof(uint16_t) * P->mft.size() + 16);
   P->ws.prob = take(sizeof(int32_t) * 4 * P->n_probes());
   P->ws.resid = take(sizeof(double) * NRES * P->n_probes());
   P->ws.bytes = o;
@@ -619,17 +650,26 @@ extern "C" {
 const char* odp_last_error(void) { return g_err.c_str(); }
 const char* odp_version(void) { return "odp 0.1 (gfx950)"; }
 
+// The frame transforms a plan of probe size p can run.
+static int check_transform(int32_t transform, int p) {
+  if (transform != ODP_FFT_F32 && transform != ODP_DFT_SPLIT_BF16 && transform != ODP_HYBRID_MFMA)
+    return fail(ODP_EINVAL, "unknown transform");
+  if (transform == ODP_DFT_SPLIT_BF16 && p != 64)
+    return fail(ODP_EUNSUPPORTED, "the split-BF16 DFT transform is built for p = 64");
+  if (transform == ODP_HYBRID_MFMA && p != 64 && p != 128)
+    return fail(ODP_EUNSUPPORTED, "the hybrid MFMA transform is built for p = 64 and 128");
+  return ODP_OK;
+}
+
 static int validate_problem(const odp_problem* prob) {
   if (prob->p != 32 && prob->p != 64 && prob->p != 128)
     return fail(ODP_EUNSUPPORTED, "p must be 32, 64 or 128");
   if (prob->H < prob->p || prob->W < prob->p) return fail(ODP_EINVAL, "image smaller than the probe");
   if (prob->J < 1 || !prob->offsets || !prob->frame_sub) return fail(ODP_EINVAL, "no frames");
   if (prob->D < 1) return fail(ODP_EINVAL, "D must be >= 1");
-  if (prob->transform != ODP_FFT_F32 && prob->transform != ODP_DFT_SPLIT_BF16)
-    return fail(ODP_EINVAL, "unknown transform");
-  if (prob->transform == ODP_DFT_SPLIT_BF16 && prob->p != 64)
-    return fail(ODP_EUNSUPPORTED, "the split-BF16 DFT transform is built for p = 64");
-  int rc = check_params(prob->eps, prob->eta, prob->r, prob->mu, prob->gamma, prob->D, prob->blind);
+  int rc = check_transform(prob->transform, prob->p);
+  if (rc) return rc;
+  rc = check_params(prob->eps, prob->eta, prob->r, prob->mu, prob->gamma, prob->D, prob->blind);
   if (rc) return rc;
   if ((int64_t)prob->H * prob->W >= (int64_t)1 << 31) return fail(ODP_EUNSUPPORTED, "image too large");
   for (int j = 0; j < prob->J; ++j) {
@@ -851,6 +891,7 @@ int odp_plan_bind(odp_plan* P, void* dev_ws, const float* dev_sqrt_f, const odp_
   if (rc) return rc;
   if (!P->fmask.empty()) ODP_HIP(up(P->ws.fmask, P->fmask.data(), sizeof(float) * pp));
   if (!P->dft.empty()) ODP_HIP(up(P->ws.dft, P->dft.data(), sizeof(uint16_t) * P->dft.size()));
+  if (!P->mft.empty()) ODP_HIP(up(P->ws.mft, P->mft.data(), sizeof(uint16_t) * P->mft.size()));
   std::vector<int32_t> prob;
   for (const odp_plan::Entry& e : P->batch) prob.insert(prob.end(), {e.J0, e.J, e.D0, e.D});
   ODP_HIP(up(P->ws.prob, prob.data(), sizeof(int32_t) * prob.size()));
@@ -962,6 +1003,7 @@ static SweepArgs sweep_args(const odp_plan* P, char* b, double* stats) {
   a.w_out = a.w;
   a.w_per_sub = P->blind;
   a.tw = P->W_<float2>(P->ws.tw);
+  a.mft = P->transform == ODP_HYBRID_MFMA ? P->W_<uint4>(P->ws.mft) : nullptr;
   a.gamma = reinterpret_cast<float2*>(b + P->st.gamma);
   a.sqrt_f = P->sqrt_f;
   a.frames = P->W_<FrameDesc>(P->ws.frames);
@@ -1362,9 +1404,8 @@ int odp_plan_get_tuning(const odp_plan* P, odp_tuning* o) {
 
 int odp_plan_set_tuning(odp_plan* P, int32_t transform, int32_t xcd_slice, int32_t tiling, hipStream_t s) {
   if (!P) return fail(ODP_EINVAL, "null argument");
-  if (transform != ODP_FFT_F32 && transform != ODP_DFT_SPLIT_BF16) return fail(ODP_EINVAL, "unknown transform");
-  if (transform == ODP_DFT_SPLIT_BF16 && P->p != 64)
-    return fail(ODP_EUNSUPPORTED, "the split-BF16 DFT transform is built for p = 64");
+  const int rc = check_transform(transform, P->p);
+  if (rc) return rc;
   if (tiling < 0 || tiling > 2) return fail(ODP_EINVAL, "tiling must be 0, 1 or 2");
   if (xcd_slice < 0 || xcd_slice > 2) return fail(ODP_EINVAL, "xcd_slice must be 0, 1 or 2");
   if (transform != P->transform || xcd_slice != P->xcd_slice || tiling != P->ts) ++P->gen;
@@ -1381,7 +1422,8 @@ int odp_plan_autotune(odp_plan* P, void* dev_scratch_state, int32_t iters, hipSt
   if (!P->wsp) return fail(ODP_EINVAL, "plan is not bound");
   if (iters < 1) iters = 1;
   std::vector<int> transforms = {P->transform};
-  if (P->p == 64) transforms = {ODP_FFT_F32, ODP_DFT_SPLIT_BF16};
+  if (P->p == 64) transforms = {ODP_FFT_F32, ODP_DFT_SPLIT_BF16, ODP_HYBRID_MFMA};
+  if (P->p == 128) transforms = {ODP_FFT_F32, ODP_HYBRID_MFMA};
   hipEvent_t e0, e1;
   ODP_HIP(hipEventCreate(&e0));
   ODP_HIP(hipEventCreate(&e1));

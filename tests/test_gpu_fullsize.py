@@ -139,17 +139,19 @@ def test_c5_full_size_one_iteration(blind, c5_inputs):
     assert max(e.values()) <= 1e-5, e       # one iteration: the operator bound
 
 
-def test_c4_full_batch_one_problem_per_probe_size():
-    say("full 64-problem batch")
+@pytest.fixture(scope="module")
+def c4_batch():
+    """The 64-problem batch as the benchmark runs it: one batch plan per probe size,
+    bound, per-problem penalties, autotuned.  Returns [(plan, [(spec, pr, w, sqrt_f)])]."""
     specs = synthetic.batch_specs(64)
     eta = 0.1
     groups = {}
-    for k, s in enumerate(specs):
-        groups.setdefault(s.p, []).append((k, s))
-    plans, states, picks = [], [], []
+    for s in specs:
+        groups.setdefault(s.p, []).append(s)
+    out = []
     for p, group in sorted(groups.items()):
         probs, sfs, ws, data = [], [], [], []
-        for k, s in group:
+        for s in group:
             pr = synthetic.draw_problem(s)
             w = pr["w"].astype(np.complex64).astype(np.complex128)
             sf = _intensities(s, pr, w)
@@ -165,8 +167,17 @@ def test_c4_full_batch_one_problem_per_probe_size():
         t = plan.autotune(scratch, iters=3)
         say("batch p", p, "problems", len(group), "tuning", t.transform, t.xcd_slice, t.tiling)
         del scratch
+        out.append((plan, data))
+    return out
+
+
+def test_c4_full_batch_one_problem_per_probe_size(c4_batch):
+    say("full 64-problem batch")
+    eta = 0.1
+    plans, states, picks = [], [], []
+    for plan, data in c4_batch:
         # the problem with the most subdomains of this probe size
-        i = max(range(len(group)), key=lambda q: plan.entry(q).D)
+        i = max(range(len(data)), key=lambda q: plan.entry(q).D)
         picks.append((plan, i, data[i]))
         plans.append(plan)
         states.append(plan.new_state())
@@ -184,3 +195,38 @@ def test_c4_full_batch_one_problem_per_probe_size():
         err = _compare(st, want, g, D0=e.D0, J0=e.J0)
         say("batch p", s.p, "problem", i, "n", s.n, "D", g.D, "errors", err)
         assert max(err.values()) <= 1e-5, err
+
+
+def test_c4_batch_100_iterations_smallest_problems(c4_batch):
+    """K = 100 iterations of the whole batch in one graph (the configuration's iteration
+    count); the merged image of the smallest problem of each probe size against the FP64
+    oracle's 100 iterations of that problem alone.  Bound max(1e-3, 2 s_100) on the Poisson
+    data, s_100 the oracle's own distance after 100 iterations between runs whose sqrt(f)
+    differs by half a float32 ulp (the larger of two seeds; the reading of the K-iteration
+    bound used for the 512^2 workload)."""
+    from oracle.od2p import merge, od2pm_run
+    K, eta = 100, 0.1
+    plans = [plan for plan, _ in c4_batch]
+    states = [plan.new_state() for plan in plans]
+    odp.Graph(plans, states, K).launch()
+    torch.cuda.synchronize()
+    for (plan, data), st in zip(c4_batch, states):
+        i = min(range(len(data)), key=lambda q: (plan.entry(q).J, q))
+        s, pr, w, sf = data[i]
+        e = plan.entry(i)
+        g = build_geometry(s.n, s.n, s.p, pr["offsets"], pr["frame_sub"])
+        img = host(plan.merge(st))[e.row0:e.row0 + e.H, e.col0:e.col0 + e.W]
+        f = sf.astype(np.float64) ** 2
+        ost, _ = od2pm_run(g, w, f, 0.5, eta, e.r, K)
+        want = merge(g, ost.u)
+        sens = 0.0
+        for seed in (7, 8):
+            unit = np.random.default_rng(seed).uniform(-1.0, 1.0, sf.shape)
+            fp = (sf.astype(np.float64) * (1.0 + 2.0 ** -24 * unit)) ** 2
+            op, _ = od2pm_run(g, w, fp, 0.5, eta, e.r, K)
+            sens = max(sens, rel(merge(g, op.u), want))
+        err = rel(img, want)
+        bound = max(1e-3, 2.0 * sens)
+        say("batch p", s.p, "smallest problem", i, "J", e.J, "D", e.D, "n", s.n, f"K={K} err {err:.3e} "
+            f"s_K {sens:.3e} bound {bound:.1e}")
+        assert err <= bound, (err, bound)
