@@ -264,9 +264,10 @@ def run_c4(args, torch, odp, synthetic):
         plan.set_penalties([0.5 * eta * plan.entry(i).illum_max for i in range(len(group))])
         scratch = plan.new_state()
         t = plan.autotune(scratch, iters=3)
-        # both frame transforms at the tuned order and tiling (the DFT path exists for p = 64)
+        # every frame transform at the tuned order and tiling (the DFT path exists for p = 64)
         per_transform = {}
-        for name, tr in (("fft_f32", odp.ODP_FFT_F32), ("dft_split_bf16", odp.ODP_DFT_SPLIT_BF16)):
+        for name, tr in (("fft_f32", odp.ODP_FFT_F32), ("dft_split_bf16", odp.ODP_DFT_SPLIT_BF16),
+                         ("hybrid_split_bf16_mfma", odp.ODP_HYBRID_MFMA)):
             if tr == odp.ODP_DFT_SPLIT_BF16 and p != 64:
                 continue
             plan.set_tuning(tr, t.xcd_slice, t.tiling)

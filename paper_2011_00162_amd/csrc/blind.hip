@@ -74,8 +74,10 @@ __global__ __launch_bounds__(Frame<P>::T) void k_probe_project(ProbeArgs a) {
 }
 
 // w_d and Delta_d for 256 probe pixels of subdomain d, one per thread: the sums run over
-// the frames of d in ascending order, eight frames' loads in flight per step, so that a
-// workgroup reads 2 KB contiguous of each frame's phi and of its u window rows.
+// the frames of d in ascending order in groups of eight, so that a workgroup reads 2 KB
+// contiguous of each frame's phi and of its u window rows.  The next group's loads are
+// issued before the current group is summed (two groups in registers), which keeps the
+// loads in flight while the FP64 sums run.
 __global__ __launch_bounds__(256) void k_probe_copies(ProbeArgs a) {
   if (a.stop && a.stop[0].stopped) return;  // uniform over the workgroup
   constexpr int B = 8;
@@ -91,20 +93,30 @@ __global__ __launch_bounds__(256) void k_probe_copies(ProbeArgs a) {
     ni += (double)pu.x * ph.y - (double)pu.y * ph.x;
     den += (double)pu.x * pu.x + (double)pu.y * pu.y;
   };
-  const int q1 = a.sub_first[d + 1];
-  int q = a.sub_first[d];
-  for (; q + B <= q1; q += B) {
-    FrameDesc f[B];
-#pragma unroll
-    for (int i = 0; i < B; ++i) f[i] = a.fpos[q + i];   // workgroup-uniform: scalar loads
-    float2 pu[B], ph[B];
+  // the loads of frames q .. q + B - 1 (workgroup-uniform descriptors: scalar loads)
+  auto load = [&](int q, float2* pu, float2* ph) {
 #pragma unroll
     for (int i = 0; i < B; ++i) {
-      pu[i] = a.u[f[i].base + (int64_t)ky * f[i].pitch + kx];
-      ph[i] = a.phi[(size_t)f[i].j * pp + kk];
+      const FrameDesc f = a.fpos[q + i];
+      pu[i] = a.u[f.base + (int64_t)ky * f.pitch + kx];
+      ph[i] = a.phi[(size_t)f.j * pp + kk];
     }
+  };
+  const int q1 = a.sub_first[d + 1];
+  int q = a.sub_first[d];
+  float2 pu[2][B], ph[2][B];
+  if (q + B <= q1) load(q, pu[0], ph[0]);
+  for (; q + B <= q1; q += 2 * B) {
+    if (q + 2 * B <= q1) load(q + B, pu[1], ph[1]);
 #pragma unroll
-    for (int i = 0; i < B; ++i) acc(pu[i], ph[i]);
+    for (int i = 0; i < B; ++i) acc(pu[0][i], ph[0][i]);
+    if (q + 2 * B > q1) {
+      q += B;
+      break;
+    }
+    if (q + 3 * B <= q1) load(q + 2 * B, pu[0], ph[0]);
+#pragma unroll
+    for (int i = 0; i < B; ++i) acc(pu[1][i], ph[1][i]);
   }
   for (; q < q1; ++q) {
     const FrameDesc fd = a.fpos[q];

@@ -44,8 +44,11 @@ struct Tab {
   bf16x8 rh, rl, ih, il;
 };
 
-// Table layout (uint4 = 8 bf16): [dir (0 forward, 1 inverse)][q < N2][lane < 64][4]
-// with the four parts in Tab order.
+// Table layout (uint4 = 8 bf16): [set][dir (0 forward, 1 inverse)][q < N2][lane < 64][4]
+// with the four parts in Tab order.  Set 0 has the natural index orders; set 1 (p = 128,
+// for Half128MF's stage A) permutes the forward matrix's output rows and the inverse
+// matrix's contraction columns by pi (see Half128MF).
+constexpr int SET_WORDS = 2 * 64 * 4;   // uint4 per set and residue
 __device__ __forceinline__ Tab load_tab(const uint4* __restrict__ tab, int n2, int inv, int q, int lane) {
   const uint4* p = tab + ((size_t)(inv * n2 + q) * 64 + lane) * 4;
   const uint4 a = p[0], b = p[1], c = p[2], d = p[3];
@@ -65,38 +68,39 @@ __device__ __forceinline__ floatx4 mfma(bf16x8 a, bf16x8 b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// The 16-point transforms (with the folded twiddle) of the thread's four line blocks,
-// in place: v[4 cb + s] = value 4g + s of line n0 of block cb, before and after.
+// The 16-point transforms (with the folded twiddle) of NB line blocks, in place:
+// v[4 cb + s] = value 4g + s of line n0 of block cb, before and after.
+template <int NB = 4>
 __device__ __forceinline__ void radix16(float2* v, const Tab& A) {
-  bf16x8 bh[4], bl[4];
+  bf16x8 bh[NB], bl[NB];
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb) {
+  for (int cb = 0; cb < NB; ++cb) {
     const uint2 s0 = split2(v[4 * cb].x, v[4 * cb].y), s1 = split2(v[4 * cb + 1].x, v[4 * cb + 1].y);
     const uint2 s2 = split2(v[4 * cb + 2].x, v[4 * cb + 2].y), s3 = split2(v[4 * cb + 3].x, v[4 * cb + 3].y);
     bh[cb] = __builtin_bit_cast(bf16x8, u32x4{s0.x, s1.x, s2.x, s3.x});
     bl[cb] = __builtin_bit_cast(bf16x8, u32x4{s0.y, s1.y, s2.y, s3.y});
   }
-  floatx4 re[4], im[4];
+  floatx4 re[NB], im[NB];
   const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
-  // three passes over the blocks, so consecutive products of one accumulator are four
+  // three passes over the blocks, so consecutive products of one accumulator are 2 NB
   // instructions apart
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb) {
+  for (int cb = 0; cb < NB; ++cb) {
     re[cb] = mfma(A.rh, bh[cb], zero);
     im[cb] = mfma(A.ih, bh[cb], zero);
   }
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb) {
+  for (int cb = 0; cb < NB; ++cb) {
     re[cb] = mfma(A.rh, bl[cb], re[cb]);
     im[cb] = mfma(A.ih, bl[cb], im[cb]);
   }
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb) {
+  for (int cb = 0; cb < NB; ++cb) {
     re[cb] = mfma(A.rl, bh[cb], re[cb]);
     im[cb] = mfma(A.il, bh[cb], im[cb]);
   }
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb)
+  for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
     for (int s = 0; s < 4; ++s) v[4 * cb + s] = make_float2(re[cb][s], im[cb][s]);
 }
@@ -168,6 +172,146 @@ struct FrameMF {
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = lds[Base::at(row(t, e), col(t, e))];
     mf::radix16(v, A);
+  }
+};
+
+// p = 128 on the two-half transform (Half128's LDS buffer of 64 rows, 512 threads, two
+// frames per CU) with stages A and B on the matrix cores.
+// Thread t: wavefront w = t / 64 (stage A residue r2 = w, stage B residue c2 = w),
+// lane = 16 g + n0.  Register slots v[4 cb + i] (cb < 8, i < 4):
+//   spatial:   x(row 8 (4g + i) + w, col 16 cb + n0)
+//   stage A:   output k1 = pi(4g + i) of line (r2 = w, col 16 cb + n0), where
+//              pi(4g + i) = 8 (i / 2) + 2g + i % 2, so slots with i / 2 = h hold half h
+//              (k1 in [8h, 8h + 8)): 16 slots per half per thread, as in Half128
+//   frequency: the 16 frequencies f = 8q + c of half h (Half128's slot 16q + 8h + c)
+//              sit in slot 4 (f / 2) + 2h + f % 2, the ones half h's stage A left.
+// The forward stage-A matrix produces its outputs in pi order (its A-operand rows are
+// permuted) and the inverse contracts in pi order (its columns are), table set 1.
+struct Half128MF {
+  static constexpr int P = 128, N2 = 8, T = 512;
+  static constexpr int LP = Half128::LP, ROWS = Half128::ROWS, LDS = Half128::LDS;
+  __device__ static __forceinline__ int at(int row, int col) { return Half128::at(row, col); }
+  __device__ static __forceinline__ int wave(int t) { return __builtin_amdgcn_readfirstlane(t >> 6); }
+  __device__ static __forceinline__ int row(int t, int e) { return 8 * (4 * ((t & 63) >> 4) + (e & 3)) + wave(t); }
+  __device__ static __forceinline__ int col(int t, int e) { return 16 * (e >> 2) + (t & 15); }
+  // slot of frequency i (< 8) of group qq of half h
+  __device__ static __forceinline__ int fslot(int h, int qq, int i) {
+    const int f = 8 * qq + i;
+    return 4 * (f >> 1) + 2 * h + (f & 1);
+  }
+  __device__ static __forceinline__ void freq_hq(int t, int h, int qq, int i, int& kr, int& kc) {
+    Half128::freq(t, 16 * qq + 8 * h + i, kr, kc);
+  }
+
+  // stage A (forward) of blocks 2 grp, 2 grp + 1 (slots 8 grp .. 8 grp + 7), in place
+  __device__ static __forceinline__ void stage_a_fwd(float2* v, const mf::Tab& A, int grp) {
+    mf::radix16<2>(v + 8 * grp, A);
+  }
+  __device__ static __forceinline__ void stage_a_inv(float2* v, const mf::Tab& A, int grp) {
+    mf::radix16<2>(v + 8 * grp, A);
+  }
+  __device__ static __forceinline__ mf::Tab tab_a(const uint4* __restrict__ tab, int inv, int t) {
+    return mf::load_tab(tab + mf::SET_WORDS * N2, N2, inv, wave(t), t & 63);
+  }
+
+  // stage B on the 64 rows of a half: wavefront w takes c2 = w, rows 16 cb + n0 (cb < 4),
+  // two blocks at a time
+  template <bool INV>
+  __device__ static __forceinline__ void stage_b(float2* lds, const uint4* __restrict__ tab, int t) {
+    const int c2 = wave(t), lane = t & 63, g = lane >> 4, n0 = lane & 15;
+    const mf::Tab A = mf::load_tab(tab, N2, INV ? 1 : 0, c2, lane);
+#pragma unroll
+    for (int grp = 0; grp < 2; ++grp) {
+      float2 v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = lds[at(32 * grp + 16 * (e >> 2) + n0, c2 + N2 * (4 * g + (e & 3)))];
+      mf::radix16<2>(v, A);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) lds[at(32 * grp + 16 * (e >> 2) + n0, c2 + N2 * (4 * g + (e & 3)))] = v[e];
+    }
+  }
+
+  // half h forward: the half's stage-A outputs into LDS, stage B, stage C (FP32, as
+  // Half128), frequencies back into the half's slots.  Starts with a barrier; ends after
+  // the stage-C reads (no barrier).
+  __device__ static __forceinline__ void half_fwd(float2* v, float2* lds, const uint4* __restrict__ tab, int t,
+                                                  int h) {
+    const int w = wave(t), lane = t & 63, g = lane >> 4, n0 = lane & 15;
+    __syncthreads();
+#pragma unroll
+    for (int cb = 0; cb < 8; ++cb)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) lds[at(8 * (2 * g + jj) + w, 16 * cb + n0)] = v[4 * cb + 2 * h + jj];
+    __syncthreads();
+    stage_b<false>(lds, tab, t);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {   // stage C, DFT8 over r2 of lines (k1r, k1c, c2)
+      const int L = t + 512 * q;
+      const int c2 = L & 7, k1c = (L >> 3) & 15, k1r = L >> 7;
+      float2 a[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) a[r] = lds[at(8 * k1r + r, 8 * k1c + c2)];
+      dft8<false>(a);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) lds[at(8 * k1r + r, 8 * k1c + c2)] = a[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {   // stage C, DFT8 over c2 of lines (k1r, k2r, k1c)
+      const int L = t + 512 * q;
+      const int k1c = L & 15, k2r = (L >> 4) & 7, k1r = L >> 7;
+      float2 a[8];
+#pragma unroll
+      for (int c = 0; c < 8; c += 2) {
+        const float4 x = *reinterpret_cast<const float4*>(lds + at(8 * k1r + k2r, 8 * k1c + c));
+        a[c] = make_float2(x.x, x.y);
+        a[c + 1] = make_float2(x.z, x.w);
+      }
+      dft8<false>(a);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) v[fslot(h, q, c)] = a[c];
+    }
+  }
+
+  // half h inverse: the exact reverse, ending with the half's stage-A values back in their
+  // slots.  Starts with a barrier; ends after the final LDS reads (no barrier).
+  __device__ static __forceinline__ void half_inv(float2* v, float2* lds, const uint4* __restrict__ tab, int t,
+                                                  int h) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int L = t + 512 * q;
+      const int k1c = L & 15, k2r = (L >> 4) & 7, k1r = L >> 7;
+      float2 a[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) a[c] = v[fslot(h, q, c)];
+      dft8<true>(a);
+#pragma unroll
+      for (int c = 0; c < 8; c += 2)
+        *reinterpret_cast<float4*>(lds + at(8 * k1r + k2r, 8 * k1c + c)) =
+            make_float4(a[c].x, a[c].y, a[c + 1].x, a[c + 1].y);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int L = t + 512 * q;
+      const int c2 = L & 7, k1c = (L >> 3) & 15, k1r = L >> 7;
+      float2 a[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) a[r] = lds[at(8 * k1r + r, 8 * k1c + c2)];
+      dft8<true>(a);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) lds[at(8 * k1r + r, 8 * k1c + c2)] = a[r];
+    }
+    __syncthreads();
+    stage_b<true>(lds, tab, t);
+    __syncthreads();
+    const int w = wave(t), lane = t & 63, g = lane >> 4, n0 = lane & 15;
+#pragma unroll
+    for (int cb = 0; cb < 8; ++cb)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) v[4 * cb + 2 * h + jj] = lds[at(8 * (2 * g + jj) + w, 16 * cb + n0)];
   }
 };
 

@@ -43,7 +43,7 @@ __device__ __forceinline__ int sweep_pos(int32_t chunk, int xcd_slice) {
 // ST: 0 no statistics, 1 the iteration's measures, 2 also the frame residuals.
 // MF: radix-16 stages on the matrix cores (FrameMF, split BF16), else Frame's FP32 stages.
 template <int P, bool MF, bool BLIND, int ST>
-__global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
+__global__ __launch_bounds__(Frame<P>::T, MF && P == 64 && ST == 0 ? 4 : 1) void k_sweep(SweepArgs a, ProxC pc) {
   using F = Frame<P>;
   using M = FrameMF<P>;    // instantiated only when MF
   constexpr bool STATS = ST > 0;
@@ -153,9 +153,11 @@ __global__ __launch_bounds__(Frame<P>::T) void k_sweep(SweepArgs a, ProxC pc) {
 // K1 at p = 128: the same step on the two-half transform (Half128: 512 threads,
 // 77 KB of LDS, two frames per CU).  The prox of each half runs between that half's
 // forward and inverse stages B and C.
-template <bool BLIND, int ST>
+// MF: stages A and B on the matrix cores (Half128MF, split BF16).
+template <bool MF, bool BLIND, int ST>
 __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_sweep128(SweepArgs a, ProxC pc) {
   using F = Half128;
+  using M = Half128MF;
   constexpr bool STATS = ST > 0;
   constexpr int P = 128;
   __shared__ __align__(16) float2 lds[F::LDS];
@@ -183,6 +185,25 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
   // 8 rows, so the first line's transform and 16 products stay in registers without
   // spilling
   float2 v[32];
+  if constexpr (MF) {
+    // gather and stage A two line blocks at a time (8 slots), the next group's loads
+    // after the current group's products
+    const mf::Tab A = M::tab_a(a.mft, 0, t);
+#pragma unroll
+    for (int grp = 0; grp < 4; ++grp) {
+#pragma unroll
+      for (int e = 8 * grp; e < 8 * grp + 8; ++e) {
+        const int row = M::row(t, e), c = M::col(t, e);
+        const uint32_t ob = 8u * (uint32_t)(row * fd.pitch + c);
+        v[e] = c_mul(*reinterpret_cast<const float2*>(reinterpret_cast<const char*>(ub) + ob),
+                     w[(uint32_t)(row * P + c)]);
+      }
+      M::stage_a_fwd(v, A, grp);
+#pragma unroll
+      for (int e = 8 * grp; e < 8 * grp + 8; ++e) pin(v[e]);
+      asm volatile("" ::: "memory");
+    }
+  } else
 #pragma unroll
   for (int l = 0; l < 2; ++l) {
 #pragma unroll
@@ -210,7 +231,8 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
   double mis = 0.0, gsum = 0.0, gdel = 0.0, gnrm = 0.0;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    F::half_fwd<TWL>(v, lds, twl, t, h);
+    if constexpr (MF) M::half_fwd(v, lds, a.mft, t, h);
+    else F::half_fwd<TWL>(v, lds, twl, t, h);
     // amplitudes and multipliers in two groups of 8 (each group's loads before its
     // stores); the other frame on the CU computes meanwhile
 #pragma unroll
@@ -226,7 +248,7 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
       }
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const int e = 16 * qq + 8 * h + i;
+        const int e = MF ? M::fslot(h, qq, i) : 16 * qq + 8 * h + i;
         const float2 X = c_scale(v[e], inv_p);
         const float sf = spre[i];
         const float2 y = c_add(gpre[i], X);
@@ -248,12 +270,35 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
         gb[(uint32_t)(kr * P + kc)] = gpre[i];
       }
     }
-    F::half_inv<TWL>(v, lds, twl, t, h);
+    if constexpr (MF) M::half_inv(v, lds, a.mft, t, h);
+    else F::half_inv<TWL>(v, lds, twl, t, h);
   }
   if (STATS) frame_stats<F::T, (ST > 1)>(a.part + NFS * (size_t)j, mis, gsum, gdel, gnrm, red);
   // inverse stage A and the output one line at a time; the second line's probe loads
   // are issued before the first line's stores (see the prox above)
   const float2* wo = a.w_out + woff;
+  if constexpr (MF) {
+    // inverse stage A two line blocks at a time; each group's probe values are loaded
+    // before its products, its outputs stored after
+    const mf::Tab A = M::tab_a(a.mft, 1, t);
+#pragma unroll
+    for (int grp = 0; grp < 4; ++grp) {
+      asm volatile("" ::: "memory");
+      float2 wk[8];
+      if (!BLIND) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) wk[i] = wo[(uint32_t)(M::row(t, 8 * grp + i) * P + M::col(t, 8 * grp + i))];
+      }
+      M::stage_a_inv(v, A, grp);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int e = 8 * grp + i;
+        const float2 x = BLIND ? v[e] : c_mulc(v[e], wk[i]);
+        pb[(uint32_t)(M::row(t, e) * P + M::col(t, e))] = x;
+      }
+    }
+    return;
+  }
   float2 wk[2][16];
 #pragma unroll
   for (int l = 0; l < 2; ++l) {
@@ -294,18 +339,26 @@ hipError_t launch_sweep(int p, const SweepArgs& a, hipStream_t s, hipEvent_t ev0
   }
   if (a.mft) {   // radix-16 stages on the matrix cores (hybrid transform)
     if (p == 64) ODP_SWEEP(64, true)
-    if (p == 128) ODP_SWEEP(128, true)
+    if (p == 128) {
+      constexpr int T = Half128MF::T;
+      if (bl && st) ODP_SWEEP_GO((k_sweep128<true, true, 1>), T);
+      else if (bl) ODP_SWEEP_GO((k_sweep128<true, true, 0>), T);
+      else if (st == 2) ODP_SWEEP_GO((k_sweep128<true, false, 2>), T);
+      else if (st) ODP_SWEEP_GO((k_sweep128<true, false, 1>), T);
+      else ODP_SWEEP_GO((k_sweep128<true, false, 0>), T);
+      return hipGetLastError();
+    }
     return hipErrorInvalidValue;
   }
   if (p == 32) ODP_SWEEP(32, false)
   if (p == 64) ODP_SWEEP(64, false)
   if (p == 128) {
     constexpr int T = Half128::T;
-    if (bl && st) ODP_SWEEP_GO((k_sweep128<true, 1>), T);
-    else if (bl) ODP_SWEEP_GO((k_sweep128<true, 0>), T);
-    else if (st == 2) ODP_SWEEP_GO((k_sweep128<false, 2>), T);
-    else if (st) ODP_SWEEP_GO((k_sweep128<false, 1>), T);
-    else ODP_SWEEP_GO((k_sweep128<false, 0>), T);
+    if (bl && st) ODP_SWEEP_GO((k_sweep128<false, true, 1>), T);
+    else if (bl) ODP_SWEEP_GO((k_sweep128<false, true, 0>), T);
+    else if (st == 2) ODP_SWEEP_GO((k_sweep128<false, false, 2>), T);
+    else if (st) ODP_SWEEP_GO((k_sweep128<false, false, 1>), T);
+    else ODP_SWEEP_GO((k_sweep128<false, false, 0>), T);
     return hipGetLastError();
   }
 #undef ODP_SWEEP

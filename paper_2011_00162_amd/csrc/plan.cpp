@@ -384,30 +384,36 @@ int build_geometry(odp_plan* P) {
   // hybrid transform (fft_mfma.hpp): for every residue q < p/16 the 16-point stage
   // matrix M_q[k][r] = W_p^{q k} W_16^{r k} (and its conjugate transpose for the
   // inverse), FP64 on the host, as MFMA A operands per lane l = 16 g + n0: row m = n0,
-  // element e = 2 s + c at input r = 4 g + s, part c; the real-output row holds
-  // (Re M, -Im M) and the imaginary-output row (Im M, Re M); each split hi + lo.
+  // element e = 2 s + c at contraction index 4 g + s, part c; the real-output row holds
+  // (Re M, -Im M) and the imaginary-output row (Im M, Re M); each split hi + lo.  Set 0
+  // in natural order; set 1 (p = 128, the two-half transform's stage A) with the
+  // forward output rows and the inverse contraction columns permuted by
+  // pi(4g + i) = 8 (i / 2) + 2g + i % 2.
   if (p == 64 || p == 128) {
-    const int nq = p / 16;
-    P->mft.assign((size_t)2 * nq * 64 * 4 * 8, 0);
-    for (int dir = 0; dir < 2; ++dir)
-      for (int q = 0; q < nq; ++q)
-        for (int l = 0; l < 64; ++l) {
-          const int g = l >> 4, m = l & 15;
-          for (int e = 0; e < 8; ++e) {
-            const int r = 4 * g + (e >> 1), c = e & 1;
-            // forward M[m][r]; inverse M^H[m][r] = conj(M[r][m])
-            const int kk = dir == 0 ? m : r, rr = dir == 0 ? r : m;
-            const double a = -2.0 * M_PI * ((double)(q * kk) / (double)p + (double)((rr * kk) % 16) / 16.0);
-            const double mr = std::cos(a), mi = dir == 0 ? std::sin(a) : -std::sin(a);
-            const double vre = c == 0 ? mr : -mi, vim = c == 0 ? mi : mr;
-            const size_t o = (((size_t)(dir * nq + q) * 64 + l) * 4) * 8 + e;
-            const uint16_t h0 = bf16_rne((float)vre), h1 = bf16_rne((float)vim);
-            P->mft[o] = h0;
-            P->mft[o + 8] = bf16_rne((float)(vre - bf16_value(h0)));
-            P->mft[o + 16] = h1;
-            P->mft[o + 24] = bf16_rne((float)(vim - bf16_value(h1)));
+    const int nq = p / 16, nsets = p == 128 ? 2 : 1;
+    auto pi = [](int x) { return 8 * ((x & 3) >> 1) + 2 * (x >> 2) + (x & 1); };
+    P->mft.assign((size_t)nsets * 2 * nq * 64 * 4 * 8, 0);
+    for (int set = 0; set < nsets; ++set)
+      for (int dir = 0; dir < 2; ++dir)
+        for (int q = 0; q < nq; ++q)
+          for (int l = 0; l < 64; ++l) {
+            const int g = l >> 4, m = l & 15;
+            for (int e = 0; e < 8; ++e) {
+              const int c = e & 1, x = 4 * g + (e >> 1);
+              const int out = set == 1 && dir == 0 ? pi(m) : m, in = set == 1 && dir == 1 ? pi(x) : x;
+              // forward M[out][in]; inverse M^H[out][in] = conj(M[in][out])
+              const int kk = dir == 0 ? out : in, rr = dir == 0 ? in : out;
+              const double a = -2.0 * M_PI * ((double)(q * kk) / (double)p + (double)((rr * kk) % 16) / 16.0);
+              const double mr = std::cos(a), mi = dir == 0 ? std::sin(a) : -std::sin(a);
+              const double vre = c == 0 ? mr : -mi, vim = c == 0 ? mi : mr;
+              const size_t o = ((((size_t)(set * 2 + dir) * nq + q) * 64 + l) * 4) * 8 + e;
+              const uint16_t h0 = bf16_rne((float)vre), h1 = bf16_rne((float)vim);
+              P->mft[o] = h0;
+              P->mft[o + 8] = bf16_rne((float)(vre - bf16_value(h0)));
+              P->mft[o + 16] = h1;
+              P->mft[o + 24] = bf16_rne((float)(vim - bf16_value(h1)));
+            }
           }
-        }
   }
   return ODP_OK;
 }

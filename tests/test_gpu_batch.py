@@ -108,7 +108,7 @@ def test_autotune_keeps_results_within_tolerance():
     t = plan.autotune(scratch, iters=3)
     say("autotune choice", dict(transform=t.transform, xcd_slice=t.xcd_slice, tile=(t.tile_rows, t.tile_cols),
                                 ms=t.ms_per_iter, tried=t.n_tried))
-    assert t.n_tried == 18 and t.ms_per_iter > 0
+    assert t.n_tried == 27 and t.ms_per_iter > 0     # 3 transforms x 3 placements x 3 tilings at p = 64
     st = plan.new_state()
     K = 8
     plan.iterate(st, K)

@@ -1,7 +1,8 @@
 """c2 (512x512 image, p = 64, 4x4 subdomains) after K = 50 and K = 200 OD2Pm
 iterations on the GPU against the FP64 oracle's runs, stored by
 tests/golden/make_c2_reference.py (which calls only the oracle and the seeded input
-recipes), for both frame transforms and two data cases.
+recipes), for both frame transforms and two data cases; and the 2048^2 blind workload
+after K = 10 OD2BP iterations against tests/golden/make_c5_reference.py's run.
 
 Bound on the merged image (8192 seeded pixel samples, relative norm):
     max(1e-3, 2 * s_K)
@@ -78,3 +79,40 @@ def test_c2_reconstruction_matches_oracle(golden, case, transform):
     assert rf_diff <= 1e-3
     assert abs(norm_diff) <= 1e-3
     assert abs(et_diff) <= 1e-3
+
+
+@pytest.fixture(scope="module")
+def golden_c5():
+    return dict(np.load(os.path.join(HERE, "golden", "c5_k10_oracle.npz")))
+
+
+@pytest.mark.parametrize("transform", [odp.ODP_FFT_F32, odp.ODP_HYBRID_MFMA], ids=["fft", "hybrid"])
+def test_c5_blind_reconstruction_matches_oracle(golden_c5, transform):
+    """The 2048^2 / 6561-frame blind workload (Alg. 3 from the flat disk of radius 40)
+    after K = 10 iterations against the oracle's run stored by
+    tests/golden/make_c5_reference.py: merged image on 8192 seeded pixels and the shared
+    probe, bound max(1e-3, 2 s_10) with s_10 the oracle's own distance after 10 iterations
+    under a perturbation at the transform's resolution: of sqrt(f) by half a float32 ulp
+    (two seeds, about 1e-5), and of the start probe by a float32 ulp (FFT) or a split-BF16
+    hi + lo pair (hybrid), which moves the Step-0 ties of the flat disk's spectrum (reading
+    22); and the RF curve to 1e-3."""
+    from tests.golden.make_c5_reference import inputs
+    G = golden_c5
+    spec, pr, sf, w0 = inputs()
+    say("c5 blind K=10, transform", transform)
+    plan = odp.Plan(spec.n, spec.n, spec.p, pr["offsets"], pr["frame_sub"], eps=0.5, eta=0.1, r=float(G["r"]),
+                    mu=float(G["mu"]), blind=True, transform=transform)
+    plan.bind(dev_f32(sf.astype(np.float32)), dev_c64(w0))
+    st = plan.new_state(w0=dev_c64(w0))
+    rf = host(plan.iterate(st, 10, stats=True))[:, 0]
+    u = host(plan.merge(st)).reshape(-1)[G["idx"]]
+    err_u = float(np.linalg.norm(u - G["u10"]) / np.linalg.norm(G["u10"]))
+    err_w = float(np.linalg.norm(host(st.probe()) - G["w10"]) / np.linalg.norm(G["w10"]))
+    s_w0 = G["sens10_w0_bf16" if transform == odp.ODP_HYBRID_MFMA else "sens10_w0"]
+    b_u = max(1e-3, 2.0 * max(float(np.max(G["sens10"])), float(s_w0[0])))
+    b_w = max(1e-3, 2.0 * max(float(np.max(G["sens10_w"])), float(s_w0[1])))
+    rf_diff = float(np.max(np.abs(rf - G["rf"]) / G["rf"]))
+    say(f"K=10 merged image err {err_u:.3e} (bound {b_u:.1e})  probe err {err_w:.3e} (bound {b_w:.1e})  "
+        f"RF max rel diff {rf_diff:.2e}")
+    assert err_u <= b_u and err_w <= b_w
+    assert rf_diff <= 1e-3
