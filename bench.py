@@ -40,7 +40,8 @@ C5_SUBS_CHECKED = (0, 3, 36)      # a corner, an edge and an interior subdomain 
 LOSS_SOURCES = ["paper_2011_00162_amd/csrc/loss.hip", "paper_2011_00162_amd/csrc/fft_frame.hpp",
                 "paper_2011_00162_amd/csrc/reduce.hpp", "paper_2011_00162_amd/csrc/odp_internal.hpp"]
 KERNEL_SOURCES = ["paper_2011_00162_amd/csrc/kernels.hip", "paper_2011_00162_amd/csrc/fft_frame.hpp",
-                  "paper_2011_00162_amd/csrc/prox.hpp", "paper_2011_00162_amd/csrc/odp_internal.hpp"]
+                  "paper_2011_00162_amd/csrc/fft_mfma.hpp", "paper_2011_00162_amd/csrc/prox.hpp",
+                  "paper_2011_00162_amd/csrc/odp_internal.hpp"]
 
 
 def kernel_hash(sources=None) -> str:
