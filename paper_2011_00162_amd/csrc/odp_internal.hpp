@@ -119,8 +119,8 @@ struct PixelArgs {
   const CellDesc* cells;
   const TileDesc* tiles;
   int32_t n_tiles, p, tile_cols;
-  int32_t n_uni;             // tiles [0, n_uni) belong to cells with at most 4 copies, the rest to
-                             // cells with 5 to MAXS
+  int32_t n_uni;             // tiles [0, n_uni) belong to cells with at most 4 copies,
+  int32_t n_mid;             // [n_uni, n_mid) to cells with 5 to 8, the rest to 9 to MAXS
   const WaveRec* waves;      // [n_uni][4]
   const float2* psi;         // per-frame outputs of the sweep
   const int32_t* tf_first;   // [n_tiles*MAXS + 1]: frames of slot s overlapping tile t

@@ -258,15 +258,16 @@ __device__ __forceinline__ int copy_groups_log2(int m) {
   return m <= 1 ? 0 : m <= 2 ? 1 : m <= 4 ? 2 : m <= 8 ? 3 : 4;
 }
 
-// Tiles of cells with five to MAXS copies (tiles [n_uni, n_tiles)): the copy index
-// varies inside a wavefront, so the descriptors come from the cell, per lane.  A thread
-// keeps v - Lam for each of its up to MAXS - 1 partners until the barrier; the partners'
-// iterate n is read partner by partner.
-template <bool STATS, bool BLIND>
+// Tiles of cells with five to MAXS copies: the copy index varies inside a wavefront, so
+// the descriptors come from the cell, per lane.  A thread keeps v - Lam for each of its up
+// to MC - 1 partners until the barrier; the partners' iterate n is read partner by
+// partner.  MC = 8 runs the tiles [n_uni, n_mid) of cells with five to eight copies,
+// MC = MAXS the rest (the partner arrays, and so the registers, are sized by MC).
+template <bool STATS, bool BLIND, int MC>
 __global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
   __shared__ double red[NPS][MAXS];
-  constexpr int NO = MAXS - 1;
-  const int tile = a.n_uni + blockIdx.x;
+  constexpr int NO = MC - 1;
+  const int tile = (MC <= 8 ? a.n_uni : a.n_mid) + blockIdx.x;
   const TileDesc td = a.tiles[tile];
   const CellDesc* cd = a.cells + td.cell;
   if (a.stop && a.stop[cd->probe].stopped) return;  // its problem met its stopping rule
@@ -349,7 +350,8 @@ hipError_t launch_pixel(const PixelArgs& a, bool stats, bool blind, hipStream_t 
   const dim3 b(256);
 #define ODP_PIXEL(ST, BL)                                                                            \
   if (a.n_uni > 0) hipLaunchKernelGGL((k_pixel_uni<ST, BL>), dim3(a.n_uni), b, 0, s, a);             \
-  if (a.n_tiles > a.n_uni) hipLaunchKernelGGL((k_pixel<ST, BL>), dim3(a.n_tiles - a.n_uni), b, 0, s, a);
+  if (a.n_mid > a.n_uni) hipLaunchKernelGGL((k_pixel<ST, BL, 8>), dim3(a.n_mid - a.n_uni), b, 0, s, a);       \
+  if (a.n_tiles > a.n_mid) hipLaunchKernelGGL((k_pixel<ST, BL, MAXS>), dim3(a.n_tiles - a.n_mid), b, 0, s, a);
   if (blind) {
     if (stats) { ODP_PIXEL(true, true) }
     else { ODP_PIXEL(false, true) }

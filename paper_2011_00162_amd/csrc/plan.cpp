@@ -84,7 +84,8 @@ struct odp_plan {
   struct TileSet {
     int rows = 0, cols = 0;
     std::vector<TileDesc> tiles;             // cells with m <= 4 first: tiles [0, n_uni)
-    int32_t n_uni = 0;
+    int32_t n_uni = 0;                       // then 5 <= m <= 8: tiles [n_uni, n_mid)
+    int32_t n_mid = 0;
     std::vector<int32_t> re_list, re_first;  // (tile, slot) entries per subdomain, for RE
     std::vector<int32_t> tf_first;           // per (tile, slot): range of pull records
     std::vector<PullEntry> pull;             // frames whose window meets the tile, ascending id
@@ -161,11 +162,12 @@ void build_tiles(const odp_plan* P, int rows, int cols, odp_plan::TileSet& T) {
   T.cols = cols;
   T.tiles.clear();
   // cells with up to four copies first (their pixel kernel runs with wavefront-uniform
-  // copy indices), then the rest
-  for (int pass = 0; pass < 2; ++pass) {
+  // copy indices), then those with five to eight, then the rest (the general kernel is
+  // instantiated for each group's largest number of partner copies)
+  for (int pass = 0; pass < 3; ++pass) {
     for (size_t c = 0; c < P->cells.size(); ++c) {
       const CellDesc& cd = P->cells[c];
-      if ((cd.m > 4) != (pass == 1)) continue;
+      if ((cd.m <= 4 ? 0 : cd.m <= 8 ? 1 : 2) != pass) continue;
       int groups = 1;
       while (groups < cd.m) groups *= 2;
       const int ppt = rows * cols / groups, tw = std::min(cols, ppt), th = ppt / tw;
@@ -184,6 +186,7 @@ void build_tiles(const odp_plan* P, int rows, int cols, odp_plan::TileSet& T) {
         }
     }
     if (pass == 0) T.n_uni = (int32_t)T.tiles.size();
+    if (pass == 1) T.n_mid = (int32_t)T.tiles.size();
   }
   std::vector<std::vector<int32_t>> per(D);
   for (size_t t = 0; t < T.tiles.size(); ++t) {
@@ -1038,6 +1041,7 @@ static PixelArgs pixel_args(const odp_plan* P, char* b, double* stats) {
   a.waves = P->W_<WaveRec>(P->ws.waves);
   a.n_tiles = (int32_t)P->tset().tiles.size();
   a.n_uni = P->tset().n_uni;
+  a.n_mid = P->tset().n_mid;
   a.p = P->p;
   a.tile_cols = P->tset().cols;
   a.psi = P->W_<float2>(P->ws.psi);
