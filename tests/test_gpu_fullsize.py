@@ -167,34 +167,40 @@ def c4_batch():
         t = plan.autotune(scratch, iters=3)
         say("batch p", p, "problems", len(group), "tuning", t.transform, t.xcd_slice, t.tiling)
         del scratch
-        out.append((plan, data))
+        out.append((plan, data, t.transform))
     return out
+
+
+def _split_bf16(transform):
+    """The split-BF16 transforms (reading 18): one iteration within 1e-4 instead of 1e-5,
+    and the oracle's sensitivity taken at a hi + lo pair's resolution (2^-17)."""
+    return transform in (odp.ODP_DFT_SPLIT_BF16, odp.ODP_HYBRID_MFMA)
 
 
 def test_c4_full_batch_one_problem_per_probe_size(c4_batch):
     say("full 64-problem batch")
     eta = 0.1
     plans, states, picks = [], [], []
-    for plan, data in c4_batch:
+    for plan, data, tr in c4_batch:
         # the problem with the most subdomains of this probe size
         i = max(range(len(data)), key=lambda q: plan.entry(q).D)
-        picks.append((plan, i, data[i]))
+        picks.append((plan, i, data[i], tr))
         plans.append(plan)
         states.append(plan.new_state())
     odp.Graph(plans, states, 2).launch()
     snaps = []
-    for (plan, i, (s, pr, w, sf)), st in zip(picks, states):
+    for (plan, i, (s, pr, w, sf), tr), st in zip(picks, states):
         e = plan.entry(i)
         g = build_geometry(s.n, s.n, s.p, pr["offsets"], pr["frame_sub"])
         subs = _subs(g)
         snaps.append((g, subs, _snapshot(st, subs, g, D0=e.D0, J0=e.J0)))
     odp.Graph(plans, states, 1).launch()
-    for (plan, i, (s, pr, w, sf)), st, (g, subs, snap) in zip(picks, states, snaps):
+    for (plan, i, (s, pr, w, sf), tr), st, (g, subs, snap) in zip(picks, states, snaps):
         e = plan.entry(i)
         want = local.od2pm_step_local(g, w, _F(sf), snap["u"], snap["lam"], snap["gamma"], 0.5, eta, e.r, subs)
         err = _compare(st, want, g, D0=e.D0, J0=e.J0)
-        say("batch p", s.p, "problem", i, "n", s.n, "D", g.D, "errors", err)
-        assert max(err.values()) <= 1e-5, err
+        say("batch p", s.p, "problem", i, "n", s.n, "D", g.D, "transform", tr, "errors", err)
+        assert max(err.values()) <= (1e-4 if _split_bf16(tr) else 1e-5), err
 
 
 def test_c4_batch_100_iterations_smallest_problems(c4_batch):
@@ -202,15 +208,16 @@ def test_c4_batch_100_iterations_smallest_problems(c4_batch):
     count); the merged image of the smallest problem of each probe size against the FP64
     oracle's 100 iterations of that problem alone.  Bound max(1e-3, 2 s_100) on the Poisson
     data, s_100 the oracle's own distance after 100 iterations between runs whose sqrt(f)
-    differs by half a float32 ulp (the larger of two seeds; the reading of the K-iteration
-    bound used for the 512^2 workload)."""
+    differs by half a float32 ulp (by 2^-17 if the autotuner chose a split-BF16 transform;
+    the larger of two seeds; the reading of the K-iteration bound used for the 512^2
+    workload)."""
     from oracle.od2p import merge, od2pm_run
     K, eta = 100, 0.1
-    plans = [plan for plan, _ in c4_batch]
+    plans = [plan for plan, _, _ in c4_batch]
     states = [plan.new_state() for plan in plans]
     odp.Graph(plans, states, K).launch()
     torch.cuda.synchronize()
-    for (plan, data), st in zip(c4_batch, states):
+    for (plan, data, tr), st in zip(c4_batch, states):
         i = min(range(len(data)), key=lambda q: (plan.entry(q).J, q))
         s, pr, w, sf = data[i]
         e = plan.entry(i)
@@ -222,11 +229,11 @@ def test_c4_batch_100_iterations_smallest_problems(c4_batch):
         sens = 0.0
         for seed in (7, 8):
             unit = np.random.default_rng(seed).uniform(-1.0, 1.0, sf.shape)
-            fp = (sf.astype(np.float64) * (1.0 + 2.0 ** -24 * unit)) ** 2
+            fp = (sf.astype(np.float64) * (1.0 + (2.0 ** -17 if _split_bf16(tr) else 2.0 ** -24) * unit)) ** 2
             op, _ = od2pm_run(g, w, fp, 0.5, eta, e.r, K)
             sens = max(sens, rel(merge(g, op.u), want))
         err = rel(img, want)
         bound = max(1e-3, 2.0 * sens)
-        say("batch p", s.p, "smallest problem", i, "J", e.J, "D", e.D, "n", s.n, f"K={K} err {err:.3e} "
+        say("batch p", s.p, "transform", tr, "smallest problem", i, "J", e.J, "D", e.D, "n", s.n, f"K={K} err {err:.3e} "
             f"s_K {sens:.3e} bound {bound:.1e}")
         assert err <= bound, (err, bound)
