@@ -174,6 +174,15 @@ def cpu_leg(args, torch, odp, synthetic):
         st, _ = od2pm_run(g, w, f, eps, eta, r, K)
         dt = time.perf_counter() - t
     u_or = merge(g, st.u)
+    # the oracle's own distance after K iterations from sqrt(f) changed by a rounding-sized
+    # factor (half a float32 ulp; a split-BF16 hi + lo pair's resolution): on Poisson data
+    # the iteration amplifies such changes, and no other arithmetic can follow one FP64
+    # trajectory more closely
+    sens = {}
+    unit = np.random.default_rng(7).uniform(-1.0, 1.0, sf32.shape)
+    for tag, scale in (("float32_half_ulp", 2.0 ** -24), ("split_bf16_pair", 2.0 ** -17)):
+        sp, _ = od2pm_run(g, w, (sf32.astype(np.float64) * (1.0 + scale * unit)) ** 2, eps, eta, r, K)
+        sens[tag] = float(np.linalg.norm(merge(g, sp.u) - u_or) / np.linalg.norm(u_or))
     # the GPU path on the identical data and iteration count, both transforms
     errs = {}
     for name, tr in (("fft_f32", odp.ODP_FFT_F32), ("dft_split_bf16", odp.ODP_DFT_SPLIT_BF16),
@@ -188,7 +197,7 @@ def cpu_leg(args, torch, odp, synthetic):
     return dict(value=g.J * K / dt, unit="frame-iters/s", cores=1, kind="oracle",
                 sample=f"{K} OD2Pm iterations of the full 512x512 / 841-frame workload (FP64 NumPy, "
                        f"single thread) in {dt:.1f} s on {cpu_model()} ({os.cpu_count()} logical CPUs)",
-                rel_err_gpu_vs_oracle=errs, rel_err_iters=K)
+                rel_err_gpu_vs_oracle=errs, rel_err_iters=K, oracle_self_sensitivity=sens)
 
 
 
@@ -400,6 +409,15 @@ def c5_cpu_leg(args, torch, odp, synthetic):
         ost, _ = blind.od2bp_run(g, f, w0, eps, eta, r, mu, K)
         dt = time.perf_counter() - t
     u_or = merge(g, ost.u)
+    # the oracle's own distance after K iterations from the start probe changed by a float32
+    # ulp (the flat disk's spectrum has near-zeros whose phase is a tie at that resolution)
+    rng = np.random.default_rng(9)
+    d0 = 2.0 ** -24 * (rng.uniform(-1.0, 1.0, w0.shape) + 1j * rng.uniform(-1.0, 1.0, w0.shape))
+    osp, _ = blind.od2bp_run(g, f, w0 * (1.0 + d0), eps, eta, r, mu, K)
+    sens = {"perturbation": "start probe x (1 + d), |Re d|, |Im d| <= 2^-24",
+            "merged_u": float(np.linalg.norm(merge(g, osp.u) - u_or) / np.linalg.norm(u_or)),
+            "w": float(np.linalg.norm(osp.w - ost.w) / np.linalg.norm(ost.w))}
+    del osp
     den = [subdomain_illumination(g, ost.w_sub[d], d) for d in range(g.D)]
     sqrt_f = torch.from_numpy(sf32).cuda()
     subs = list(C5_SUBS_CHECKED)
@@ -448,7 +466,7 @@ def c5_cpu_leg(args, torch, odp, synthetic):
     return dict(value=g.J * K / dt, unit="frame-iters/s", cores=1, kind="oracle",
                 sample=f"{K} OD2BP iterations (Alg. 3) of the full 2048x2048 / 6561-frame blind workload from Step 0 "
                        f"(FP64 NumPy, single thread) in {dt:.1f} s on {cpu_model()} ({os.cpu_count()} logical CPUs)",
-                rel_err_gpu_vs_oracle=errs)
+                rel_err_gpu_vs_oracle=errs, oracle_self_sensitivity=sens)
 
 
 # iterations to RF <= 1e-5 that the paper reports for its stripes on its own 512^2 image

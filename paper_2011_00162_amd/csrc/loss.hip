@@ -16,13 +16,23 @@
 
 namespace odp {
 
+// Frame of this workgroup: workgroup b runs on XCD b % 8, and each XCD takes a contiguous
+// slice of the frames (scan order), so neighbouring windows, which share image rows, are
+// read through one L2.  The grid is 8 ceil(J / 8); -1 for the workgroups past J.
+__device__ __forceinline__ int loss_frame(int J) {
+  const int chunk = (J + NXCD - 1) / NXCD, b = blockIdx.x;
+  const int j = (b % NXCD) * chunk + b / NXCD;
+  return j < J ? j : -1;
+}
+
 template <int P, bool GRAD>
 __global__ __launch_bounds__(Frame<P>::T) void k_loss(LossArgs a) {
   using F = Frame<P>;
   __shared__ __align__(16) float2 lds[F::LDS];
   __shared__ __align__(16) float2 twl[F::N2 * TWL];   // stage-B twiddles in LDS (no global-load waits)
   __shared__ double red[F::T / 64];
-  const int j = blockIdx.x, t = threadIdx.x;
+  const int j = loss_frame(a.J), t = threadIdx.x;
+  if (j < 0) return;   // uniform over the workgroup
   const int col = F::a_col(t), r2 = F::a_r2(t);
   const int64_t base = (int64_t)a.offsets[2 * j] * a.W + a.offsets[2 * j + 1];
   const float inv_p = 1.0f / (float)P;
@@ -74,7 +84,8 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
   __shared__ __align__(16) float2 lds[F::LDS];
   __shared__ __align__(16) float2 twl[F::N2 * TWL];
   __shared__ double red[F::T / 64];
-  const int j = blockIdx.x, t = threadIdx.x;
+  const int j = loss_frame(a.J), t = threadIdx.x;
+  if (j < 0) return;   // uniform over the workgroup
   const int col = F::a_col(t);
   const int64_t base = (int64_t)a.offsets[2 * j] * a.W + a.offsets[2 * j + 1];
   const float inv_p = 1.0f / (float)P;
@@ -264,10 +275,11 @@ __global__ __launch_bounds__(256) void k_loss_total(const double* frame_loss, in
 }
 
 hipError_t launch_loss(int p, const LossArgs& a, bool grad, hipStream_t s) {
+  const dim3 grid(NXCD * ((a.J + NXCD - 1) / NXCD));   // see loss_frame
 #define ODP_LOSS(PP)                                                                                   \
   if (p == PP) {                                                                                       \
-    if (grad) hipLaunchKernelGGL((k_loss<PP, true>), dim3(a.J), dim3(Frame<PP>::T), 0, s, a);            \
-    else hipLaunchKernelGGL((k_loss<PP, false>), dim3(a.J), dim3(Frame<PP>::T), 0, s, a);                \
+    if (grad) hipLaunchKernelGGL((k_loss<PP, true>), grid, dim3(Frame<PP>::T), 0, s, a);                 \
+    else hipLaunchKernelGGL((k_loss<PP, false>), grid, dim3(Frame<PP>::T), 0, s, a);                     \
     return hipGetLastError();                                                                          \
   }
   ODP_LOSS(32)
@@ -275,7 +287,7 @@ hipError_t launch_loss(int p, const LossArgs& a, bool grad, hipStream_t s) {
   // p = 128: the loss alone on the two-half transform; with the gradient the per-element
   // FP64 work and the inverse path spill on it (measured slower), so it keeps Frame<128>
   if (p == 128 && !grad) {
-    hipLaunchKernelGGL((k_loss128<false>), dim3(a.J), dim3(Half128::T), 0, s, a);
+    hipLaunchKernelGGL((k_loss128<false>), grid, dim3(Half128::T), 0, s, a);
     return hipGetLastError();
   }
   ODP_LOSS(128)
