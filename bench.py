@@ -132,6 +132,28 @@ def time_iterations(torch, plan, state, steps):
     return t0.elapsed_time(t1)
 
 
+def copy_rate_gbs(torch, mib=1024, reps=10):
+    """Bytes moved per second (read + write) by a plain device-to-device copy of `mib` MiB
+    (torch's copy_, one hipMemcpyAsync): the HBM rate a streaming kernel reaches on this
+    GPU, reported beside the roofline as context."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * n * 4 / (ms / 1e3) / 1e9
+
+
 def sweep_event_ms(torch, plan, state, n):
     """Average and median duration of the frame-sweep kernel over n further iterations, from
     event pairs the kernel itself records at its start and end on its launch stream
@@ -678,6 +700,9 @@ def main() -> int:
             "traffic": head["sweep_roofline"]["traffic"],
             "algorithmic_bytes_per_launch": head["sweep_algorithmic_bytes"],
             "avg_launch_ms": head["sweep_ms"],
+            "traffic_rate_GBps": (head["sweep_roofline"]["traffic"] / (head["sweep_ms"] / 1e3) / 1e9
+                                  if head["sweep_roofline"]["traffic"] else None),
+            "plain_copy_GBps": copy_rate_gbs(torch),
         },
         "transforms": c5["out"],
     }

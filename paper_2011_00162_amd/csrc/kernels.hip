@@ -233,42 +233,59 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
   for (int h = 0; h < 2; ++h) {
     if constexpr (MF) M::half_fwd(v, lds, a.mft, t, h);
     else F::half_fwd<TWL>(v, lds, twl, t, h);
-    // amplitudes and multipliers in two groups of 8 (each group's loads before its
-    // stores); the other frame on the CU computes meanwhile
+    // the other half's 16 values wait in the LDS buffer, idle between the stage-C reads
+    // and the inverse; the 32 registers they free let all 16 amplitude and multiplier
+    // loads of this half be in flight at once
+    auto slot = [&](int hh, int k) { return MF ? 4 * (k >> 1) + 2 * hh + (k & 1) : 16 * (k >> 3) + 8 * hh + (k & 7); };
+    static_assert(16 * F::T <= F::LDS, "the parked half fits the LDS buffer");
+    float4* park = reinterpret_cast<float4*>(lds);   // 8 x 512 float4 of the 64-row buffer
+    __syncthreads();                                 // every thread's stage-C reads are done
 #pragma unroll
-    for (int qq = 0; qq < 2; ++qq) {
-      float2 gpre[8];
-      float spre[8];
+    for (int k = 0; k < 8; ++k) {
+      const float2 x0 = v[slot(1 - h, 2 * k)], x1 = v[slot(1 - h, 2 * k + 1)];
+      park[k * F::T + t] = make_float4(x0.x, x0.y, x1.x, x1.y);
+    }
+    asm volatile("" ::: "memory");
+    float2 gpre[16];
+    float spre[16];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        int kr, kc;
-        F::freq(t, 16 * qq + 8 * h + i, kr, kc);
-        spre[i] = sb[(uint32_t)(kr * P + kc)];
-        gpre[i] = gb[(uint32_t)(kr * P + kc)];
+    for (int k = 0; k < 16; ++k) {
+      int kr, kc;
+      F::freq(t, 16 * (k >> 3) + 8 * h + (k & 7), kr, kc);
+      spre[k] = sb[(uint32_t)(kr * P + kc)];
+      gpre[k] = gb[(uint32_t)(kr * P + kc)];
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int e = slot(h, k);
+      const float2 X = c_scale(v[e], inv_p);
+      const float sf = spre[k];
+      const float2 y = c_add(gpre[k], X);
+      const float2 z = prox_stagm(y, sf, pc);
+      const float2 g = c_sub(y, z);
+      if (STATS) {
+        const double ax = sqrt((double)X.x * X.x + (double)X.y * X.y);
+        mis += fabs(ax - (double)sf);
+        gsum += g_eps(ax, (double)sf, (double)a.eps);
+        if (ST > 1) frame_terms(gpre[k], g, gdel, gnrm);
       }
+      gpre[k] = g;
+      v[e] = c_scale(c_sub(z, g), inv_p);   // both 1/p factors of the unitary pair applied here
+    }
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int e = MF ? M::fslot(h, qq, i) : 16 * qq + 8 * h + i;
-        const float2 X = c_scale(v[e], inv_p);
-        const float sf = spre[i];
-        const float2 y = c_add(gpre[i], X);
-        const float2 z = prox_stagm(y, sf, pc);
-        const float2 g = c_sub(y, z);
-        if (STATS) {
-          const double ax = sqrt((double)X.x * X.x + (double)X.y * X.y);
-          mis += fabs(ax - (double)sf);
-          gsum += g_eps(ax, (double)sf, (double)a.eps);
-          if (ST > 1) frame_terms(gpre[i], g, gdel, gnrm);
-        }
-        gpre[i] = g;
-        v[e] = c_scale(c_sub(z, g), inv_p);   // both 1/p factors of the unitary pair applied here
-      }
+    for (int k = 0; k < 16; ++k) {
+      int kr, kc;
+      F::freq(t, 16 * (k >> 3) + 8 * h + (k & 7), kr, kc);
+      gb[(uint32_t)(kr * P + kc)] = gpre[k];
+    }
+    asm volatile("" ::: "memory");
+    // each thread reads back only what it wrote; half_inv's leading barrier orders these
+    // reads before its first LDS writes
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        int kr, kc;
-        F::freq(t, 16 * qq + 8 * h + i, kr, kc);
-        gb[(uint32_t)(kr * P + kc)] = gpre[i];
-      }
+    for (int k = 0; k < 8; ++k) {
+      const float4 x = park[k * F::T + t];
+      v[slot(1 - h, 2 * k)] = make_float2(x.x, x.y);
+      v[slot(1 - h, 2 * k + 1)] = make_float2(x.z, x.w);
     }
     if constexpr (MF) M::half_inv(v, lds, a.mft, t, h);
     else F::half_inv<TWL>(v, lds, twl, t, h);
