@@ -42,6 +42,20 @@ __device__ __forceinline__ float2 c_mulc(float2 a, float2 b) {
   return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
 __device__ __forceinline__ float2 c_scale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// Streaming accesses (non-temporal hint): data touched once per sweep (amplitudes,
+// multipliers, the handoff) should not push the reused image windows out of L2.
+typedef float odp_f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float ld_nt(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float2 ld_nt(const float2* p) {
+  const odp_f2v x = __builtin_nontemporal_load(reinterpret_cast<const odp_f2v*>(p));
+  return make_float2(x.x, x.y);
+}
+__device__ __forceinline__ void st_nt(float2* p, float2 v) {
+  odp_f2v x;
+  x.x = v.x;
+  x.y = v.y;
+  __builtin_nontemporal_store(x, reinterpret_cast<odp_f2v*>(p));
+}
 // multiply by -i (forward) or +i (inverse)
 template <bool INV>
 __device__ __forceinline__ float2 c_rot(float2 a) {

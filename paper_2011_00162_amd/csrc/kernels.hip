@@ -252,8 +252,8 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
     for (int k = 0; k < 16; ++k) {
       int kr, kc;
       F::freq(t, 16 * (k >> 3) + 8 * h + (k & 7), kr, kc);
-      spre[k] = sb[(uint32_t)(kr * P + kc)];
-      gpre[k] = gb[(uint32_t)(kr * P + kc)];
+      spre[k] = ld_nt(sb + (uint32_t)(kr * P + kc));
+      gpre[k] = ld_nt(gb + (uint32_t)(kr * P + kc));
     }
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
     for (int k = 0; k < 16; ++k) {
       int kr, kc;
       F::freq(t, 16 * (k >> 3) + 8 * h + (k & 7), kr, kc);
-      gb[(uint32_t)(kr * P + kc)] = gpre[k];
+      st_nt(gb + (uint32_t)(kr * P + kc), gpre[k]);
     }
     asm volatile("" ::: "memory");
     // each thread reads back only what it wrote; half_inv's leading barrier orders these
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
       for (int i = 0; i < 8; ++i) {
         const int e = 8 * grp + i;
         const float2 x = BLIND ? v[e] : c_mulc(v[e], wk[i]);
-        pb[(uint32_t)(M::row(t, e) * P + M::col(t, e))] = x;
+        st_nt(pb + (uint32_t)(M::row(t, e) * P + M::col(t, e)), x);
       }
     }
     return;
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
       }
     }
 #pragma unroll
-    for (int r1 = 0; r1 < 16; ++r1) pb[(uint32_t)(F::row_of(t, 16 * l + r1) * P + col)] = v[16 * l + r1];
+    for (int r1 = 0; r1 < 16; ++r1) st_nt(pb + (uint32_t)(F::row_of(t, 16 * l + r1) * P + col), v[16 * l + r1]);
   }
 }
 
