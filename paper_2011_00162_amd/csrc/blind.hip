@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void k_probe_copies(ProbeArgs a) {
     for (int i = 0; i < B; ++i) {
       const FrameDesc f = a.fpos[q + i];
       pu[i] = a.u[f.base + (int64_t)ky * f.pitch + kx];
-      ph[i] = a.phi[(size_t)f.j * pp + kk];
+      ph[i] = ld_nt(a.phi + (size_t)f.j * pp + kk);   // read here and once more by the U-step
     }
   };
   const int q1 = a.sub_first[d + 1];
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void k_probe_copies(ProbeArgs a) {
   }
   for (; q < q1; ++q) {
     const FrameDesc fd = a.fpos[q];
-    acc(a.u[fd.base + (int64_t)ky * fd.pitch + kx], a.phi[(size_t)fd.j * pp + kk]);
+    acc(a.u[fd.base + (int64_t)ky * fd.pitch + kx], ld_nt(a.phi + (size_t)fd.j * pp + kk));
   }
   if (!ok) return;
   const size_t o = (size_t)d * pp + k;

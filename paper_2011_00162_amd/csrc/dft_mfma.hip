@@ -235,9 +235,9 @@ __global__ __launch_bounds__(256, WGS_PER_CU) void k_sweep_dft64(SweepArgs a, Df
     float4 sfq[4], gq0[4], gq1[4];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
-      sfq[mt] = *reinterpret_cast<const float4*>(a.sqrt_f + rowb + 16 * mt);
-      gq0[mt] = reinterpret_cast<const float4*>(a.gamma + rowb + 16 * mt)[0];
-      gq1[mt] = reinterpret_cast<const float4*>(a.gamma + rowb + 16 * mt)[1];
+      sfq[mt] = ld_nt(reinterpret_cast<const float4*>(a.sqrt_f + rowb + 16 * mt));
+      gq0[mt] = ld_nt(reinterpret_cast<const float4*>(a.gamma + rowb + 16 * mt));
+      gq1[mt] = ld_nt(reinterpret_cast<const float4*>(a.gamma + rowb + 16 * mt) + 1);
     }
 
     // product 2: X^^T[kc][kr] = sum_c F[kc][c] Y^T[c][kr]; B = product 1's tiles (pi order)
@@ -289,8 +289,8 @@ __global__ __launch_bounds__(256, WGS_PER_CU) void k_sweep_dft64(SweepArgs a, Df
             if (ST > 1) frame_terms(gv[i], gn[i], gdel, gnrm);
           }
         }
-        gp[0] = make_float4(gn[0].x, gn[0].y, gn[1].x, gn[1].y);
-        gp[1] = make_float4(gn[2].x, gn[2].y, gn[3].x, gn[3].y);
+        st_nt(gp, make_float4(gn[0].x, gn[0].y, gn[1].x, gn[1].y));
+        st_nt(gp + 1, make_float4(gn[2].x, gn[2].y, gn[3].x, gn[3].y));
       }
     }
     if (STATS) frame_stats<256, (ST > 1)>(a.part + NFS * (size_t)j, mis, gsum, gdel, gnrm, red);
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(256, WGS_PER_CU) void k_sweep_dft64(SweepArgs a, Df
       for (int i = 0; i < 4; ++i) {
         const int r = 16 * w + 4 * g + i, c = 16 * nt + n0;
         const float2 x = make_float2(xre[i], xim[i]);
-        a.psi[fbase + r * DP + c] = BLIND ? x : c_mulc(x, wq[nt][i]);
+        st_nt(a.psi + fbase + r * DP + c, BLIND ? x : c_mulc(x, wq[nt][i]));
       }
     }
   }

@@ -56,6 +56,19 @@ __device__ __forceinline__ void st_nt(float2* p, float2 v) {
   x.y = v.y;
   __builtin_nontemporal_store(x, reinterpret_cast<odp_f2v*>(p));
 }
+typedef float odp_f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld_nt(const float4* p) {
+  const odp_f4v x = __builtin_nontemporal_load(reinterpret_cast<const odp_f4v*>(p));
+  return make_float4(x.x, x.y, x.z, x.w);
+}
+__device__ __forceinline__ void st_nt(float4* p, float4 v) {
+  odp_f4v x;
+  x.x = v.x;
+  x.y = v.y;
+  x.z = v.z;
+  x.w = v.w;
+  __builtin_nontemporal_store(x, reinterpret_cast<odp_f4v*>(p));
+}
 // multiply by -i (forward) or +i (inverse)
 template <bool INV>
 __device__ __forceinline__ float2 c_rot(float2 a) {

@@ -90,8 +90,8 @@ __global__ __launch_bounds__(Frame<P>::T, MF && P == 64 && ST == 0 ? 4 : 1) void
   for (int e = 0; e < 16; ++e) {
     int kr, kc;
     F::freq(t, e, kr, kc);
-    if (PRE >= 1) spre[e] = a.sqrt_f[fbase + kr * P + kc];
-    if (PRE >= 2) gpre[e] = a.gamma[fbase + kr * P + kc];
+    if (PRE >= 1) spre[e] = ld_nt(a.sqrt_f + fbase + kr * P + kc);
+    if (PRE >= 2) gpre[e] = ld_nt(a.gamma + fbase + kr * P + kc);
   }
   if constexpr (MF) M::forward_bc(v, lds, a.mft, t);
   else F::template forward_bc<TWL>(v, lds, twl, t);
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(Frame<P>::T, MF && P == 64 && ST == 0 ? 4 : 1) void
     for (int e = 0; e < 16; ++e) {
       int kr, kc;
       F::freq(t, e, kr, kc);
-      gpre[e] = a.gamma[fbase + kr * P + kc];
+      gpre[e] = ld_nt(a.gamma + fbase + kr * P + kc);
     }
   }
   double mis = 0.0, gsum = 0.0, gdel = 0.0, gnrm = 0.0;
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(Frame<P>::T, MF && P == 64 && ST == 0 ? 4 : 1) void
     F::freq(t, e, kr, kc);
     const size_t idx = fbase + kr * P + kc;
     const float2 X = c_scale(v[e], inv_p);
-    const float sf = PRE >= 1 ? spre[e] : a.sqrt_f[idx];
+    const float sf = PRE >= 1 ? spre[e] : ld_nt(a.sqrt_f + idx);
     const float2 y = c_add(gpre[e], X);
     const float2 z = prox_stagm(y, sf, pc);
     const float2 g = c_sub(y, z);
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(Frame<P>::T, MF && P == 64 && ST == 0 ? 4 : 1) void
   for (int e = 0; e < 16; ++e) {
     int kr, kc;
     F::freq(t, e, kr, kc);
-    a.gamma[fbase + kr * P + kc] = gpre[e];
+    st_nt(a.gamma + fbase + kr * P + kc, gpre[e]);
   }
   if (STATS) frame_stats<F::T, (ST > 1)>(a.part + NFS * (size_t)j, mis, gsum, gdel, gnrm, red);
   __syncthreads();  // stage-C reads of all threads done before inverse writes reuse LDS
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(Frame<P>::T, MF && P == 64 && ST == 0 ? 4 : 1) void
     for (int e = 0; e < 16; ++e) v[e] = c_mulc(v[e], wk[e]);
   }
 #pragma unroll
-  for (int e = 0; e < 16; ++e) a.psi[fbase + prow(e) * P + pcol(e)] = v[e];
+  for (int e = 0; e < 16; ++e) st_nt(a.psi + fbase + prow(e) * P + pcol(e), v[e]);
 }
 
 // K1 at p = 128: the same step on the two-half transform (Half128: 512 threads,

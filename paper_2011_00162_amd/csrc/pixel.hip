@@ -70,7 +70,7 @@ __device__ __forceinline__ void pull_pixels(const PullEntry* __restrict__ pull, 
         ps[q][h] = make_float2(0.f, 0.f);
         ww[q][h] = make_float2(0.f, 0.f);
         if (in[q][h]) {
-          ps[q][h] = *reinterpret_cast<const float2*>(fb + pix8[h]);
+          ps[q][h] = ld_nt(reinterpret_cast<const float2*>(fb + pix8[h]));
           if (BLIND) ww[q][h] = ws[dy * p + dx];
         }
       }
