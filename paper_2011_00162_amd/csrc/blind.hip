@@ -78,6 +78,7 @@ __global__ __launch_bounds__(Frame<P>::T) void k_probe_project(ProbeArgs a) {
 // contiguous of each frame's phi and of its u window rows.  The next group's loads are
 // issued before the current group is summed (two groups in registers), which keeps the
 // loads in flight while the FP64 sums run.
+template <bool NT>
 __global__ __launch_bounds__(256) void k_probe_copies(ProbeArgs a) {
   if (a.stop && a.stop[0].stopped) return;  // uniform over the workgroup
   constexpr int B = 8;
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(256) void k_probe_copies(ProbeArgs a) {
     for (int i = 0; i < B; ++i) {
       const FrameDesc f = a.fpos[q + i];
       pu[i] = a.u[f.base + (int64_t)ky * f.pitch + kx];
-      ph[i] = ld_nt(a.phi + (size_t)f.j * pp + kk);   // read here and once more by the U-step
+      ph[i] = ld_s<NT>(a.phi + (size_t)f.j * pp + kk);   // read here and once more by the U-step
     }
   };
   const int q1 = a.sub_first[d + 1];
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(256) void k_probe_copies(ProbeArgs a) {
   }
   for (; q < q1; ++q) {
     const FrameDesc fd = a.fpos[q];
-    acc(a.u[fd.base + (int64_t)ky * fd.pitch + kx], ld_nt(a.phi + (size_t)fd.j * pp + kk));
+    acc(a.u[fd.base + (int64_t)ky * fd.pitch + kx], ld_s<NT>(a.phi + (size_t)fd.j * pp + kk));
   }
   if (!ok) return;
   const size_t o = (size_t)d * pp + k;
@@ -269,7 +270,8 @@ hipError_t launch_probe_update(const ProbeArgs& a, hipStream_t s) {
     ODP_PROJ(128)
 #undef ODP_PROJ
   }
-  hipLaunchKernelGGL(k_probe_copies, dim3((pp + 255) / 256, a.D), dim3(256), 0, s, a);
+  if (a.stream) hipLaunchKernelGGL(k_probe_copies<true>, dim3((pp + 255) / 256, a.D), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_probe_copies<false>, dim3((pp + 255) / 256, a.D), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

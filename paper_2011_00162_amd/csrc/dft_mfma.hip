@@ -39,6 +39,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "fft_frame.hpp"
 #include "odp_internal.hpp"
@@ -139,7 +140,7 @@ __device__ __forceinline__ void cmma(floatx4& re, floatx4& im, const CS& a, cons
 }  // namespace
 
 // ST: 0 no statistics, 1 the iteration's measures, 2 also the frame residuals
-template <bool BLIND, int ST>
+template <bool BLIND, int ST, bool NT>
 __global__ __launch_bounds__(256, WGS_PER_CU) void k_sweep_dft64(SweepArgs a, DftTable dt, ProxC pc) {
   constexpr bool STATS = ST > 0;
   __shared__ __attribute__((aligned(16))) __bf16 ft[4 * PL];   // F: re hi, re lo, im hi, im lo
@@ -235,9 +236,9 @@ __global__ __launch_bounds__(256, WGS_PER_CU) void k_sweep_dft64(SweepArgs a, Df
     float4 sfq[4], gq0[4], gq1[4];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
-      sfq[mt] = ld_nt(reinterpret_cast<const float4*>(a.sqrt_f + rowb + 16 * mt));
-      gq0[mt] = ld_nt(reinterpret_cast<const float4*>(a.gamma + rowb + 16 * mt));
-      gq1[mt] = ld_nt(reinterpret_cast<const float4*>(a.gamma + rowb + 16 * mt) + 1);
+      sfq[mt] = ld_s<NT>(reinterpret_cast<const float4*>(a.sqrt_f + rowb + 16 * mt));
+      gq0[mt] = ld_s<NT>(reinterpret_cast<const float4*>(a.gamma + rowb + 16 * mt));
+      gq1[mt] = ld_s<NT>(reinterpret_cast<const float4*>(a.gamma + rowb + 16 * mt) + 1);
     }
 
     // product 2: X^^T[kc][kr] = sum_c F[kc][c] Y^T[c][kr]; B = product 1's tiles (pi order)
@@ -289,8 +290,8 @@ __global__ __launch_bounds__(256, WGS_PER_CU) void k_sweep_dft64(SweepArgs a, Df
             if (ST > 1) frame_terms(gv[i], gn[i], gdel, gnrm);
           }
         }
-        st_nt(gp, make_float4(gn[0].x, gn[0].y, gn[1].x, gn[1].y));
-        st_nt(gp + 1, make_float4(gn[2].x, gn[2].y, gn[3].x, gn[3].y));
+        st_s<NT>(gp, make_float4(gn[0].x, gn[0].y, gn[1].x, gn[1].y));
+        st_s<NT>(gp + 1, make_float4(gn[2].x, gn[2].y, gn[3].x, gn[3].y));
       }
     }
     if (STATS) frame_stats<256, (ST > 1)>(a.part + NFS * (size_t)j, mis, gsum, gdel, gnrm, red);
@@ -364,7 +365,7 @@ __global__ __launch_bounds__(256, WGS_PER_CU) void k_sweep_dft64(SweepArgs a, Df
       for (int i = 0; i < 4; ++i) {
         const int r = 16 * w + 4 * g + i, c = 16 * nt + n0;
         const float2 x = make_float2(xre[i], xim[i]);
-        st_nt(a.psi + fbase + r * DP + c, BLIND ? x : c_mulc(x, wq[nt][i]));
+        st_s<NT>(a.psi + fbase + r * DP + c, BLIND ? x : c_mulc(x, wq[nt][i]));
       }
     }
   }
@@ -381,11 +382,16 @@ hipError_t launch_sweep_dft(int p, const SweepArgs& a, const DftTable& dt, hipSt
   const dim3 grid(G), blk(256);
   const bool bl = a.blind != 0;
   const int st = a.part == nullptr ? 0 : (a.frame_res && !bl ? 2 : 1);
-  if (bl && st) hipExtLaunchKernelGGL((k_sweep_dft64<true, 1>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
-  else if (bl) hipExtLaunchKernelGGL((k_sweep_dft64<true, 0>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
-  else if (st == 2) hipExtLaunchKernelGGL((k_sweep_dft64<false, 2>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
-  else if (st) hipExtLaunchKernelGGL((k_sweep_dft64<false, 1>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
-  else hipExtLaunchKernelGGL((k_sweep_dft64<false, 0>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
+  auto go = [&](auto nt) {
+    constexpr bool NT = decltype(nt)::value;
+    if (bl && st) hipExtLaunchKernelGGL((k_sweep_dft64<true, 1, NT>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
+    else if (bl) hipExtLaunchKernelGGL((k_sweep_dft64<true, 0, NT>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
+    else if (st == 2) hipExtLaunchKernelGGL((k_sweep_dft64<false, 2, NT>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
+    else if (st) hipExtLaunchKernelGGL((k_sweep_dft64<false, 1, NT>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
+    else hipExtLaunchKernelGGL((k_sweep_dft64<false, 0, NT>), grid, blk, 0, s, ev0, ev1, 0, a, dt, pc);
+  };
+  if (a.stream) go(std::true_type{});
+  else go(std::false_type{});
   return hipGetLastError();
 }
 

@@ -42,8 +42,11 @@ __device__ __forceinline__ float2 c_mulc(float2 a, float2 b) {
   return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
 __device__ __forceinline__ float2 c_scale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
-// Streaming accesses (non-temporal hint): data touched once per sweep (amplitudes,
-// multipliers, the handoff) should not push the reused image windows out of L2.
+// Streaming accesses (non-temporal hint) for the frame arrays a sweep touches once
+// (amplitudes, multipliers, the handoff) when they are far larger than the last-level
+// cache: they then do not push the reused image windows out of L2.  When the frame
+// arrays fit in the 256 MB Infinity Cache, they stay there from one iteration to the
+// next with ordinary accesses, which the hint would defeat; ld_s / st_s pick by NT.
 typedef float odp_f2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float ld_nt(const float* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ float2 ld_nt(const float2* p) {
@@ -68,6 +71,16 @@ __device__ __forceinline__ void st_nt(float4* p, float4 v) {
   x.z = v.z;
   x.w = v.w;
   __builtin_nontemporal_store(x, reinterpret_cast<odp_f4v*>(p));
+}
+template <bool NT, class T>
+__device__ __forceinline__ T ld_s(const T* p) {
+  if constexpr (NT) return ld_nt(p);
+  else return *p;
+}
+template <bool NT, class T>
+__device__ __forceinline__ void st_s(T* p, T v) {
+  if constexpr (NT) st_nt(p, v);
+  else *p = v;
 }
 // multiply by -i (forward) or +i (inverse)
 template <bool INV>

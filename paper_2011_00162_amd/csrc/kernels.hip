@@ -42,7 +42,8 @@ __device__ __forceinline__ int sweep_pos(int32_t chunk, int xcd_slice) {
 // ---------------------------------------------------------------------------
 // ST: 0 no statistics, 1 the iteration's measures, 2 also the frame residuals.
 // MF: radix-16 stages on the matrix cores (FrameMF, split BF16), else Frame's FP32 stages.
-template <int P, bool MF, bool BLIND, int ST>
+// NT: streaming (non-temporal) accesses to the frame arrays (ld_s / st_s).
+template <int P, bool MF, bool BLIND, int ST, bool NT>
 __global__ __launch_bounds__(Frame<P>::T, MF && P == 64 && ST == 0 ? 4 : 1) void k_sweep(SweepArgs a, ProxC pc) {
   using F = Frame<P>;
   using M = FrameMF<P>;    // instantiated only when MF
@@ -90,8 +91,8 @@ __global__ __launch_bounds__(Frame<P>::T, MF && P == 64 && ST == 0 ? 4 : 1) void
   for (int e = 0; e < 16; ++e) {
     int kr, kc;
     F::freq(t, e, kr, kc);
-    if (PRE >= 1) spre[e] = ld_nt(a.sqrt_f + fbase + kr * P + kc);
-    if (PRE >= 2) gpre[e] = ld_nt(a.gamma + fbase + kr * P + kc);
+    if (PRE >= 1) spre[e] = ld_s<NT>(a.sqrt_f + fbase + kr * P + kc);
+    if (PRE >= 2) gpre[e] = ld_s<NT>(a.gamma + fbase + kr * P + kc);
   }
   if constexpr (MF) M::forward_bc(v, lds, a.mft, t);
   else F::template forward_bc<TWL>(v, lds, twl, t);
@@ -103,7 +104,7 @@ __global__ __launch_bounds__(Frame<P>::T, MF && P == 64 && ST == 0 ? 4 : 1) void
     for (int e = 0; e < 16; ++e) {
       int kr, kc;
       F::freq(t, e, kr, kc);
-      gpre[e] = ld_nt(a.gamma + fbase + kr * P + kc);
+      gpre[e] = ld_s<NT>(a.gamma + fbase + kr * P + kc);
     }
   }
   double mis = 0.0, gsum = 0.0, gdel = 0.0, gnrm = 0.0;
@@ -113,7 +114,7 @@ __global__ __launch_bounds__(Frame<P>::T, MF && P == 64 && ST == 0 ? 4 : 1) void
     F::freq(t, e, kr, kc);
     const size_t idx = fbase + kr * P + kc;
     const float2 X = c_scale(v[e], inv_p);
-    const float sf = PRE >= 1 ? spre[e] : ld_nt(a.sqrt_f + idx);
+    const float sf = PRE >= 1 ? spre[e] : ld_s<NT>(a.sqrt_f + idx);
     const float2 y = c_add(gpre[e], X);
     const float2 z = prox_stagm(y, sf, pc);
     const float2 g = c_sub(y, z);
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(Frame<P>::T, MF && P == 64 && ST == 0 ? 4 : 1) void
   for (int e = 0; e < 16; ++e) {
     int kr, kc;
     F::freq(t, e, kr, kc);
-    st_nt(a.gamma + fbase + kr * P + kc, gpre[e]);
+    st_s<NT>(a.gamma + fbase + kr * P + kc, gpre[e]);
   }
   if (STATS) frame_stats<F::T, (ST > 1)>(a.part + NFS * (size_t)j, mis, gsum, gdel, gnrm, red);
   __syncthreads();  // stage-C reads of all threads done before inverse writes reuse LDS
@@ -147,14 +148,14 @@ __global__ __launch_bounds__(Frame<P>::T, MF && P == 64 && ST == 0 ? 4 : 1) void
     for (int e = 0; e < 16; ++e) v[e] = c_mulc(v[e], wk[e]);
   }
 #pragma unroll
-  for (int e = 0; e < 16; ++e) st_nt(a.psi + fbase + prow(e) * P + pcol(e), v[e]);
+  for (int e = 0; e < 16; ++e) st_s<NT>(a.psi + fbase + prow(e) * P + pcol(e), v[e]);
 }
 
 // K1 at p = 128: the same step on the two-half transform (Half128: 512 threads,
 // 77 KB of LDS, two frames per CU).  The prox of each half runs between that half's
 // forward and inverse stages B and C.
 // MF: stages A and B on the matrix cores (Half128MF, split BF16).
-template <bool MF, bool BLIND, int ST>
+template <bool MF, bool BLIND, int ST, bool NT>
 __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_sweep128(SweepArgs a, ProxC pc) {
   using F = Half128;
   using M = Half128MF;
@@ -239,11 +240,16 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
     auto slot = [&](int hh, int k) { return MF ? 4 * (k >> 1) + 2 * hh + (k & 1) : 16 * (k >> 3) + 8 * hh + (k & 7); };
     static_assert(16 * F::T <= F::LDS, "the parked half fits the LDS buffer");
     float4* park = reinterpret_cast<float4*>(lds);   // 8 x 512 float4 of the 64-row buffer
+    // the frequency offsets below are computed here from an opaque copy of the thread
+    // index: hoisted to the start of the kernel they would stay live across the
+    // transforms and spill
+    int tq = t;
+    asm volatile("" : "+v"(tq));
     __syncthreads();                                 // every thread's stage-C reads are done
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const float2 x0 = v[slot(1 - h, 2 * k)], x1 = v[slot(1 - h, 2 * k + 1)];
-      park[k * F::T + t] = make_float4(x0.x, x0.y, x1.x, x1.y);
+      park[k * F::T + tq] = make_float4(x0.x, x0.y, x1.x, x1.y);
     }
     asm volatile("" ::: "memory");
     float2 gpre[16];
@@ -251,9 +257,9 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       int kr, kc;
-      F::freq(t, 16 * (k >> 3) + 8 * h + (k & 7), kr, kc);
-      spre[k] = ld_nt(sb + (uint32_t)(kr * P + kc));
-      gpre[k] = ld_nt(gb + (uint32_t)(kr * P + kc));
+      F::freq(tq, 16 * (k >> 3) + 8 * h + (k & 7), kr, kc);
+      spre[k] = ld_s<NT>(sb + (uint32_t)(kr * P + kc));
+      gpre[k] = ld_s<NT>(gb + (uint32_t)(kr * P + kc));
     }
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
@@ -275,15 +281,15 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       int kr, kc;
-      F::freq(t, 16 * (k >> 3) + 8 * h + (k & 7), kr, kc);
-      st_nt(gb + (uint32_t)(kr * P + kc), gpre[k]);
+      F::freq(tq, 16 * (k >> 3) + 8 * h + (k & 7), kr, kc);
+      st_s<NT>(gb + (uint32_t)(kr * P + kc), gpre[k]);
     }
     asm volatile("" ::: "memory");
     // each thread reads back only what it wrote; half_inv's leading barrier orders these
     // reads before its first LDS writes
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const float4 x = park[k * F::T + t];
+      const float4 x = park[k * F::T + tq];
       v[slot(1 - h, 2 * k)] = make_float2(x.x, x.y);
       v[slot(1 - h, 2 * k + 1)] = make_float2(x.z, x.w);
     }
@@ -311,7 +317,7 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
       for (int i = 0; i < 8; ++i) {
         const int e = 8 * grp + i;
         const float2 x = BLIND ? v[e] : c_mulc(v[e], wk[i]);
-        st_nt(pb + (uint32_t)(M::row(t, e) * P + M::col(t, e)), x);
+        st_s<NT>(pb + (uint32_t)(M::row(t, e) * P + M::col(t, e)), x);
       }
     }
     return;
@@ -334,52 +340,51 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
       }
     }
 #pragma unroll
-    for (int r1 = 0; r1 < 16; ++r1) st_nt(pb + (uint32_t)(F::row_of(t, 16 * l + r1) * P + col), v[16 * l + r1]);
+    for (int r1 = 0; r1 < 16; ++r1) st_s<NT>(pb + (uint32_t)(F::row_of(t, 16 * l + r1) * P + col), v[16 * l + r1]);
   }
+}
+
+// the five statistics / blind variants of one sweep kernel
+template <int P, bool MF, bool NT>
+static hipError_t go_sweep(const SweepArgs& a, const ProxC& pc, dim3 grid, hipStream_t s, hipEvent_t ev0,
+                           hipEvent_t ev1) {
+  const bool bl = a.blind != 0;
+  const int st = a.part == nullptr ? 0 : (a.frame_res && !bl ? 2 : 1);
+#define ODP_SWEEP_GO(K, T) hipExtLaunchKernelGGL(K, grid, dim3(T), 0, s, ev0, ev1, 0, a, pc)
+  if constexpr (P == 128) {
+    constexpr int T = Half128::T;
+    if (bl && st) ODP_SWEEP_GO((k_sweep128<MF, true, 1, NT>), T);
+    else if (bl) ODP_SWEEP_GO((k_sweep128<MF, true, 0, NT>), T);
+    else if (st == 2) ODP_SWEEP_GO((k_sweep128<MF, false, 2, NT>), T);
+    else if (st) ODP_SWEEP_GO((k_sweep128<MF, false, 1, NT>), T);
+    else ODP_SWEEP_GO((k_sweep128<MF, false, 0, NT>), T);
+  } else {
+    constexpr int T = Frame<P>::T;
+    if (bl && st) ODP_SWEEP_GO((k_sweep<P, MF, true, 1, NT>), T);
+    else if (bl) ODP_SWEEP_GO((k_sweep<P, MF, true, 0, NT>), T);
+    else if (st == 2) ODP_SWEEP_GO((k_sweep<P, MF, false, 2, NT>), T);
+    else if (st) ODP_SWEEP_GO((k_sweep<P, MF, false, 1, NT>), T);
+    else ODP_SWEEP_GO((k_sweep<P, MF, false, 0, NT>), T);
+  }
+#undef ODP_SWEEP_GO
+  return hipGetLastError();
 }
 
 hipError_t launch_sweep(int p, const SweepArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const ProxC pc = prox_coeffs(a.eps, a.eta);
   const dim3 grid(NXCD * a.chunk);
-  const bool bl = a.blind != 0;
-  const int st = a.part == nullptr ? 0 : (a.frame_res && !bl ? 2 : 1);
-#define ODP_SWEEP_GO(K, T) hipExtLaunchKernelGGL(K, grid, dim3(T), 0, s, ev0, ev1, 0, a, pc)
-#define ODP_SWEEP(PP, MF)                                                                    \
-  {                                                                                          \
-    constexpr int T = Frame<PP>::T;                                                          \
-    if (bl && st) ODP_SWEEP_GO((k_sweep<PP, MF, true, 1>), T);                               \
-    else if (bl) ODP_SWEEP_GO((k_sweep<PP, MF, true, 0>), T);                                \
-    else if (st == 2) ODP_SWEEP_GO((k_sweep<PP, MF, false, 2>), T);                          \
-    else if (st) ODP_SWEEP_GO((k_sweep<PP, MF, false, 1>), T);                               \
-    else ODP_SWEEP_GO((k_sweep<PP, MF, false, 0>), T);                                       \
-    return hipGetLastError();                                                                \
-  }
+  const bool nt = a.stream != 0;
+#define ODP_SWEEP(PP, MF) \
+  return nt ? go_sweep<PP, MF, true>(a, pc, grid, s, ev0, ev1) : go_sweep<PP, MF, false>(a, pc, grid, s, ev0, ev1);
   if (a.mft) {   // radix-16 stages on the matrix cores (hybrid transform)
     if (p == 64) ODP_SWEEP(64, true)
-    if (p == 128) {
-      constexpr int T = Half128MF::T;
-      if (bl && st) ODP_SWEEP_GO((k_sweep128<true, true, 1>), T);
-      else if (bl) ODP_SWEEP_GO((k_sweep128<true, true, 0>), T);
-      else if (st == 2) ODP_SWEEP_GO((k_sweep128<true, false, 2>), T);
-      else if (st) ODP_SWEEP_GO((k_sweep128<true, false, 1>), T);
-      else ODP_SWEEP_GO((k_sweep128<true, false, 0>), T);
-      return hipGetLastError();
-    }
+    if (p == 128) ODP_SWEEP(128, true)
     return hipErrorInvalidValue;
   }
   if (p == 32) ODP_SWEEP(32, false)
   if (p == 64) ODP_SWEEP(64, false)
-  if (p == 128) {
-    constexpr int T = Half128::T;
-    if (bl && st) ODP_SWEEP_GO((k_sweep128<false, true, 1>), T);
-    else if (bl) ODP_SWEEP_GO((k_sweep128<false, true, 0>), T);
-    else if (st == 2) ODP_SWEEP_GO((k_sweep128<false, false, 2>), T);
-    else if (st) ODP_SWEEP_GO((k_sweep128<false, false, 1>), T);
-    else ODP_SWEEP_GO((k_sweep128<false, false, 0>), T);
-    return hipGetLastError();
-  }
+  if (p == 128) ODP_SWEEP(128, false)
 #undef ODP_SWEEP
-#undef ODP_SWEEP_GO
   return hipErrorInvalidValue;
 }
 

@@ -69,6 +69,7 @@ static_assert(sizeof(StopStatus) == 32, "StopStatus layout");
 
 // ---------------------------------------------------------------- launch args
 struct SweepArgs {
+  int32_t stream;            // 1: non-temporal accesses to the frame arrays (see ld_s)
   const float2* u;           // u_sub
   const float2* w;           // probe [p][p] (non-blind) or copies [D][p][p] (blind)
   const float2* w_out;       // the same probe, read again for the output multiply
@@ -113,6 +114,7 @@ struct WaveRec {
 static_assert(sizeof(WaveRec) == 160, "WaveRec layout");
 
 struct PixelArgs {
+  int32_t stream;            // 1: non-temporal reads of the handoff
   float2* u;                 // u_sub (updated in place)
   const float* rcp;          // 1 / (eta den + r k + gamma); 0 = held pixel (non-blind)
   float2* lam;
@@ -175,6 +177,7 @@ hipError_t launch_copy(float2* dst, const float2* src, int64_t n, hipStream_t s)
 
 // blind (Alg. 3) probe steps
 struct ProbeArgs {
+  int32_t stream;            // 1: non-temporal reads of the handoff
   const float2* u;           // u_sub (iterate n)
   const float2* phi;         // F^{-1}(Z - Gamma) per frame
   const FrameDesc* frames;

@@ -45,7 +45,7 @@ __device__ __forceinline__ PullEntry load_entry(const PullEntry* e) {
 // 8 (y p + x) of pixel h, so a psi address is a per-record scalar base plus a
 // per-lane 32-bit offset.  Only lanes inside a window load; the others add 0, which
 // leaves the sum unchanged (it never holds -0).
-template <bool BLIND>
+template <bool BLIND, bool NT>
 __device__ __forceinline__ void pull_pixels(const PullEntry* __restrict__ pull, int k0, int k1,
                                             const float2* __restrict__ psi, const float2* __restrict__ ws,
                                             const int* yi, const int* xi, const uint32_t* pix8, int p,
@@ -70,7 +70,7 @@ __device__ __forceinline__ void pull_pixels(const PullEntry* __restrict__ pull, 
         ps[q][h] = make_float2(0.f, 0.f);
         ww[q][h] = make_float2(0.f, 0.f);
         if (in[q][h]) {
-          ps[q][h] = ld_nt(reinterpret_cast<const float2*>(fb + pix8[h]));
+          ps[q][h] = ld_s<NT>(reinterpret_cast<const float2*>(fb + pix8[h]));
           if (BLIND) ww[q][h] = ws[dy * p + dx];
         }
       }
@@ -167,7 +167,7 @@ __device__ __forceinline__ void residual_terms(int m, float2 un, float2 uo, cons
 // and takes its descriptor from its own WaveRec (scalar loads, one round trip).
 // The non-blind kernel is held to 80 VGPRs: six workgroups per CU keep all tiles of
 // a 512 x 512 problem with 4 x 4 subdomains resident at once.
-template <bool STATS, bool BLIND>
+template <bool STATS, bool BLIND, bool NT>
 __global__ __launch_bounds__(256, BLIND ? 1 : 6) void k_pixel_uni(PixelArgs a) {
   __shared__ double red[NPS][MAXS];
   constexpr int NO = 3;                          // partner copies at most
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256, BLIND ? 1 : 6) void k_pixel_uni(PixelArgs a) {
   uint32_t pix8[NPX];
 #pragma unroll
   for (int h = 0; h < NPX; ++h) pix8[h] = 8u * (uint32_t)(yi[h] * p + xi[h]);
-  pull_pixels<BLIND>(a.pull, w.k0, w.k1, a.psi, ws, yi, xi, pix8, p, num, den);
+  pull_pixels<BLIND, NT>(a.pull, w.k0, w.k1, a.psi, ws, yi, xi, pix8, p, num, den);
 
   float2 un[NPX], dv[NPX][NO];
   double sv[NPS] = {};
@@ -263,7 +263,7 @@ __device__ __forceinline__ int copy_groups_log2(int m) {
 // to MC - 1 partners until the barrier; the partners' iterate n is read partner by
 // partner.  MC = 8 runs the tiles [n_uni, n_mid) of cells with five to eight copies,
 // MC = MAXS the rest (the partner arrays, and so the registers, are sized by MC).
-template <bool STATS, bool BLIND, int MC>
+template <bool STATS, bool BLIND, int MC, bool NT>
 __global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
   __shared__ double red[NPS][MAXS];
   constexpr int NO = MC - 1;
@@ -308,7 +308,7 @@ __global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
   uint32_t pix8[NPX];
 #pragma unroll
   for (int h = 0; h < NPX; ++h) pix8[h] = 8u * (uint32_t)(yi[h] * p + xi[h]);
-  pull_pixels<BLIND>(a.pull, a.tf_first[tile * MAXS + s], a.tf_first[tile * MAXS + s + 1], a.psi, ws, yi, xi, pix8,
+  pull_pixels<BLIND, NT>(a.pull, a.tf_first[tile * MAXS + s], a.tf_first[tile * MAXS + s + 1], a.psi, ws, yi, xi, pix8,
                      p, num, den);
 #pragma unroll
   for (int h = 0; h < NPX; ++h) {
@@ -346,18 +346,23 @@ __global__ __launch_bounds__(256) void k_pixel(PixelArgs a) {
   if (STATS) pixel_stats(a, tile, m, tpg, sv, red);
 }
 
-hipError_t launch_pixel(const PixelArgs& a, bool stats, bool blind, hipStream_t s) {
+template <bool ST, bool BL, bool NT>
+static void go_pixel(const PixelArgs& a, hipStream_t s) {
   const dim3 b(256);
-#define ODP_PIXEL(ST, BL)                                                                            \
-  if (a.n_uni > 0) hipLaunchKernelGGL((k_pixel_uni<ST, BL>), dim3(a.n_uni), b, 0, s, a);             \
-  if (a.n_mid > a.n_uni) hipLaunchKernelGGL((k_pixel<ST, BL, 8>), dim3(a.n_mid - a.n_uni), b, 0, s, a);       \
-  if (a.n_tiles > a.n_mid) hipLaunchKernelGGL((k_pixel<ST, BL, MAXS>), dim3(a.n_tiles - a.n_mid), b, 0, s, a);
+  if (a.n_uni > 0) hipLaunchKernelGGL((k_pixel_uni<ST, BL, NT>), dim3(a.n_uni), b, 0, s, a);
+  if (a.n_mid > a.n_uni) hipLaunchKernelGGL((k_pixel<ST, BL, 8, NT>), dim3(a.n_mid - a.n_uni), b, 0, s, a);
+  if (a.n_tiles > a.n_mid) hipLaunchKernelGGL((k_pixel<ST, BL, MAXS, NT>), dim3(a.n_tiles - a.n_mid), b, 0, s, a);
+}
+
+hipError_t launch_pixel(const PixelArgs& a, bool stats, bool blind, hipStream_t s) {
+#define ODP_PIXEL(ST, BL) \
+  { if (a.stream) go_pixel<ST, BL, true>(a, s); else go_pixel<ST, BL, false>(a, s); }
   if (blind) {
-    if (stats) { ODP_PIXEL(true, true) }
-    else { ODP_PIXEL(false, true) }
+    if (stats) ODP_PIXEL(true, true)
+    else ODP_PIXEL(false, true)
   } else {
-    if (stats) { ODP_PIXEL(true, false) }
-    else { ODP_PIXEL(false, false) }
+    if (stats) ODP_PIXEL(true, false)
+    else ODP_PIXEL(false, false)
   }
 #undef ODP_PIXEL
   return hipGetLastError();

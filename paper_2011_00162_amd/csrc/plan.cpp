@@ -125,6 +125,7 @@ struct odp_plan {
   std::vector<uint16_t> dft;               // split-BF16 DFT matrix planes (transform = DFT)
   std::vector<uint16_t> mft;               // split-BF16 radix-16 stage matrices (hybrid transform)
   int32_t chunk = 0;
+  int32_t stream = 0;   // 1: non-temporal accesses to the frame arrays (set from their size)
   // workspace layout (byte offsets)
   struct {
     size_t tw, w, frames, fpos, order, sub_first, offsets, rects, usub_off, cells, tiles, waves, re_list, re_first,
@@ -351,6 +352,11 @@ int build_geometry(odp_plan* P) {
   for (int j = 0; j < J; ++j) P->sub_first[P->frame_sub[j] + 1]++;
   for (int d = 0; d < D; ++d) P->sub_first[d + 1] += P->sub_first[d];
   P->chunk = (J + NXCD - 1) / NXCD;
+  // The frame arrays an iteration streams (Gamma read and written, sqrt(f), the handoff
+  // written and read back: 28 B per frame pixel) are accessed with the non-temporal hint
+  // when they exceed the 256 MiB Infinity Cache of an MI355X; smaller ones stay in that
+  // cache from one iteration to the next with ordinary accesses.
+  P->stream = (double)J * P->p * P->p * 28.0 > 256.0 * (1 << 20) ? 1 : 0;
   static const int shapes[3][2] = {{16, 32}, {8, 64}, {32, 16}};
   for (int k = 0; k < 3; ++k) build_tiles(P, shapes[k][0], shapes[k][1], P->tsets[k]);
   P->covered = 0;
@@ -1028,6 +1034,7 @@ static SweepArgs sweep_args(const odp_plan* P, char* b, double* stats) {
   a.blind = P->blind;
   a.stop = P->stopping() ? reinterpret_cast<const StopStatus*>(b + P->st.stop) : nullptr;
   a.frame_res = P->balancing() && (P->bal_which & ODP_BALANCE_ETA) ? 1 : 0;
+  a.stream = P->stream;
   return a;
 }
 
@@ -1053,6 +1060,7 @@ static PixelArgs pixel_args(const odp_plan* P, char* b, double* stats) {
   a.part = stats || P->balancing() || P->stop_check(b) ? P->W_<double>(P->ws.tpart) : nullptr;
   a.dend = P->W_<double>(P->ws.den);
   a.stop = P->stopping() ? reinterpret_cast<const StopStatus*>(b + P->st.stop) : nullptr;
+  a.stream = P->stream;
   return a;
 }
 
@@ -1248,6 +1256,7 @@ int odp_probe_update(odp_plan* P, void* dev_state, hipStream_t s) {
   a.eta = P->eta;
   a.mu = P->mu;
   a.stop = P->stopping() ? reinterpret_cast<const StopStatus*>(b + P->st.stop) : nullptr;
+  a.stream = P->stream;
   ODP_HIP(launch_probe_update(a, s));
   return ODP_OK;
 }
