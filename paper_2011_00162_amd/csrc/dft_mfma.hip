@@ -264,8 +264,8 @@ __global__ __launch_bounds__(256, WGS_PER_CU) void k_sweep_dft64(SweepArgs a, Df
     }
 
     // prox and Gamma update at kr = 16w + n0, kc = 16 mt + 4g + i; xr/xi become t = z - Gamma
-    double mis = 0.0, gsum = 0.0, gdel = 0.0, gnrm = 0.0;
-    {
+    float mis = 0.f, gsum = 0.f, gdel = 0.f, gnrm = 0.f;   // the lane's 16 terms (FP64 across lanes)
+      {
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt) {
         float4* gp = reinterpret_cast<float4*>(a.gamma + rowb + 16 * mt);
@@ -284,9 +284,7 @@ __global__ __launch_bounds__(256, WGS_PER_CU) void k_sweep_dft64(SweepArgs a, Df
           xr[mt][i] = tv.x;
           xi[mt][i] = tv.y;
           if (STATS) {
-            const double ax = sqrt((double)X.x * X.x + (double)X.y * X.y);
-            mis += fabs(ax - (double)sfv[i]);
-            gsum += g_eps(ax, (double)sfv[i], (double)a.eps);
+            elem_measures(X, sfv[i], a.eps, a.gcoef, mis, gsum);
             if (ST > 1) frame_terms(gv[i], gn[i], gdel, gnrm);
           }
         }

@@ -84,6 +84,7 @@ struct SweepArgs {
   int32_t J, chunk;          // frames, frames per XCD slice
   int32_t xcd_slice;         // 1: workgroup b takes slice b % 8 of the order; 0: order[b]
   float eps, eta;
+  float gcoef;               // (1 - eps) / (2 eps), the measures' truncated g_eps branch
   double* part;              // [J][NFS] statistics (L1 misfit, G_eps, |Gamma^{n+1} - Gamma^n|^2,
                              //   |Gamma^{n+1}|^2) or null
   float2* psi;               // [J][p][p] per-frame output, natural spatial layout:

@@ -1029,6 +1029,7 @@ static SweepArgs sweep_args(const odp_plan* P, char* b, double* stats) {
   a.xcd_slice = P->xcd_slice;
   a.eps = (float)P->eps;
   a.eta = (float)P->eta;
+  a.gcoef = (float)(0.5 * (1.0 - P->eps) / P->eps);
   a.part = stats || P->balancing() || P->stop_check(b) ? P->W_<double>(P->ws.fpart) : nullptr;
   a.psi = P->W_<float2>(P->ws.psi);
   a.blind = P->blind;

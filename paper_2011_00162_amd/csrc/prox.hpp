@@ -34,9 +34,25 @@ __device__ __forceinline__ float2 prox_stagm(float2 y, float sf, const ProxC& c)
   return nz ? make_float2(y.x * s, y.y * s) : make_float2(rho, 0.0f);
 }
 
-// g_eps(x; b) of eq. obj-1 from |x| and sqrt(b), in FP64
-__device__ __forceinline__ double g_eps(double ax, double sb, double eps) {
-  return (ax < eps * sb) ? 0.5 * (1.0 - eps) * (sb * sb - ax * ax / eps) : 0.5 * (ax - sb) * (ax - sb);
+// One frame element's terms of the iteration's measures (Sec. 4): the misfit
+// | |X| - sqrt(f) | and g_eps(X; f), from the FP32 spectrum X in FP32 (|X| by the
+// hardware square root, about an ulp; g_eps is continuous where its branch switches, so
+// a switch near the threshold moves nothing).  gcoef = (1 - eps) / (2 eps): the truncated
+// branch is gcoef (eps f - |X|^2).  Branch-free; the caller sums a thread's terms of a
+// half frame in FP32 and adds that partial to its FP64 sums.
+__device__ __forceinline__ void elem_measures(float2 X, float sf, float eps, float gcoef, float& mis,
+                                              float& gsum) {
+  const float ax2 = fmaf(X.x, X.x, X.y * X.y);
+  const float ax = __builtin_amdgcn_sqrtf(ax2);
+  const float d = ax - sf;
+  const float esf = eps * sf;
+  const float gt = gcoef * fmaf(esf, sf, -ax2);
+  const float gq = 0.5f * d * d;
+  mis += fabsf(d);
+  gsum += ax < esf ? gt : gq;
+  // one element after the other: interleaving the terms of many elements (the
+  // scheduler's choice for an unrolled loop) holds all their temporaries at once
+  asm volatile("" : "+v"(mis), "+v"(gsum));
 }
 
 }  // namespace odp
