@@ -470,14 +470,26 @@ struct Half128 {
     dft16<true>(v + 16 * l);
   }
 
+  // LDS index of the k-th (k < 8) 128-bit pair of complex values that thread t reads in
+  // the last stage-C pass of a half (see half_fwd).  These pairs partition the buffer
+  // over the threads, so a thread may overwrite its own right after that pass without a
+  // barrier.
+  __device__ static __forceinline__ int own_pair(int t, int k) {
+    const int L = t + 512 * (k >> 2);
+    const int k1c = L & 15, k2r = (L >> 4) & 7, k1r = L >> 7;
+    return at(8 * k1r + k2r, 8 * k1c + 2 * (k & 3));
+  }
+
   // half h forward: stage-A outputs of the half into LDS, stages B and C, frequencies
   // back into the same slots.  Starts with a barrier (the LDS buffer may still be read
-  // by the previous half); ends after the stage-C reads (no barrier).
-  template <int TS>
+  // by the previous half) unless LEAD is false: a caller whose last LDS accesses before
+  // it were this thread's own final reads of half_inv (the same slots as the first
+  // writes here) needs none.  Ends after the stage-C reads (no barrier).
+  template <int TS, bool LEAD = true>
   __device__ static __forceinline__ void half_fwd(float2* v, float2* lds, const float2* __restrict__ twl, int t,
                                                   int h) {
     const int col = a_col(t), g = t >> 7;
-    __syncthreads();
+    if (LEAD) __syncthreads();
 #pragma unroll
     for (int l = 0; l < 2; ++l)
 #pragma unroll
@@ -515,12 +527,14 @@ struct Half128 {
   }
 
   // half h inverse: the exact reverse, ending with the stage-A inputs of the half back
-  // in their slots.  Starts with a barrier (the stage-C reads of the forward half);
-  // ends after the final LDS reads (no barrier).
-  template <int TS>
+  // in their slots.  Starts with a barrier (the stage-C reads of the forward half) unless
+  // LEAD is false: its first writes go to the thread's own_pair slots, which no other
+  // thread reads in the last stage-C pass, so a caller that touched no other LDS since
+  // then needs none.  Ends after the final LDS reads (no barrier).
+  template <int TS, bool LEAD = true>
   __device__ static __forceinline__ void half_inv(float2* v, float2* lds, const float2* __restrict__ twl, int t,
                                                   int h) {
-    __syncthreads();
+    if (LEAD) __syncthreads();
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int L = t + 512 * q;

@@ -232,12 +232,14 @@ struct Half128MF {
   }
 
   // half h forward: the half's stage-A outputs into LDS, stage B, stage C (FP32, as
-  // Half128), frequencies back into the half's slots.  Starts with a barrier; ends after
-  // the stage-C reads (no barrier).
+  // Half128), frequencies back into the half's slots.  Starts with a barrier unless LEAD
+  // is false (as Half128::half_fwd: the first writes here are the slots of this thread's
+  // final reads in half_inv); ends after the stage-C reads (no barrier).
+  template <bool LEAD = true>
   __device__ static __forceinline__ void half_fwd(float2* v, float2* lds, const uint4* __restrict__ tab, int t,
                                                   int h) {
     const int w = wave(t), lane = t & 63, g = lane >> 4, n0 = lane & 15;
-    __syncthreads();
+    if (LEAD) __syncthreads();
 #pragma unroll
     for (int cb = 0; cb < 8; ++cb)
 #pragma unroll
@@ -275,10 +277,12 @@ struct Half128MF {
   }
 
   // half h inverse: the exact reverse, ending with the half's stage-A values back in their
-  // slots.  Starts with a barrier; ends after the final LDS reads (no barrier).
+  // slots.  Starts with a barrier unless LEAD is false (as Half128::half_inv: the first
+  // writes go to the thread's own_pair slots); ends after the final LDS reads (no barrier).
+  template <bool LEAD = true>
   __device__ static __forceinline__ void half_inv(float2* v, float2* lds, const uint4* __restrict__ tab, int t,
                                                   int h) {
-    __syncthreads();
+    if (LEAD) __syncthreads();
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int L = t + 512 * q;

@@ -217,7 +217,7 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
       if (l == 1) asm volatile("" ::: "memory");   // keep the next group's loads after these
     }
     // stage-B twiddles to LDS after the first line's loads are issued (visible after
-    // the first barrier of half_fwd)
+    // the barrier that follows half_fwd's stage-A writes)
     if (l == 0 && t < F::N2 * 16) twl[(t >> 4) * TWL + (t & 15)] = a.tw[t];
     F::stage_a_fwd_line(v, a.tw, t, l);
     // the line's 16 outputs are complete here: the compiler may not sink parts of the
@@ -230,24 +230,25 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
   double mis = 0.0, gsum = 0.0, gdel = 0.0, gnrm = 0.0;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    if constexpr (MF) M::half_fwd(v, lds, a.mft, t, h);
-    else F::half_fwd<TWL>(v, lds, twl, t, h);
+    // no leading barriers: every LDS slot a thread writes first in a half transform is
+    // one that only this thread touched last (Half128::own_pair, the stage-A slots)
+    if constexpr (MF) M::template half_fwd<false>(v, lds, a.mft, t, h);
+    else F::template half_fwd<TWL, false>(v, lds, twl, t, h);
     // the other half's 16 values wait in the LDS buffer, idle between the stage-C reads
     // and the inverse; the 32 registers they free let all 16 amplitude and multiplier
     // loads of this half be in flight at once
     auto slot = [&](int hh, int k) { return MF ? 4 * (k >> 1) + 2 * hh + (k & 1) : 16 * (k >> 3) + 8 * hh + (k & 7); };
-    static_assert(16 * F::T <= F::LDS, "the parked half fits the LDS buffer");
-    float4* park = reinterpret_cast<float4*>(lds);   // 8 x 512 float4 of the 64-row buffer
     // the frequency offsets below are computed here from an opaque copy of the thread
     // index: hoisted to the start of the kernel they would stay live across the
     // transforms and spill
     int tq = t;
     asm volatile("" : "+v"(tq));
-    __syncthreads();                                 // every thread's stage-C reads are done
+    // the other half goes into the 16 LDS values this thread has just read in the last
+    // stage-C pass (no other thread reads them, so no barrier)
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const float2 x0 = v[slot(1 - h, 2 * k)], x1 = v[slot(1 - h, 2 * k + 1)];
-      park[k * F::T + tq] = make_float4(x0.x, x0.y, x1.x, x1.y);
+      *reinterpret_cast<float4*>(lds + F::own_pair(tq, k)) = make_float4(x0.x, x0.y, x1.x, x1.y);
     }
     asm volatile("" ::: "memory");
     float2 gpre[16];
@@ -288,16 +289,16 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
       gnrm += hgnrm;
     }
     asm volatile("" ::: "memory");
-    // each thread reads back only what it wrote; half_inv's leading barrier orders these
-    // reads before its first LDS writes
+    // each thread reads back only what it wrote; half_inv's first LDS writes go to these
+    // same slots, after these reads in the thread's own program order
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const float4 x = park[k * F::T + tq];
+      const float4 x = *reinterpret_cast<const float4*>(lds + F::own_pair(tq, k));
       v[slot(1 - h, 2 * k)] = make_float2(x.x, x.y);
       v[slot(1 - h, 2 * k + 1)] = make_float2(x.z, x.w);
     }
-    if constexpr (MF) M::half_inv(v, lds, a.mft, t, h);
-    else F::half_inv<TWL>(v, lds, twl, t, h);
+    if constexpr (MF) M::template half_inv<false>(v, lds, a.mft, t, h);
+    else F::template half_inv<TWL, false>(v, lds, twl, t, h);
   }
   if (STATS) frame_stats<F::T, (ST > 1)>(a.part + NFS * (size_t)j, mis, gsum, gdel, gnrm, red);
   // inverse stage A and the output one line at a time; the second line's probe loads
