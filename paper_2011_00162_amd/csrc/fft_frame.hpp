@@ -440,7 +440,7 @@ struct Half128 {
   static constexpr int LP = 152;                   // row pitch (complex), as Frame<128>
   static constexpr int ROWS = 64;                  // rows per half
   static constexpr int LDS = ROWS * LP;
-  __device__ static __forceinline__ int at(int row, int col) { return row * LP + col + 2 * (col >> 4); }
+  __host__ __device__ static __forceinline__ int at(int row, int col) { return row * LP + col + 2 * (col >> 4); }
   __device__ static __forceinline__ int a_col(int t) { return t & 127; }
   __device__ static __forceinline__ int uniform_g(int t) { return __builtin_amdgcn_readfirstlane(t >> 7); }
   // image row of spatial slot e (column a_col(t))
@@ -474,10 +474,15 @@ struct Half128 {
   // the last stage-C pass of a half (see half_fwd).  These pairs partition the buffer
   // over the threads, so a thread may overwrite its own right after that pass without a
   // barrier.
-  __device__ static __forceinline__ int own_pair(int t, int k) {
+  __host__ __device__ static __forceinline__ int own_pair(int t, int k) {
     const int L = t + 512 * (k >> 2);
     const int k1c = L & 15, k2r = (L >> 4) & 7, k1r = L >> 7;
     return at(8 * k1r + k2r, 8 * k1c + 2 * (k & 3));
+  }
+  // LDS index of stage-A output k (< 8) of line l of thread t in a half (its slot
+  // 16 l + 8 h + k): written first in half_fwd, read last in half_inv
+  __host__ __device__ static __forceinline__ int a_slot(int t, int k, int l) {
+    return at(8 * k + (t >> 7) + 4 * l, t & 127);
   }
 
   // half h forward: stage-A outputs of the half into LDS, stages B and C, frequencies
@@ -488,12 +493,11 @@ struct Half128 {
   template <int TS, bool LEAD = true>
   __device__ static __forceinline__ void half_fwd(float2* v, float2* lds, const float2* __restrict__ twl, int t,
                                                   int h) {
-    const int col = a_col(t), g = t >> 7;
     if (LEAD) __syncthreads();
 #pragma unroll
     for (int l = 0; l < 2; ++l)
 #pragma unroll
-      for (int k = 0; k < 8; ++k) lds[at(8 * k + g + 4 * l, col)] = v[16 * l + 8 * h + k];
+      for (int k = 0; k < 8; ++k) lds[a_slot(t, k, l)] = v[16 * l + 8 * h + k];
     __syncthreads();
     stage_b<false, TS>(lds, twl, t);
     __syncthreads();
@@ -510,13 +514,11 @@ struct Half128 {
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {   // stage C, DFT8 over c2 of lines (k1r, k2r, k1c)
-      const int L = t + 512 * q;
-      const int k1c = L & 15, k2r = (L >> 4) & 7, k1r = L >> 7;
+    for (int q = 0; q < 2; ++q) {   // stage C, DFT8 over c2 of lines (k1r, k2r, k1c): own_pair
       float2 a[8];
 #pragma unroll
       for (int c = 0; c < 8; c += 2) {
-        const float4 x = *reinterpret_cast<const float4*>(lds + at(8 * k1r + k2r, 8 * k1c + c));
+        const float4 x = *reinterpret_cast<const float4*>(lds + own_pair(t, 4 * q + c / 2));
         a[c] = make_float2(x.x, x.y);
         a[c + 1] = make_float2(x.z, x.w);
       }
@@ -536,17 +538,14 @@ struct Half128 {
                                                   int h) {
     if (LEAD) __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int L = t + 512 * q;
-      const int k1c = L & 15, k2r = (L >> 4) & 7, k1r = L >> 7;
+    for (int q = 0; q < 2; ++q) {   // inverse DFT8 over c2 of lines (k1r, k2r, k1c): own_pair
       float2 a[8];
 #pragma unroll
       for (int c = 0; c < 8; ++c) a[c] = v[16 * q + 8 * h + c];
       dft8<true>(a);
 #pragma unroll
       for (int c = 0; c < 8; c += 2)
-        *reinterpret_cast<float4*>(lds + at(8 * k1r + k2r, 8 * k1c + c)) =
-            make_float4(a[c].x, a[c].y, a[c + 1].x, a[c + 1].y);
+        *reinterpret_cast<float4*>(lds + own_pair(t, 4 * q + c / 2)) = make_float4(a[c].x, a[c].y, a[c + 1].x, a[c + 1].y);
     }
     __syncthreads();
 #pragma unroll
@@ -563,11 +562,10 @@ struct Half128 {
     __syncthreads();
     stage_b<true, TS>(lds, twl, t);
     __syncthreads();
-    const int col = a_col(t), g = t >> 7;
 #pragma unroll
     for (int l = 0; l < 2; ++l)
 #pragma unroll
-      for (int k = 0; k < 8; ++k) v[16 * l + 8 * h + k] = lds[at(8 * k + g + 4 * l, col)];
+      for (int k = 0; k < 8; ++k) v[16 * l + 8 * h + k] = lds[a_slot(t, k, l)];
   }
 
   // stage B on the 64 rows of a half: thread t takes row t / 8 and c2 = t % 8 (the

@@ -191,6 +191,11 @@ struct Half128MF {
   static constexpr int P = 128, N2 = 8, T = 512;
   static constexpr int LP = Half128::LP, ROWS = Half128::ROWS, LDS = Half128::LDS;
   __device__ static __forceinline__ int at(int row, int col) { return Half128::at(row, col); }
+  // LDS index of the half's stage-A value (block cb < 8, jj < 2) of lane `lane` of
+  // wavefront w: written first in half_fwd, read last in half_inv
+  __host__ __device__ static __forceinline__ int a_slot(int w, int lane, int cb, int jj) {
+    return Half128::at(8 * (2 * (lane >> 4) + jj) + w, 16 * cb + (lane & 15));
+  }
   __device__ static __forceinline__ int wave(int t) { return __builtin_amdgcn_readfirstlane(t >> 6); }
   __device__ static __forceinline__ int row(int t, int e) { return 8 * (4 * ((t & 63) >> 4) + (e & 3)) + wave(t); }
   __device__ static __forceinline__ int col(int t, int e) { return 16 * (e >> 2) + (t & 15); }
@@ -238,12 +243,12 @@ struct Half128MF {
   template <bool LEAD = true>
   __device__ static __forceinline__ void half_fwd(float2* v, float2* lds, const uint4* __restrict__ tab, int t,
                                                   int h) {
-    const int w = wave(t), lane = t & 63, g = lane >> 4, n0 = lane & 15;
+    const int w = wave(t), lane = t & 63;
     if (LEAD) __syncthreads();
 #pragma unroll
     for (int cb = 0; cb < 8; ++cb)
 #pragma unroll
-      for (int jj = 0; jj < 2; ++jj) lds[at(8 * (2 * g + jj) + w, 16 * cb + n0)] = v[4 * cb + 2 * h + jj];
+      for (int jj = 0; jj < 2; ++jj) lds[a_slot(w, lane, cb, jj)] = v[4 * cb + 2 * h + jj];
     __syncthreads();
     stage_b<false>(lds, tab, t);
     __syncthreads();
@@ -260,13 +265,11 @@ struct Half128MF {
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {   // stage C, DFT8 over c2 of lines (k1r, k2r, k1c)
-      const int L = t + 512 * q;
-      const int k1c = L & 15, k2r = (L >> 4) & 7, k1r = L >> 7;
+    for (int q = 0; q < 2; ++q) {   // stage C, DFT8 over c2 of lines (k1r, k2r, k1c): own_pair
       float2 a[8];
 #pragma unroll
       for (int c = 0; c < 8; c += 2) {
-        const float4 x = *reinterpret_cast<const float4*>(lds + at(8 * k1r + k2r, 8 * k1c + c));
+        const float4 x = *reinterpret_cast<const float4*>(lds + Half128::own_pair(t, 4 * q + c / 2));
         a[c] = make_float2(x.x, x.y);
         a[c + 1] = make_float2(x.z, x.w);
       }
@@ -284,16 +287,14 @@ struct Half128MF {
                                                   int h) {
     if (LEAD) __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int L = t + 512 * q;
-      const int k1c = L & 15, k2r = (L >> 4) & 7, k1r = L >> 7;
+    for (int q = 0; q < 2; ++q) {   // inverse DFT8 over c2 of lines (k1r, k2r, k1c): own_pair
       float2 a[8];
 #pragma unroll
       for (int c = 0; c < 8; ++c) a[c] = v[fslot(h, q, c)];
       dft8<true>(a);
 #pragma unroll
       for (int c = 0; c < 8; c += 2)
-        *reinterpret_cast<float4*>(lds + at(8 * k1r + k2r, 8 * k1c + c)) =
+        *reinterpret_cast<float4*>(lds + Half128::own_pair(t, 4 * q + c / 2)) =
             make_float4(a[c].x, a[c].y, a[c + 1].x, a[c + 1].y);
     }
     __syncthreads();
@@ -311,11 +312,11 @@ struct Half128MF {
     __syncthreads();
     stage_b<true>(lds, tab, t);
     __syncthreads();
-    const int w = wave(t), lane = t & 63, g = lane >> 4, n0 = lane & 15;
+    const int w = wave(t), lane = t & 63;
 #pragma unroll
     for (int cb = 0; cb < 8; ++cb)
 #pragma unroll
-      for (int jj = 0; jj < 2; ++jj) v[4 * cb + 2 * h + jj] = lds[at(8 * (2 * g + jj) + w, 16 * cb + n0)];
+      for (int jj = 0; jj < 2; ++jj) v[4 * cb + 2 * h + jj] = lds[a_slot(w, lane, cb, jj)];
   }
 };
 
