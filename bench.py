@@ -37,11 +37,14 @@ PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_sweep_c2_pmc.md")
 PMC_SUMMARY_C5 = os.path.join(ROOT, "profiles", "k_sweep128_c5_pmc.md")
 PMC_SUMMARY_C3 = os.path.join(ROOT, "profiles", "loss_c3_pmc.md")
 C5_SUBS_CHECKED = (0, 3, 36)      # a corner, an edge and an interior subdomain of the 8 x 8 grid
+# sources whose text a committed PMC summary is tied to (the kernels, the headers they
+# include, and the host plan code that sets launch shapes, orders and the streaming mode)
 LOSS_SOURCES = ["paper_2011_00162_amd/csrc/loss.hip", "paper_2011_00162_amd/csrc/fft_frame.hpp",
-                "paper_2011_00162_amd/csrc/reduce.hpp", "paper_2011_00162_amd/csrc/odp_internal.hpp"]
-KERNEL_SOURCES = ["paper_2011_00162_amd/csrc/kernels.hip", "paper_2011_00162_amd/csrc/fft_frame.hpp",
-                  "paper_2011_00162_amd/csrc/fft_mfma.hpp", "paper_2011_00162_amd/csrc/prox.hpp",
-                  "paper_2011_00162_amd/csrc/odp_internal.hpp"]
+                "paper_2011_00162_amd/csrc/reduce.hpp", "paper_2011_00162_amd/csrc/odp_internal.hpp",
+                "paper_2011_00162_amd/csrc/plan.cpp"]
+KERNEL_SOURCES = sorted("paper_2011_00162_amd/csrc/" + f
+                        for f in os.listdir(os.path.join(ROOT, "paper_2011_00162_amd", "csrc"))
+                        if f.endswith((".hip", ".hpp", ".cpp")))
 
 
 def kernel_hash(sources=None) -> str:
