@@ -25,6 +25,20 @@ __device__ __forceinline__ int loss_frame(int J) {
   return j < J ? j : -1;
 }
 
+// One element's loss term (|X| - sqrt f)^2 from the FP32 spectrum: |X| = |X|^2 / |X| by the
+// hardware reciprocal square root (about an ulp), the difference and its square in FP32,
+// added to the FP64 sum one element after the other (an empty asm on the sum keeps the
+// scheduler from interleaving the temporaries of many elements, which spilled).  Returns
+// 1/|X| (0 for X = 0), which the gradient uses.
+__device__ __forceinline__ float loss_term(float2 X, float sf, double& loss) {
+  const float a2 = X.x * X.x + X.y * X.y;
+  const float inv = a2 > 0.0f ? __builtin_amdgcn_rsqf(a2) : 0.0f;
+  const float d = a2 * inv - sf;
+  loss += (double)(d * d);
+  asm volatile("" : "+v"(loss));
+  return inv;
+}
+
 template <int P, bool GRAD>
 __global__ __launch_bounds__(Frame<P>::T) void k_loss(LossArgs a) {
   using F = Frame<P>;
@@ -55,13 +69,9 @@ __global__ __launch_bounds__(Frame<P>::T) void k_loss(LossArgs a) {
     F::freq(t, e, kr, kc);
     const float2 X = c_scale(v[e], inv_p);
     const float sf = a.sqrt_f[fbase + kr * P + kc];
-    const float a2 = X.x * X.x + X.y * X.y;
-    const double ax = sqrt((double)a2);
-    loss += (ax - sf) * (ax - sf);
+    const float inv = loss_term(X, sf, loss);
     if (GRAD) {
-      const bool nz = a2 > 0.0f;
-      const float inv = nz ? __builtin_amdgcn_rsqf(a2) : 0.0f;
-      const float sc = nz ? 2.0f * (1.0f - sf * inv) : 0.0f;
+      const float sc = inv > 0.0f ? 2.0f * (1.0f - sf * inv) : 0.0f;
       v[e] = c_scale(X, sc * inv_p);
     }
   }
@@ -116,14 +126,23 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
   double loss = 0.0;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    F::half_fwd<TWL>(v, lds, twl, t, h);
+    // leading barriers only where a thread's first LDS writes could meet another thread's
+    // last accesses: before the second half when no inverse ran in between (the first
+    // half's stage-C reads are other slots than the stage-A writes); the stage-A and
+    // own_pair slots are thread-private otherwise (Half128::a_slot, own_pair)
+    if (h == 1 && !GRAD) F::template half_fwd<TWL, true>(v, lds, twl, t, h);
+    else F::template half_fwd<TWL, false>(v, lds, twl, t, h);
+    // frequency offsets from an opaque copy of the thread index, computed here (hoisted
+    // to the start of the kernel they would stay live across the transforms)
+    int tq = t;
+    asm volatile("" : "+v"(tq));
 #pragma unroll
     for (int qq = 0; qq < 2; ++qq) {   // two groups of 8, each finished before the next
       float sfq[8];
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         int kr, kc;
-        F::freq(t, 16 * qq + 8 * h + i, kr, kc);
+        F::freq(tq, 16 * qq + 8 * h + i, kr, kc);
         sfq[i] = sb[(uint32_t)(kr * P + kc)];
       }
 #pragma unroll
@@ -131,20 +150,16 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
         const int e = 16 * qq + 8 * h + i;
         const float2 X = c_scale(v[e], inv_p);
         const float sf = sfq[i];
-        const float a2 = X.x * X.x + X.y * X.y;
-        const double ax = sqrt((double)a2);
-        loss += (ax - sf) * (ax - sf);
+        const float inv = loss_term(X, sf, loss);
         if (GRAD) {
-          const bool nz = a2 > 0.0f;
-          const float inv = nz ? __builtin_amdgcn_rsqf(a2) : 0.0f;
-          const float sc = nz ? 2.0f * (1.0f - sf * inv) : 0.0f;
+          const float sc = inv > 0.0f ? 2.0f * (1.0f - sf * inv) : 0.0f;
           v[e] = c_scale(X, sc * inv_p);
         }
         pin(v[e]);
       }
       asm volatile("" ::: "memory");
     }
-    if (GRAD) F::half_inv<TWL>(v, lds, twl, t, h);
+    if (GRAD) F::template half_inv<TWL, false>(v, lds, twl, t, h);
   }
   loss = block_sum<F::T>(loss, red);
   if (t == 0) a.frame_loss[j] = loss;
@@ -284,13 +299,12 @@ hipError_t launch_loss(int p, const LossArgs& a, bool grad, hipStream_t s) {
   }
   ODP_LOSS(32)
   ODP_LOSS(64)
-  // p = 128: the loss alone on the two-half transform; with the gradient the per-element
-  // FP64 work and the inverse path spill on it (measured slower), so it keeps Frame<128>
-  if (p == 128 && !grad) {
-    hipLaunchKernelGGL((k_loss128<false>), grid, dim3(Half128::T), 0, s, a);
+  // p = 128 on the two-half transform (two frames per CU)
+  if (p == 128) {
+    if (grad) hipLaunchKernelGGL((k_loss128<true>), grid, dim3(Half128::T), 0, s, a);
+    else hipLaunchKernelGGL((k_loss128<false>), grid, dim3(Half128::T), 0, s, a);
     return hipGetLastError();
   }
-  ODP_LOSS(128)
 #undef ODP_LOSS
   return hipErrorInvalidValue;
 }
