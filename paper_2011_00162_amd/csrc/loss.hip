@@ -178,8 +178,7 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
 // subdomain are covered by no frame and stay 0 (cleared by the caller).  The padded
 // pull lists are read PULL_B records at a time for both of the thread's pixels, so
 // their loads are in flight together; each pixel sums its frames in list order.
-__global__ __launch_bounds__(256) void k_grad_u(LossGradArgs a) {
-  const int tile = blockIdx.x;
+__device__ __forceinline__ void grad_u_tile(const LossGradArgs& a, int tile) {
   const TileDesc td = a.tiles[tile];
   const CellDesc* cd = a.cells + td.cell;
   const int p = a.p;
@@ -223,10 +222,10 @@ __global__ __launch_bounds__(256) void k_grad_u(LossGradArgs a) {
 }
 
 // dL/dw partial sums over frame chunks (FP64; eight frames' loads in flight per step,
-// summed in frame order), then a fixed-order final sum.
-__global__ __launch_bounds__(256) void k_grad_w_part(LossGradArgs a) {
+// summed in frame order), then a fixed-order final sum.  Block kb of chunk `chunk`.
+__device__ __forceinline__ void grad_w_part_block(const LossGradArgs& a, int kb, int chunk) {
   constexpr int B = 8;
-  const int p = a.p, k = blockIdx.x * 256 + threadIdx.x, chunk = blockIdx.y;
+  const int p = a.p, k = kb * 256 + threadIdx.x;
   if (k >= p * p) return;
   const int ky = k / p, kx = k % p;
   const int j0 = chunk * a.frames_per_chunk;
@@ -259,9 +258,32 @@ __global__ __launch_bounds__(256) void k_grad_w_part(LossGradArgs a) {
   a.wpart[2 * ((size_t)chunk * p * p + k) + 1] = gy;
 }
 
+// Both gradients' pulls in one launch (they are independent): workgroups [0, n_u) take
+// the image tiles, the rest the probe-gradient partial sums (block kb of chunk c at
+// n_u + c * nb + kb), so neither waits for the other's tail.
+__global__ __launch_bounds__(256) void k_grad(LossGradArgs a, int n_u, int nb) {
+  const int b = blockIdx.x;
+  if (b < n_u) grad_u_tile(a, b);
+  else grad_w_part_block(a, (b - n_u) % nb, (b - n_u) / nb);
+}
+
+// the frames' loss terms summed in a fixed order by one workgroup
+__device__ __forceinline__ void loss_total_block(const double* frame_loss, int J, double* out) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int j = threadIdx.x; j < J; j += 256) s += frame_loss[j];
+  s = block_sum<256>(s, sh);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
 // the chunks' partial sums per probe pixel: the four wavefronts of a workgroup take every
 // fourth chunk for the same 64 pixels, added in wavefront order
+// With a.loss_out set, one more workgroup (the last) sums the frames' loss terms instead.
 __global__ __launch_bounds__(256) void k_grad_w_final(LossGradArgs a) {
+  if (a.loss_out && blockIdx.x == gridDim.x - 1) {   // uniform over the workgroup
+    loss_total_block(a.frame_loss, a.J, a.loss_out);
+    return;
+  }
   __shared__ double part[2][4][64];
   const int p = a.p, lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int k = blockIdx.x * 64 + lane;
@@ -282,11 +304,7 @@ __global__ __launch_bounds__(256) void k_grad_w_final(LossGradArgs a) {
 }
 
 __global__ __launch_bounds__(256) void k_loss_total(const double* frame_loss, int J, double* out) {
-  __shared__ double sh[4];
-  double s = 0.0;
-  for (int j = threadIdx.x; j < J; j += 256) s += frame_loss[j];
-  s = block_sum<256>(s, sh);
-  if (threadIdx.x == 0) out[0] = s;
+  loss_total_block(frame_loss, J, out);
 }
 
 hipError_t launch_loss(int p, const LossArgs& a, bool grad, hipStream_t s) {
@@ -315,12 +333,13 @@ hipError_t launch_loss_total(const double* frame_loss, int J, double* out, hipSt
 }
 
 hipError_t launch_loss_grads(const LossGradArgs& a, hipStream_t s) {
-  if (a.grad_u && a.n_tiles > 0) hipLaunchKernelGGL(k_grad_u, dim3(a.n_tiles), dim3(256), 0, s, a);
-  if (a.grad_w) {
-    const int nb = (a.p * a.p + 255) / 256;
-    hipLaunchKernelGGL(k_grad_w_part, dim3(nb, a.n_chunks), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_grad_w_final, dim3((a.p * a.p + 63) / 64), dim3(256), 0, s, a);
-  }
+  const int nb = (a.p * a.p + 255) / 256;
+  const int n_u = a.grad_u ? a.n_tiles : 0, n_w = a.grad_w ? nb * a.n_chunks : 0;
+  if (n_u + n_w > 0) hipLaunchKernelGGL(k_grad, dim3(n_u + n_w), dim3(256), 0, s, a, n_u, nb);
+  if (a.grad_w)
+    hipLaunchKernelGGL(k_grad_w_final, dim3((a.p * a.p + 63) / 64 + (a.loss_out ? 1 : 0)), dim3(256), 0, s, a);
+  else if (a.loss_out)
+    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, s, a.frame_loss, a.J, a.loss_out);
   return hipGetLastError();
 }
 

@@ -271,6 +271,8 @@ struct LossGradArgs {
   float2* grad_w;            // [p][p] or null
   double* wpart;             // [n_chunks][p][p][2]
   int32_t n_chunks, frames_per_chunk;
+  const double* frame_loss;  // [J] per-frame loss terms, summed into loss_out by the last
+  double* loss_out;          //   workgroup of the probe gradient's final sum (or null)
 };
 
 hipError_t launch_loss(int p, const LossArgs& a, bool grad, hipStream_t s);

@@ -1380,8 +1380,10 @@ int odp_amp_loss(const odp_plan* P, const odp_c32* u, const odp_c32* w, double* 
   la.frame_loss = P->W_<double>(P->ws.fpart);
   la.phi = P->W_<float2>(P->ws.psi);
   ODP_HIP(launch_loss(P->p, la, grad, s));
-  ODP_HIP(launch_loss_total(la.frame_loss, P->J, loss_out, s));
-  if (!grad) return ODP_OK;
+  if (!grad) {
+    ODP_HIP(launch_loss_total(la.frame_loss, P->J, loss_out, s));
+    return ODP_OK;
+  }
   // pixels in no tile are covered by no frame: their gradient is 0 (the tiles write the rest)
   if (grad_u && P->covered < (int64_t)P->H * P->W)
     ODP_HIP(launch_fill(reinterpret_cast<float2*>(grad_u), (int64_t)P->H * P->W, make_float2(0.f, 0.f), s));
@@ -1404,6 +1406,8 @@ int odp_amp_loss(const odp_plan* P, const odp_c32* u, const odp_c32* w, double* 
   ga.wpart = P->W_<double>(P->ws.wpart);
   ga.frames_per_chunk = (P->J + LOSS_CHUNKS - 1) / LOSS_CHUNKS;
   ga.n_chunks = (P->J + ga.frames_per_chunk - 1) / ga.frames_per_chunk;
+  ga.frame_loss = la.frame_loss;   // the loss total is summed with the probe gradient
+  ga.loss_out = loss_out;
   ODP_HIP(launch_loss_grads(ga, s));
   return ODP_OK;
 }

@@ -45,6 +45,23 @@ def test_loss_and_gradients(n, dy, dx):
         assert rel(host(gw), gw_o) <= 1e-5, rel(host(gw), gw_o)
 
 
+@pytest.mark.parametrize("want_u,want_w", [(True, False), (False, True), (False, False)],
+                         ids=["grad_u_only", "grad_w_only", "loss_only"])
+def test_one_gradient_or_none(want_u, want_w):
+    # the loss total is formed by a different kernel depending on which gradients are
+    # asked for; every combination gives the oracle's loss and requested gradients
+    say("amplitude loss, gradients", want_u, want_w)
+    plan, u, w, f, off = _case(256, 2, 2)
+    loss, gu, gw = plan.amp_loss(dev_c64(u), dev_c64(w), grad_u=want_u, grad_w=want_w)
+    L, gu_o, gw_o = amploss.grad(u, w, off, f)
+    assert abs(host(loss)[0] - L) <= 1e-5 * L
+    assert (gu is None) != want_u and (gw is None) != want_w
+    if want_u:
+        assert rel(host(gu), gu_o) <= 1e-5, rel(host(gu), gu_o)
+    if want_w:
+        assert rel(host(gw), gw_o) <= 1e-5, rel(host(gw), gw_o)
+
+
 def test_autograd_function_matches_entry_point():
     say("autograd")
     plan, u, w, f, off = _case(256)
