@@ -264,7 +264,7 @@ __global__ __launch_bounds__(256, WGS_PER_CU) void k_sweep_dft64(SweepArgs a, Df
     }
 
     // prox and Gamma update at kr = 16w + n0, kc = 16 mt + 4g + i; xr/xi become t = z - Gamma
-    float mis = 0.f, gsum = 0.f, gdel = 0.f, gnrm = 0.f;   // the lane's 16 terms (FP64 across lanes)
+    double mis = 0.0, gsum = 0.0, gdel = 0.0, gnrm = 0.0;
       {
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt) {

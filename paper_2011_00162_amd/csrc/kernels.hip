@@ -107,7 +107,7 @@ __global__ __launch_bounds__(Frame<P>::T, MF && P == 64 && ST == 0 ? 4 : 1) void
       gpre[e] = ld_s<NT>(a.gamma + fbase + kr * P + kc);
     }
   }
-  float mis = 0.f, gsum = 0.f, gdel = 0.f, gnrm = 0.f;   // the thread's 16 terms (FP64 across threads)
+  double mis = 0.0, gsum = 0.0, gdel = 0.0, gnrm = 0.0;
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     int kr, kc;
@@ -253,7 +253,6 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
     asm volatile("" ::: "memory");
     float2 gpre[16];
     float spre[16];
-    float hmis = 0.f, hgsum = 0.f, hgdel = 0.f, hgnrm = 0.f;   // this half's 16 terms
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       int kr, kc;
@@ -270,8 +269,8 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
       const float2 z = prox_stagm(y, sf, pc);
       const float2 g = c_sub(y, z);
       if (STATS) {
-        elem_measures(X, sf, a.eps, a.gcoef, hmis, hgsum);
-        if (ST > 1) frame_terms(gpre[k], g, hgdel, hgnrm);
+        elem_measures(X, sf, a.eps, a.gcoef, mis, gsum);
+        if (ST > 1) frame_terms(gpre[k], g, gdel, gnrm);
       }
       gpre[k] = g;
       v[e] = c_scale(c_sub(z, g), inv_p);   // both 1/p factors of the unitary pair applied here
@@ -281,12 +280,6 @@ __global__ __launch_bounds__(Half128::T) __attribute__((amdgpu_waves_per_eu(4, 4
       int kr, kc;
       F::freq(tq, 16 * (k >> 3) + 8 * h + (k & 7), kr, kc);
       st_s<NT>(gb + (uint32_t)(kr * P + kc), gpre[k]);
-    }
-    if (STATS) {
-      mis += hmis;
-      gsum += hgsum;
-      gdel += hgdel;
-      gnrm += hgnrm;
     }
     asm volatile("" ::: "memory");
     // each thread reads back only what it wrote; half_inv's first LDS writes go to these

@@ -38,20 +38,19 @@ __device__ __forceinline__ float2 prox_stagm(float2 y, float sf, const ProxC& c)
 // | |X| - sqrt(f) | and g_eps(X; f), from the FP32 spectrum X in FP32 (|X| by the
 // hardware square root, about an ulp; g_eps is continuous where its branch switches, so
 // a switch near the threshold moves nothing).  gcoef = (1 - eps) / (2 eps): the truncated
-// branch is gcoef (eps f - |X|^2).  Branch-free; the caller sums a thread's terms of a
-// half frame in FP32 and adds that partial to its FP64 sums.
-__device__ __forceinline__ void elem_measures(float2 X, float sf, float eps, float gcoef, float& mis,
-                                              float& gsum) {
+// branch is gcoef (eps f - |X|^2).  Branch-free; each term is added to the caller's FP64
+// sums, one element after the other (an empty asm on the sums keeps the scheduler from
+// interleaving the temporaries of many elements, which spilled).
+__device__ __forceinline__ void elem_measures(float2 X, float sf, float eps, float gcoef, double& mis,
+                                              double& gsum) {
   const float ax2 = fmaf(X.x, X.x, X.y * X.y);
   const float ax = __builtin_amdgcn_sqrtf(ax2);
   const float d = ax - sf;
   const float esf = eps * sf;
   const float gt = gcoef * fmaf(esf, sf, -ax2);
   const float gq = 0.5f * d * d;
-  mis += fabsf(d);
-  gsum += ax < esf ? gt : gq;
-  // one element after the other: interleaving the terms of many elements (the
-  // scheduler's choice for an unrolled loop) holds all their temporaries at once
+  mis += (double)fabsf(d);
+  gsum += (double)(ax < esf ? gt : gq);
   asm volatile("" : "+v"(mis), "+v"(gsum));
 }
 

@@ -27,12 +27,11 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 // One frequency's terms of the frame constraint's residuals (penalty balancing):
 // |Gamma^{n+1} - Gamma^n|^2 and |Gamma^{n+1}|^2 in FP32 (they only steer a factor-of-tau
-// decision), summed over a thread's frequencies in FP32 one after the other (see
-// elem_measures) and added to FP64 sums by the caller.
-__device__ __forceinline__ void frame_terms(float2 g_old, float2 g_new, float& del, float& nrm) {
+// decision), added to FP64 sums one after the other (see elem_measures).
+__device__ __forceinline__ void frame_terms(float2 g_old, float2 g_new, double& del, double& nrm) {
   const float dx = g_new.x - g_old.x, dy = g_new.y - g_old.y;
-  del += dx * dx + dy * dy;
-  nrm += g_new.x * g_new.x + g_new.y * g_new.y;
+  del += (double)(dx * dx + dy * dy);
+  nrm += (double)(g_new.x * g_new.x + g_new.y * g_new.y);
   asm volatile("" : "+v"(del), "+v"(nrm));
 }
 
