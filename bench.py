@@ -381,17 +381,20 @@ def run_c5(args, torch, odp, synthetic):
             plan = c5_plan(odp, spec, pr, sqrt_f, w0 if blind else w_true, blind, tr)
             scratch = plan.new_state(w0=w0 if blind else None)
             tune = plan.autotune(scratch, iters=3)
-            plan.set_tuning(tr, tune.xcd_slice, tune.tiling)
+            xs = tune.xcd_slice if args.placement < 0 else args.placement
+            plan.set_tuning(tr, xs, tune.tiling)
             del scratch
             st = plan.new_state(w0=w0 if blind else None)
             plan.iterate(st, args.warmup)
             ms = time_iterations(torch, plan, st, args.steps) / args.steps
             sweep_avg, sweep_med = sweep_event_ms(torch, plan, st, min(args.steps, 20))
             alg = 20.0 * J * spec.p ** 2 + 16.0 * plan.info.p_sub
-            key = "traffic_bytes_per_launch" + ("_blind" if blind else "")
+            # the frame placement changes how often image windows are re-read across the
+            # XCDs' L2s, so the committed counters are kept per placement
+            key = "traffic_bytes_per_launch" + ("_blind" if blind else "") + f"_xcd{xs}"
             out.setdefault(tname, {})[mode] = {
                 "value": J / (ms / 1e3), "ms_per_step": ms,
-                "tuning": {"xcd_slice": tune.xcd_slice, "tile": [tune.tile_rows, tune.tile_cols]},
+                "tuning": {"xcd_slice": xs, "tile": [tune.tile_rows, tune.tile_cols]},
                 "sweep_ms": sweep_avg, "sweep_median_ms": sweep_med, "sweep_algorithmic_bytes": alg,
                 "sweep_roofline": {"bound": "hbm", "achieved": alg / (sweep_avg / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
                                    "unit": "GB/s", "frac": alg / (sweep_avg / 1e3) / 1e9 / HBM_PEAK_GBS,
@@ -636,6 +639,9 @@ def main() -> int:
                     help="c5 (default: 2048^2 blind, the metric's line, with the 512^2 workload beside it); "
                          "c2 512^2 alone; c3 loss+gradient; c4 64-problem batch; "
                          "table1 iterations to RF <= 1e-5 against the number of stripes (context)")
+    ap.add_argument("--placement", type=int, default=-1, choices=[-1, 0, 1, 2],
+                    help="2048^2 line: frame placement (xcd_slice) of the timed configuration instead of the "
+                         "autotuner's choice (profiling runs; -1 = the autotuner's)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (scales the HBM counters)")
     args = ap.parse_args()
