@@ -608,7 +608,7 @@ def c2_report(args, torch, odp, synthetic):
         "tuning": g["tuning"], "frames": g["J"], "probe": g["p"], "image": g["n"], "subdomains": g["D"],
         "transforms": {
             "fft_f32": {"value": value, "ms_per_step": g["total_ms"] / args.steps, "sweep_ms": g["sweep_avg_ms"],
-                        "sweep_roofline": {"bound": "hbm", "kernel": "k_sweep<64>", "achieved": achieved,
+                        "sweep_roofline": {"bound": "hbm", "kernel": "k_sweep<64, false, false, 0, false>", "achieved": achieved,
                                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                                            "traffic": measured_traffic(),
                                            "algorithmic_bytes_per_launch": g["alg_bytes"]}},
@@ -701,7 +701,7 @@ def main() -> int:
                    "probe": 128, "image": 2048, "subdomains": 64, "pairs": 210},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_sweep128<true, 0> (blind frame sweep)",
+            "kernel": "k_sweep128<false, true, 0, true> (blind FFT frame sweep, streaming accesses)",
             "achieved": head["sweep_roofline"]["achieved"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
