@@ -298,7 +298,7 @@ def run_c4(args, torch, odp, synthetic):
         plan.bind(torch.from_numpy(np.concatenate(sfs)).cuda(), torch.from_numpy(np.stack(ws)).cuda())
         plan.set_penalties([0.5 * eta * plan.entry(i).illum_max for i in range(len(group))])
         scratch = plan.new_state()
-        t = plan.autotune(scratch, iters=3)
+        t = plan.autotune(scratch, iters=10)
         # every frame transform at the tuned order and tiling (the DFT path exists for p = 64)
         per_transform = {}
         for name, tr in (("fft_f32", odp.ODP_FFT_F32), ("dft_split_bf16", odp.ODP_DFT_SPLIT_BF16),
@@ -380,7 +380,7 @@ def run_c5(args, torch, odp, synthetic):
             blind = mode == "blind"
             plan = c5_plan(odp, spec, pr, sqrt_f, w0 if blind else w_true, blind, tr)
             scratch = plan.new_state(w0=w0 if blind else None)
-            tune = plan.autotune(scratch, iters=3)
+            tune = plan.autotune(scratch, iters=10)   # 10 iterations per setting: placements differ by a few %
             xs = tune.xcd_slice if args.placement < 0 else args.placement
             plan.set_tuning(tr, xs, tune.tiling)
             del scratch
