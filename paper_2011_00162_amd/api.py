@@ -208,6 +208,11 @@ class Plan:
     def set_tuning(self, transform: int, xcd_slice: int, tiling: int, stream=None) -> None:
         check(lib().odp_plan_set_tuning(self._h, int(transform), int(xcd_slice), int(tiling), _stream(stream)))
 
+    def set_streaming(self, mode: int = -1) -> None:
+        """Cache policy of the frame arrays: 1 streaming (non-temporal) kernel variants, 0
+        ordinary accesses, -1 by size (the default); identical results either way."""
+        check(lib().odp_plan_set_streaming(self._h, int(mode)))
+
     def set_stopping(self, measure: int = ODP_STOP_NONE, tol: float = 0.0, max_iter: int = 0,
                      every: int = 1) -> None:
         """Device-side stopping rule of Sec. 4 (ODP_STOP_RF / ODP_STOP_RE, tolerance,

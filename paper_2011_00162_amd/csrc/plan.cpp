@@ -151,6 +151,13 @@ struct odp_plan {
 
 namespace {
 
+// The default cache policy of a plan's frame arrays: streaming when they (Gamma read and
+// written, sqrt(f), the handoff written and read back: 28 B per frame pixel) exceed the
+// 256 MiB Infinity Cache.
+int32_t stream_by_size(const odp_plan* P) {
+  return (double)P->J * P->p * P->p * 28.0 > 256.0 * (1 << 20) ? 1 : 0;
+}
+
 // Cut every cell into tiles and list, per (tile, subdomain slot), the slot's frames
 // whose window meets the tile (ascending id).  A cell with m copies per pixel gets
 // tiles of 512 / m' pixels (m' = m rounded up to a power of two, at most MAXS = 16: 32
@@ -356,7 +363,7 @@ int build_geometry(odp_plan* P) {
   // written and read back: 28 B per frame pixel) are accessed with the non-temporal hint
   // when they exceed the 256 MiB Infinity Cache of an MI355X; smaller ones stay in that
   // cache from one iteration to the next with ordinary accesses.
-  P->stream = (double)J * P->p * P->p * 28.0 > 256.0 * (1 << 20) ? 1 : 0;
+  P->stream = stream_by_size(P);
   static const int shapes[3][2] = {{16, 32}, {8, 64}, {32, 16}};
   for (int k = 0; k < 3; ++k) build_tiles(P, shapes[k][0], shapes[k][1], P->tsets[k]);
   P->covered = 0;
@@ -1438,6 +1445,15 @@ int odp_plan_set_tuning(odp_plan* P, int32_t transform, int32_t xcd_slice, int32
   P->xcd_slice = xcd_slice;
   P->ts = tiling;
   if (moved && P->wsp) return upload_tiles(P, s);
+  return ODP_OK;
+}
+
+int odp_plan_set_streaming(odp_plan* P, int32_t mode) {
+  if (!P) return fail(ODP_EINVAL, "null argument");
+  if (mode < -1 || mode > 1) return fail(ODP_EINVAL, "streaming mode must be -1, 0 or 1");
+  const int32_t st = mode < 0 ? stream_by_size(P) : mode;
+  if (st != P->stream) ++P->gen;
+  P->stream = st;
   return ODP_OK;
 }
 
