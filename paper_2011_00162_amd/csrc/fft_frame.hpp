@@ -571,11 +571,15 @@ struct Half128 {
   // stage B on the 64 rows of a half: thread t takes row t / 8 and c2 = t % 8 (the
   // same column lines as Frame<128>, twiddle rows TS apart).  The twiddles are read
   // where they are applied (after the DFT forward, before it inverse), so they never
-  // sit in registers across the butterfly.
+  // sit in registers across the butterfly.  The twiddle row's offset comes from an
+  // opaque copy of c2: shared between the four calls of a frame sweep, it would stay
+  // live across the prox and spill.
   template <bool INV, int TS>
   __device__ static __forceinline__ void stage_b(float2* lds, const float2* __restrict__ tw, int t) {
     const int c2 = t & 7, R = t >> 3;
-    const float4* tb4 = reinterpret_cast<const float4*>(tw + TS * c2);
+    int c2q = c2;
+    asm volatile("" : "+v"(c2q));
+    const float4* tb4 = reinterpret_cast<const float4*>(tw + TS * c2q);
     float2 v[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) v[k] = lds[at(R, c2 + 8 * k)];

@@ -125,6 +125,9 @@ struct PixelArgs {
   int32_t n_uni;             // tiles [0, n_uni) belong to cells with at most 4 copies,
   int32_t n_mid;             // [n_uni, n_mid) to cells with 5 to 8, the rest to 9 to MAXS
   const WaveRec* waves;      // [n_uni][4]
+  int32_t pairs;             // 1: in every tile [0, n_uni) the pull records' column origins
+                             // have the parity of the tile's left column, so a thread's two
+                             // row neighbours take one 16-byte load per record
   const float2* psi;         // per-frame outputs of the sweep
   const int32_t* tf_first;   // [n_tiles*MAXS + 1]: frames of slot s overlapping tile t
   const PullEntry* pull;     // their records, ascending frame id

@@ -19,9 +19,10 @@ namespace odp {
 //
 // Every thread owns two (pixel, subdomain copy) pairs of one copy: a cell with m
 // copies per pixel has tiles of 512 / m' pixels (m' = m rounded up to a power of
-// two); thread t takes copy s = t / (256 / m') and the tile pixels i and
-// i + 256 / m' (i = t % (256 / m')), so every copy does one pull and all copies of a
-// pixel sit in one workgroup.  u_d and Lam_{d,e} of a pixel are written only by the
+// two); thread t takes copy s = t / (256 / m') and two tile pixels of that copy, i and
+// i + 256 / m' (i = t % (256 / m')), or in k_pixel_uni, when the plan's records allow it
+// (PixelArgs::pairs), the row neighbours 2i and 2i + 1; so every copy does one pull and
+// all copies of a pixel sit in one workgroup.  u_d and Lam_{d,e} of a pixel are written only by the
 // thread of copy d, after a barrier that follows every thread's reads of the
 // iterate n, so each thread sees u^n and Lam^n of the other copies.  Pairs (a, b),
 // a < b, of the cell's subdomain list are stored at index b(b-1)/2 + a.
@@ -87,6 +88,57 @@ __device__ __forceinline__ void pull_pixels(const PullEntry* __restrict__ pull, 
           num[h] = c_add(num[h], ps[q][h]);
         }
       }
+#pragma unroll
+    for (int q = 0; q < B; ++q) e[q] = en[q];
+  }
+}
+
+// The same sums for a thread whose two pixels are row neighbours (xi, xi + 1), in a plan
+// where every record's column origin has the parity of xi (PixelArgs::pairs): dx = xi - c
+// is even, so both pixels are inside a window or both outside it (p is even), and one
+// 16-byte load fetches the two (16-byte aligned: the frame offset is 8 (dy p + dx)).  Each
+// pixel's sum runs over the same records in the same order as in pull_pixels.
+template <bool BLIND, bool NT>
+__device__ __forceinline__ void pull_pairs(const PullEntry* __restrict__ pull, int k0, int k1,
+                                           const float2* __restrict__ psi, const float2* __restrict__ ws, int yi,
+                                           int xi, uint32_t pix8, int p, float2* num, double* den) {
+  constexpr int B = PULL_B;
+  PullEntry e[B];
+#pragma unroll
+  for (int q = 0; q < B; ++q) e[q] = load_entry(pull + k0 + q);
+  for (int k = k0; k < k1; k += B) {
+    PullEntry en[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) en[q] = load_entry(pull + k + B + q);
+    bool in[B];
+    float4 ps[B], ww[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      const char* fb = reinterpret_cast<const char*>(psi + e[q].base);
+      const int dy = yi - e[q].r, dx = xi - e[q].c;
+      in[q] = (unsigned)dy < (unsigned)p && (unsigned)dx < (unsigned)p;
+      ps[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      ww[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (in[q]) {
+        ps[q] = ld_s<NT>(reinterpret_cast<const float4*>(fb + pix8));
+        if (BLIND) ww[q] = *reinterpret_cast<const float4*>(ws + dy * p + dx);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      const float2 p0 = make_float2(ps[q].x, ps[q].y), p1 = make_float2(ps[q].z, ps[q].w);
+      if (BLIND) {
+        const float2 w0 = make_float2(ww[q].x, ww[q].y), w1 = make_float2(ww[q].z, ww[q].w);
+        const float2 c0 = c_mulc(p0, w0), c1 = c_mulc(p1, w1);
+        num[0] = in[q] ? c_add(num[0], c0) : num[0];
+        num[1] = in[q] ? c_add(num[1], c1) : num[1];
+        den[0] += in[q] ? (double)w0.x * w0.x + (double)w0.y * w0.y : 0.0;
+        den[1] += in[q] ? (double)w1.x * w1.x + (double)w1.y * w1.y : 0.0;
+      } else {
+        num[0] = c_add(num[0], p0);
+        num[1] = c_add(num[1], p1);
+      }
+    }
 #pragma unroll
     for (int q = 0; q < B; ++q) e[q] = en[q];
   }
@@ -181,8 +233,8 @@ __global__ __launch_bounds__(256, BLIND ? 1 : 6) void k_pixel_uni(PixelArgs a) {
   int tr[NPX], tc[NPX], yi[NPX], xi[NPX];
   bool act[NPX];
 #pragma unroll
-  for (int h = 0; h < NPX; ++h) {
-    const int i = q + h * tpg;
+  for (int h = 0; h < NPX; ++h) {                // row neighbours 2q, 2q + 1 with pairs, else q, q + tpg
+    const int i = a.pairs ? 2 * q + h : q + h * tpg;
     tr[h] = i >> w.lcw;
     tc[h] = i & ((1 << w.lcw) - 1);
     act[h] = s < m && tr[h] < w.nr && tc[h] < w.nc;
@@ -221,10 +273,16 @@ __global__ __launch_bounds__(256, BLIND ? 1 : 6) void k_pixel_uni(PixelArgs a) {
     den[h] = 0.0;
   }
   const float2* ws = BLIND ? a.w_sub + (size_t)w.sub * p * p : nullptr;
-  uint32_t pix8[NPX];
+  static_assert(NPX == 2, "pixel pairs");
+  if (a.pairs) {
+    pull_pairs<BLIND, NT>(a.pull, w.k0, w.k1, a.psi, ws, yi[0], xi[0], 8u * (uint32_t)(yi[0] * p + xi[0]), p, num,
+                          den);
+  } else {
+    uint32_t pix8[NPX];
 #pragma unroll
-  for (int h = 0; h < NPX; ++h) pix8[h] = 8u * (uint32_t)(yi[h] * p + xi[h]);
-  pull_pixels<BLIND, NT>(a.pull, w.k0, w.k1, a.psi, ws, yi, xi, pix8, p, num, den);
+    for (int h = 0; h < NPX; ++h) pix8[h] = 8u * (uint32_t)(yi[h] * p + xi[h]);
+    pull_pixels<BLIND, NT>(a.pull, w.k0, w.k1, a.psi, ws, yi, xi, pix8, p, num, den);
+  }
 
   float2 un[NPX], dv[NPX][NO];
   double sv[NPS] = {};

@@ -89,6 +89,8 @@ struct odp_plan {
     std::vector<int32_t> re_list, re_first;  // (tile, slot) entries per subdomain, for RE
     std::vector<int32_t> tf_first;           // per (tile, slot): range of pull records
     std::vector<PullEntry> pull;             // frames whose window meets the tile, ascending id
+    bool pairs = false;                      // tiles [0, n_uni): every record's column origin has
+                                             // the parity of the tile's left column
   };
   TileSet tsets[3];
   int64_t covered = 0;  // image pixels in some subdomain (the tiles partition them)
@@ -229,6 +231,19 @@ void build_tiles(const odp_plan* P, int rows, int cols, odp_plan::TileSet& T) {
   }
   T.tf_first[T.tiles.size() * MAXS] = (int32_t)T.pull.size();
   for (int q = 0; q < PULL_B; ++q) T.pull.push_back(PullEntry{0, PULL_NONE, PULL_NONE});  // read ahead of the last list
+  // with every window column origin of a tile's parity, a window edge never falls between
+  // the two row neighbours a thread of k_pixel_uni holds (tile widths and offsets are even)
+  T.pairs = true;
+  for (int32_t t = 0; t < T.n_uni && T.pairs; ++t) {
+    const TileDesc& td = T.tiles[t];
+    const CellDesc& cd = P->cells[td.cell];
+    const int x0 = cd.c0 + td.c0;
+    for (int32_t k = T.tf_first[(size_t)t * MAXS]; k < T.tf_first[(size_t)t * MAXS + cd.m]; ++k)
+      if (T.pull[k].r != PULL_NONE && ((T.pull[k].c - x0) & 1)) {
+        T.pairs = false;
+        break;
+      }
+  }
 }
 
 int build_geometry(odp_plan* P) {
@@ -1054,6 +1069,7 @@ static PixelArgs pixel_args(const odp_plan* P, char* b, double* stats) {
   a.cells = P->W_<CellDesc>(P->ws.cells);
   a.tiles = P->W_<TileDesc>(P->ws.tiles);
   a.waves = P->W_<WaveRec>(P->ws.waves);
+  a.pairs = P->tset().pairs ? 1 : 0;
   a.n_tiles = (int32_t)P->tset().tiles.size();
   a.n_uni = P->tset().n_uni;
   a.n_mid = P->tset().n_mid;
