@@ -25,7 +25,7 @@ EXPORTS = [
     "odp_blind_initial_probe_static",
     "odp_pixel_update", "odp_merge", "odp_amp_loss", "odp_last_error", "odp_version",
     "odp_batch_plan_create", "odp_batch_get_entry", "odp_batch_set_penalties", "odp_plan_get_tuning",
-    "odp_plan_set_tuning", "odp_plan_set_streaming", "odp_plan_autotune", "odp_graph_create", "odp_graph_launch", "odp_graph_destroy",
+    "odp_plan_set_tuning", "odp_plan_set_streaming", "odp_plan_set_pixel_pairs", "odp_plan_autotune", "odp_graph_create", "odp_graph_launch", "odp_graph_destroy",
     "odp_plan_set_sweep_events", "odp_plan_set_stopping", "odp_state_get_stop_status", "odp_plan_set_balancing",
     "odp_plan_workspace_bytes", "odp_state_bytes", "odp_plan_get_eta",
 ]
@@ -72,7 +72,7 @@ class BatchEntry(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("transform", "xcd_slice", "tiling", "tile_rows", "tile_cols")] + [
-        ("ms_per_iter", C.c_double), ("n_tried", C.c_int32)]
+        ("ms_per_iter", C.c_double), ("n_tried", C.c_int32), ("pixel_pairs", C.c_int32)]
 
 
 _lib = None
@@ -116,6 +116,7 @@ def lib() -> C.CDLL:
         "odp_plan_get_tuning": (C.c_int, [vp, C.POINTER(Tuning)]),
         "odp_plan_set_tuning": (C.c_int, [vp, i32, i32, i32, vp]),
         "odp_plan_set_streaming": (C.c_int, [vp, i32]),
+        "odp_plan_set_pixel_pairs": (C.c_int, [vp, i32]),
         "odp_plan_set_stopping": (C.c_int, [vp, i32, C.c_double, i32, i32]),
         "odp_plan_set_balancing": (C.c_int, [vp, C.c_double, C.c_double, i32, i32, i32]),
         "odp_plan_get_eta": (C.c_double, [vp]),

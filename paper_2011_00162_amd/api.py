@@ -213,6 +213,12 @@ class Plan:
         ordinary accesses, -1 by size (the default); identical results either way."""
         check(lib().odp_plan_set_streaming(self._h, int(mode)))
 
+    def set_pixel_pairs(self, mode: int = 1) -> None:
+        """Pixel-update pull width: 1 (default) one 16-byte load for a thread's two row
+        neighbours wherever the plan's window columns allow it, 0 one load per pixel;
+        identical iterates either way (``get_tuning().pixel_pairs`` reports the choice)."""
+        check(lib().odp_plan_set_pixel_pairs(self._h, int(mode)))
+
     def set_stopping(self, measure: int = ODP_STOP_NONE, tol: float = 0.0, max_iter: int = 0,
                      every: int = 1) -> None:
         """Device-side stopping rule of Sec. 4 (ODP_STOP_RF / ODP_STOP_RE, tolerance,

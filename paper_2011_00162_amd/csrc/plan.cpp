@@ -128,6 +128,7 @@ struct odp_plan {
   std::vector<uint16_t> mft;               // split-BF16 radix-16 stage matrices (hybrid transform)
   int32_t chunk = 0;
   int32_t stream = 0;   // 1: non-temporal accesses to the frame arrays (set from their size)
+  int32_t pairs_on = 1; // 0: the pixel update keeps one load per pixel even where pairs apply
   // workspace layout (byte offsets)
   struct {
     size_t tw, w, frames, fpos, order, sub_first, offsets, rects, usub_off, cells, tiles, waves, re_list, re_first,
@@ -1069,7 +1070,7 @@ static PixelArgs pixel_args(const odp_plan* P, char* b, double* stats) {
   a.cells = P->W_<CellDesc>(P->ws.cells);
   a.tiles = P->W_<TileDesc>(P->ws.tiles);
   a.waves = P->W_<WaveRec>(P->ws.waves);
-  a.pairs = P->tset().pairs ? 1 : 0;
+  a.pairs = P->pairs_on && P->tset().pairs ? 1 : 0;
   a.n_tiles = (int32_t)P->tset().tiles.size();
   a.n_uni = P->tset().n_uni;
   a.n_mid = P->tset().n_mid;
@@ -1446,6 +1447,7 @@ int odp_plan_get_tuning(const odp_plan* P, odp_tuning* o) {
   o->tile_cols = P->tset().cols;
   o->ms_per_iter = 0.0;
   o->n_tried = 0;
+  o->pixel_pairs = P->pairs_on && P->tset().pairs ? 1 : 0;
   return ODP_OK;
 }
 
@@ -1470,6 +1472,14 @@ int odp_plan_set_streaming(odp_plan* P, int32_t mode) {
   const int32_t st = mode < 0 ? stream_by_size(P) : mode;
   if (st != P->stream) ++P->gen;
   P->stream = st;
+  return ODP_OK;
+}
+
+int odp_plan_set_pixel_pairs(odp_plan* P, int32_t mode) {
+  if (!P) return fail(ODP_EINVAL, "null argument");
+  if (mode < 0 || mode > 1) return fail(ODP_EINVAL, "pixel pairs mode must be 0 or 1");
+  if (mode != P->pairs_on) ++P->gen;
+  P->pairs_on = mode;
   return ODP_OK;
 }
 

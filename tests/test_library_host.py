@@ -212,6 +212,32 @@ def test_tuning_values_are_checked():
             assert (t.xcd_slice, t.tiling, (t.tile_rows, t.tile_cols)) == (xcd, tiling, shape)
 
 
+def test_pixel_pairs_follow_the_window_columns():
+    """The paired pull (one 16-byte load for a thread's two row neighbours) is on exactly
+    when every window of a tile starts at a column of the tile's parity: even raster
+    offsets give even cell edges; one window moved to an odd column turns it off."""
+    L = odp.lib()
+    plan = odp.Plan(**_plan_args())                       # offsets 0, 8, ..., 32: all even
+    for tiling in (0, 1, 2):
+        assert L.odp_plan_set_tuning(plan._h, odp.ODP_FFT_F32, 0, tiling, None) == 0
+        assert plan.tuning().pixel_pairs == 1
+    plan.set_pixel_pairs(0)
+    assert plan.tuning().pixel_pairs == 0
+    plan.set_pixel_pairs(1)
+    assert plan.tuning().pixel_pairs == 1
+    assert L.odp_plan_set_pixel_pairs(plan._h, 2) == ODP_EINVAL
+    assert L.odp_plan_set_pixel_pairs(plan._h, -1) == ODP_EINVAL
+    assert L.odp_plan_set_pixel_pairs(None, 1) == ODP_EINVAL
+    a = _plan_args()
+    off = a["offsets"].copy()
+    off[5, 1] += 1                                        # one window of the first subdomain at an odd column
+    a["offsets"] = off
+    odd = odp.Plan(**a)
+    for tiling in (0, 1, 2):
+        assert L.odp_plan_set_tuning(odd._h, odp.ODP_FFT_F32, 0, tiling, None) == 0
+        assert odd.tuning().pixel_pairs == 0
+
+
 def test_initial_probe_arguments_are_checked():
     import ctypes as C
     plan = odp.Plan(**_plan_args())
