@@ -24,6 +24,7 @@ struct CellDesc {
   int32_t r0, c0;            // top-left pixel in the image
   float r;                   // overlap penalty of the problem the cell belongs to
   int32_t probe;             // probe index of that problem
+  int32_t nr, nc;            // extent (rows, columns)
   int32_t sub[MAXS];         // subdomain ids, ascending
   int32_t upitch[MAXS];      // row pitch of each subdomain array
   int64_t ubase[MAXS];       // u_sub index of the cell's top-left in each subdomain

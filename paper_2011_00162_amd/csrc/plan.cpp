@@ -122,7 +122,6 @@ struct odp_plan {
   };
   std::vector<Entry> batch;
   std::vector<int32_t> sub_problem;        // [D] problem of each subdomain
-  std::vector<int> cuts_r, cuts_c;         // cell cuts
   std::vector<float2> tw;
   std::vector<uint16_t> dft;               // split-BF16 DFT matrix planes (transform = DFT)
   std::vector<uint16_t> mft;               // split-BF16 radix-16 stage matrices (hybrid transform)
@@ -182,8 +181,7 @@ void build_tiles(const odp_plan* P, int rows, int cols, odp_plan::TileSet& T) {
       int groups = 1;
       while (groups < cd.m) groups *= 2;
       const int ppt = rows * cols / groups, tw = std::min(cols, ppt), th = ppt / tw;
-      const int r1 = *std::upper_bound(P->cuts_r.begin(), P->cuts_r.end(), cd.r0);
-      const int c1 = *std::upper_bound(P->cuts_c.begin(), P->cuts_c.end(), cd.c0);
+      const int r1 = cd.r0 + cd.nr, c1 = cd.c0 + cd.nc;
       for (int ty = 0; ty < r1 - cd.r0; ty += th)
         for (int tx = 0; tx < c1 - cd.c0; tx += tw) {
           TileDesc td;
@@ -291,69 +289,73 @@ int build_geometry(odp_plan* P) {
       }
     }
   P->n_lam = loff;
-  // cells: cut the image at every rectangle edge
-  std::vector<int> rc = {0, H}, cc = {0, W};
-  for (int d = 0; d < D; ++d) {
-    rc.push_back(P->rects[4 * d]);
-    rc.push_back(P->rects[4 * d + 2]);
-    cc.push_back(P->rects[4 * d + 1]);
-    cc.push_back(P->rects[4 * d + 3]);
-  }
-  std::sort(rc.begin(), rc.end());
-  rc.erase(std::unique(rc.begin(), rc.end()), rc.end());
-  std::sort(cc.begin(), cc.end());
-  cc.erase(std::unique(cc.begin(), cc.end()), cc.end());
-  P->cuts_r = rc;
-  P->cuts_c = cc;
   // pair lookup
   std::vector<int> pair_of((size_t)D * D, -1);
   for (size_t q = 0; q < P->pairs.size(); ++q) {
     pair_of[(size_t)P->pairs[q].a * D + P->pairs[q].b] = (int)q;
   }
+  // cells: each problem's region cut at its own rectangles' edges (a batch places its
+  // problems side by side; cutting every problem at the others' edges too would split
+  // each into thin strips)
   P->cells.clear();
   P->max_cover = 0;
-  for (size_t yi = 0; yi + 1 < rc.size(); ++yi)
-    for (size_t xi = 0; xi + 1 < cc.size(); ++xi) {
-      const int r0 = rc[yi], r1 = rc[yi + 1], c0 = cc[xi], c1 = cc[xi + 1];
-      std::vector<int> S;
-      for (int d = 0; d < D; ++d) {
-        const int32_t* R = &P->rects[4 * d];
-        if (R[0] <= r0 && r1 <= R[2] && R[1] <= c0 && c1 <= R[3]) S.push_back(d);
-      }
-      if (S.empty()) continue;
-      P->max_cover = std::max<int32_t>(P->max_cover, (int32_t)S.size());
-      if ((int)S.size() > MAXS)
-        return fail(ODP_EUNSUPPORTED, "more than " + std::to_string(MAXS) + " subdomains overlap one pixel");
-      CellDesc cd;
-      std::memset(&cd, 0, sizeof(cd));
-      cd.m = (int32_t)S.size();
-      cd.npair = cd.m * (cd.m - 1) / 2;
-      cd.r0 = r0;
-      cd.c0 = c0;
-      for (int s = 0; s < cd.m; ++s) {
-        const int d = S[s];
-        const int32_t* R = &P->rects[4 * d];
-        cd.sub[s] = d;
-        cd.upitch[s] = R[3] - R[1];
-        cd.ubase[s] = P->usub_off[d] + (int64_t)(r0 - R[0]) * (R[3] - R[1]) + (c0 - R[1]);
-      }
-      for (int t = 1; t < cd.m; ++t)
-        for (int s = 0; s < t; ++s) {
-          const int q = t * (t - 1) / 2 + s;
-          const int pq = pair_of[(size_t)S[s] * D + S[t]];
-          if (pq < 0) return fail(ODP_EGEOM, "internal: missing pair");
-          const Pair& pr = P->pairs[pq];
-          const int pw = pr.c1 - pr.c0, ph = pr.r1 - pr.r0;
-          cd.lbase[q] = pr.off + (int64_t)(r0 - pr.r0) * pw + (c0 - pr.c0);
-          cd.lstride[q] = (int64_t)ph * pw;
-          cd.lpitch[q] = pw;
-          cd.pa[q] = (int8_t)s;
-          cd.pb[q] = (int8_t)t;
-        }
-      cd.r = (float)P->batch[P->sub_problem[S[0]]].r;
-      cd.probe = P->sub_problem[S[0]];
-      P->cells.push_back(cd);
+  for (const odp_plan::Entry& e : P->batch) {
+    std::vector<int> rc = {e.row0, e.row0 + e.H}, cc = {e.col0, e.col0 + e.W};
+    for (int d = e.D0; d < e.D0 + e.D; ++d) {
+      rc.push_back(P->rects[4 * d]);
+      rc.push_back(P->rects[4 * d + 2]);
+      cc.push_back(P->rects[4 * d + 1]);
+      cc.push_back(P->rects[4 * d + 3]);
     }
+    std::sort(rc.begin(), rc.end());
+    rc.erase(std::unique(rc.begin(), rc.end()), rc.end());
+    std::sort(cc.begin(), cc.end());
+    cc.erase(std::unique(cc.begin(), cc.end()), cc.end());
+    for (size_t yi = 0; yi + 1 < rc.size(); ++yi)
+      for (size_t xi = 0; xi + 1 < cc.size(); ++xi) {
+        const int r0 = rc[yi], r1 = rc[yi + 1], c0 = cc[xi], c1 = cc[xi + 1];
+        std::vector<int> S;
+        for (int d = e.D0; d < e.D0 + e.D; ++d) {
+          const int32_t* R = &P->rects[4 * d];
+          if (R[0] <= r0 && r1 <= R[2] && R[1] <= c0 && c1 <= R[3]) S.push_back(d);
+        }
+        if (S.empty()) continue;
+        P->max_cover = std::max<int32_t>(P->max_cover, (int32_t)S.size());
+        if ((int)S.size() > MAXS)
+          return fail(ODP_EUNSUPPORTED, "more than " + std::to_string(MAXS) + " subdomains overlap one pixel");
+        CellDesc cd;
+        std::memset(&cd, 0, sizeof(cd));
+        cd.m = (int32_t)S.size();
+        cd.npair = cd.m * (cd.m - 1) / 2;
+        cd.r0 = r0;
+        cd.c0 = c0;
+        cd.nr = r1 - r0;
+        cd.nc = c1 - c0;
+        for (int s = 0; s < cd.m; ++s) {
+          const int d = S[s];
+          const int32_t* R = &P->rects[4 * d];
+          cd.sub[s] = d;
+          cd.upitch[s] = R[3] - R[1];
+          cd.ubase[s] = P->usub_off[d] + (int64_t)(r0 - R[0]) * (R[3] - R[1]) + (c0 - R[1]);
+        }
+        for (int t = 1; t < cd.m; ++t)
+          for (int s = 0; s < t; ++s) {
+            const int q = t * (t - 1) / 2 + s;
+            const int pq = pair_of[(size_t)S[s] * D + S[t]];
+            if (pq < 0) return fail(ODP_EGEOM, "internal: missing pair");
+            const Pair& pr = P->pairs[pq];
+            const int pw = pr.c1 - pr.c0, ph = pr.r1 - pr.r0;
+            cd.lbase[q] = pr.off + (int64_t)(r0 - pr.r0) * pw + (c0 - pr.c0);
+            cd.lstride[q] = (int64_t)ph * pw;
+            cd.lpitch[q] = pw;
+            cd.pa[q] = (int8_t)s;
+            cd.pb[q] = (int8_t)t;
+          }
+        cd.r = (float)P->batch[P->sub_problem[S[0]]].r;
+        cd.probe = P->sub_problem[S[0]];
+        P->cells.push_back(cd);
+      }
+  }
   // frames: base index inside the owning subdomain; processing order grouped by subdomain
   P->frames.resize(J);
   for (int j = 0; j < J; ++j) {
