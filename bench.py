@@ -109,7 +109,8 @@ def gpu_leg(args, torch, odp, synthetic, transform=0):
     # frame order and pixel tiling as the library's autotuner picks them (on a scratch
     # state, before the timed region); the transform stays the one this leg measures
     tune = plan.autotune(plan.new_state(), iters=20)
-    plan.set_tuning(transform, tune.xcd_slice, tune.tiling)
+    xs = tune.xcd_slice if args.placement < 0 else args.placement
+    plan.set_tuning(transform, xs, tune.tiling)
     state = plan.new_state()
     info = plan.info
 
@@ -120,7 +121,7 @@ def gpu_leg(args, torch, odp, synthetic, transform=0):
     return dict(J=J, n=n, p=p, D=info.D, total_ms=total_ms, sweep_avg_ms=sweep_avg,
                 sweep_median_ms=sweep_med, alg_bytes=alg_bytes, r=r, eta=eta, eps=eps,
                 p_sub=info.p_sub, n_pairs=info.n_pairs,
-                tuning={"xcd_slice": tune.xcd_slice, "tiling": tune.tiling, "tile": [tune.tile_rows, tune.tile_cols]})
+                tuning={"xcd_slice": xs, "tiling": tune.tiling, "tile": [tune.tile_rows, tune.tile_cols]})
 
 
 def time_iterations(torch, plan, state, steps):
@@ -610,7 +611,9 @@ def c2_report(args, torch, odp, synthetic):
             "fft_f32": {"value": value, "ms_per_step": g["total_ms"] / args.steps, "sweep_ms": g["sweep_avg_ms"],
                         "sweep_roofline": {"bound": "hbm", "kernel": "k_sweep<64, false, false, 0, false>", "achieved": achieved,
                                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                                           "traffic": measured_traffic(),
+                                           # counters per frame placement (windows re-read across L2s)
+                                           "traffic": measured_traffic(
+                                               key=f"traffic_bytes_per_launch_xcd{g['tuning']['xcd_slice']}"),
                                            "algorithmic_bytes_per_launch": g["alg_bytes"]}},
             "dft_split_bf16": {"value": gd["J"] * args.steps / (gd["total_ms"] / 1e3),
                                "ms_per_step": gd["total_ms"] / args.steps, "sweep_ms": gd["sweep_avg_ms"],
@@ -640,8 +643,8 @@ def main() -> int:
                          "c2 512^2 alone; c3 loss+gradient; c4 64-problem batch; "
                          "table1 iterations to RF <= 1e-5 against the number of stripes (context)")
     ap.add_argument("--placement", type=int, default=-1, choices=[-1, 0, 1, 2],
-                    help="2048^2 line: frame placement (xcd_slice) of the timed configuration instead of the "
-                         "autotuner's choice (profiling runs; -1 = the autotuner's)")
+                    help="frame placement (xcd_slice) of the timed configurations (2048^2 and 512^2 lines) "
+                         "instead of the autotuner's choice (profiling runs; -1 = the autotuner's)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (scales the HBM counters)")
     args = ap.parse_args()
