@@ -176,6 +176,22 @@ def test_batch_plan_packs_independent_problems():
     np.testing.assert_array_equal(g.pairs, np.array(sorted(pair_rows), dtype=np.int32).reshape(-1, 6))
 
 
+def test_batch_cells_are_the_problems_own():
+    """Each problem of a batch is cut into pixel-update cells at its own subdomain edges
+    only: the batch's cells and tiles are those of its problems planned alone, at every
+    tiling (cutting at the other problems' edges too multiplied them about 17-fold)."""
+    items = [(s, pr) for (s, pr) in _batch_problems(12) if s.p == 64]
+    probs = [dict(H=s.n, W=s.n, p=s.p, offsets=pr["offsets"], frame_sub=pr["frame_sub"], r=1.0) for s, pr in items]
+    batch = odp.Plan.batch(probs)
+    singles = [odp.Plan(s.n, s.n, s.p, pr["offsets"], pr["frame_sub"], r=1.0) for s, pr in items]
+    assert batch.info.n_cells == sum(q.info.n_cells for q in singles)
+    L = odp.lib()
+    for tiling in (0, 1, 2):
+        for q in [batch] + singles:
+            assert L.odp_plan_set_tuning(q._h, odp.ODP_FFT_F32, 0, tiling, None) == 0
+        assert batch.info.n_tiles == sum(q.info.n_tiles for q in singles), tiling
+
+
 def test_batch_rejects_mixed_probe_sizes():
     items = _batch_problems(12)
     ps = {s.p for s, _ in items}
