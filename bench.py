@@ -41,7 +41,7 @@ C5_SUBS_CHECKED = (0, 3, 36)      # a corner, an edge and an interior subdomain 
 # include, and the host plan code that sets launch shapes, orders and the streaming mode)
 LOSS_SOURCES = ["paper_2011_00162_amd/csrc/loss.hip", "paper_2011_00162_amd/csrc/fft_frame.hpp",
                 "paper_2011_00162_amd/csrc/reduce.hpp", "paper_2011_00162_amd/csrc/odp_internal.hpp",
-                "paper_2011_00162_amd/csrc/plan.cpp"]
+                "paper_2011_00162_amd/csrc/pull.hpp", "paper_2011_00162_amd/csrc/plan.cpp"]
 KERNEL_SOURCES = sorted("paper_2011_00162_amd/csrc/" + f
                         for f in os.listdir(os.path.join(ROOT, "paper_2011_00162_amd", "csrc"))
                         if f.endswith((".hip", ".hpp", ".cpp")))

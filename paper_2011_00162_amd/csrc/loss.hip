@@ -12,6 +12,7 @@
 
 #include "fft_frame.hpp"
 #include "odp_internal.hpp"
+#include "pull.hpp"
 #include "reduce.hpp"
 
 namespace odp {
@@ -182,38 +183,31 @@ __device__ __forceinline__ void grad_u_tile(const LossGradArgs& a, int tile) {
   const TileDesc td = a.tiles[tile];
   const CellDesc* cd = a.cells + td.cell;
   const int p = a.p;
-  // tiles partition the covered pixels, so each pixel is written by one thread
+  // tiles partition the covered pixels, so each pixel is written by one thread; with
+  // a.pairs the thread's two pixels are row neighbours (one 16-byte load per frame)
   int yi[NPX], xi[NPX];
   bool act[NPX];
   float2 g[NPX];
 #pragma unroll
   for (int h = 0; h < NPX; ++h) {
-    const int i = threadIdx.x + 256 * h, tr = i / a.tile_cols, tc = i % a.tile_cols;
+    const int i = a.pairs ? 2 * (int)threadIdx.x + h : (int)threadIdx.x + 256 * h;
+    const int tr = i / a.tile_cols, tc = i % a.tile_cols;
     act[h] = tr < td.nr && tc < td.nc;
     yi[h] = cd->r0 + td.r0 + tr;
     xi[h] = cd->c0 + td.c0 + tc;
     g[h] = make_float2(0.f, 0.f);
   }
+  static_assert(NPX == 2, "pixel pairs");
   for (int s = 0; s < cd->m; ++s) {
-    const int k1 = a.tf_first[tile * MAXS + s + 1];
-    for (int k = a.tf_first[tile * MAXS + s]; k < k1; k += PULL_B) {
-      PullEntry pe[PULL_B];
+    const int k0 = a.tf_first[tile * MAXS + s], k1 = a.tf_first[tile * MAXS + s + 1];
+    if (a.pairs) {
+      pull_pairs<true, false, false>(a.pull, k0, k1, a.phi, a.w, yi[0], xi[0], 8u * (uint32_t)(yi[0] * p + xi[0]),
+                                     p, g, nullptr);
+    } else {
+      uint32_t pix8[NPX];
 #pragma unroll
-      for (int b = 0; b < PULL_B; ++b) pe[b] = a.pull[k + b];   // lists padded to PULL_B
-      float2 ph[NPX][PULL_B], ww[NPX][PULL_B];
-#pragma unroll
-      for (int h = 0; h < NPX; ++h)
-#pragma unroll
-        for (int b = 0; b < PULL_B; ++b) {
-          const int dy = yi[h] - pe[b].r, dx = xi[h] - pe[b].c;
-          const bool in = act[h] && (unsigned)dy < (unsigned)p && (unsigned)dx < (unsigned)p;
-          ph[h][b] = in ? a.phi[pe[b].base + (int64_t)yi[h] * p + xi[h]] : make_float2(0.f, 0.f);
-          ww[h][b] = in ? a.w[dy * p + dx] : make_float2(0.f, 0.f);
-        }
-#pragma unroll
-      for (int h = 0; h < NPX; ++h)
-#pragma unroll
-        for (int b = 0; b < PULL_B; ++b) g[h] = c_add(g[h], c_mulc(ph[h][b], ww[h][b]));
+      for (int h = 0; h < NPX; ++h) pix8[h] = 8u * (uint32_t)(yi[h] * p + xi[h]);
+      pull_pixels<true, false, false>(a.pull, k0, k1, a.phi, a.w, yi, xi, pix8, p, g, nullptr);
     }
   }
 #pragma unroll

@@ -271,6 +271,7 @@ struct LossGradArgs {
   int32_t n_tiles, tile_cols;
   const int32_t* tf_first;
   const PullEntry* pull;
+  int32_t pairs;             // 1: row-neighbour pixel pairs (as PixelArgs::pairs)
   float2* grad_u;            // [H][W] or null
   float2* grad_w;            // [p][p] or null
   double* wpart;             // [n_chunks][p][p][2]

@@ -231,9 +231,10 @@ void build_tiles(const odp_plan* P, int rows, int cols, odp_plan::TileSet& T) {
   T.tf_first[T.tiles.size() * MAXS] = (int32_t)T.pull.size();
   for (int q = 0; q < PULL_B; ++q) T.pull.push_back(PullEntry{0, PULL_NONE, PULL_NONE});  // read ahead of the last list
   // with every window column origin of a tile's parity, a window edge never falls between
-  // the two row neighbours a thread of k_pixel_uni holds (tile widths and offsets are even)
+  // the two row neighbours a thread of k_pixel_uni or of the loss's image gradient holds
+  // (tile widths are even); every tile is checked, the loss pulls over all of them
   T.pairs = true;
-  for (int32_t t = 0; t < T.n_uni && T.pairs; ++t) {
+  for (size_t t = 0; t < T.tiles.size() && T.pairs; ++t) {
     const TileDesc& td = T.tiles[t];
     const CellDesc& cd = P->cells[td.cell];
     const int x0 = cd.c0 + td.c0;
@@ -1427,6 +1428,7 @@ int odp_amp_loss(const odp_plan* P, const odp_c32* u, const odp_c32* w, double* 
   ga.tile_cols = P->tset().cols;
   ga.tf_first = P->W_<int32_t>(P->ws.tf_first);
   ga.pull = P->W_<PullEntry>(P->ws.pull);
+  ga.pairs = P->pairs_on && P->tset().pairs ? 1 : 0;
   ga.grad_u = reinterpret_cast<float2*>(grad_u);
   ga.grad_w = reinterpret_cast<float2*>(grad_w);
   ga.wpart = P->W_<double>(P->ws.wpart);

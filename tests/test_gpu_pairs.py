@@ -14,7 +14,7 @@ import pytest
 import torch
 
 import paper_2011_00162_amd as odp
-from tests.gpu_util import gpu_plan, host
+from tests.gpu_util import dev_c64, gpu_plan, host
 from tests.oracle_problems import oracle_problem, tiny_spec
 from tests.test_gpu_streaming import _parts, _start
 
@@ -56,3 +56,26 @@ def test_paired_pull_is_bit_identical(name, spec, transform, blind, tiling):
     differ = {k: int((a0[k] != a1[k]).sum()) for k in a0 if not torch.equal(a0[k], a1[k])}
     assert not differ, differ
     np.testing.assert_allclose(s1, s0, rtol=1e-12, atol=1e-300)
+
+
+@pytest.mark.parametrize("dy", [1, 2])
+def test_paired_pull_gives_the_same_loss_gradient(dy):
+    """The amplitude loss's image gradient pulls the same way: bit-identical dL/du with the
+    paired and the one-pixel pull (256^2 crops of the loss workload, one and 2 x 2
+    subdomains, every tiling)."""
+    from tests.test_gpu_loss import _case
+    say("loss gradient, pixel pairs on/off, subdomains", dy, "x", dy)
+    plan, u, w, f, off = _case(256, dy, dy)
+    L = odp.lib()
+    for tiling in (0, 1, 2):
+        assert L.odp_plan_set_tuning(plan._h, odp.ODP_FFT_F32, 1, tiling, None) == 0
+        out = []
+        for mode in (0, 1):
+            plan.set_pixel_pairs(mode)
+            assert plan.tuning().pixel_pairs == mode
+            loss, gu, gw = plan.amp_loss(dev_c64(u), dev_c64(w))
+            torch.cuda.synchronize()
+            out.append((host(loss), gu.clone(), gw.clone()))
+        (l0, u0, w0), (l1, u1, w1) = out
+        assert torch.equal(u0, u1), (tiling, int((u0 != u1).sum()))
+        assert torch.equal(w0, w1) and np.array_equal(l0, l1)
