@@ -240,6 +240,30 @@ def test_cap_with_five_to_eight_copies():
     _cap_freezes(plan)
 
 
+@pytest.mark.parametrize("blind", [False, True], ids=["known_probe", "blind"])
+@pytest.mark.parametrize("groups", [6, 12], ids=["six_copies", "twelve_copies"])
+def test_statistics_variants_keep_the_iterate_with_many_copies(groups, blind):
+    """The general pixel kernel (cells with 5-8 and 9-16 copies) forms u and Lam partner by
+    partner without statistics and from whole partner arrays with them; both keep the same
+    arithmetic order, so K iterations give the same state bit for bit either way."""
+    from tests.test_gpu_streaming import _parts, _start
+    spec = tiny_spec(n=96, p=32, step=8, jitter=1, radius=12, peak=1e4)
+    say("statistics on/off,", groups, "subdomains interleaved,", "blind" if blind else "known probe")
+    P = oracle_problem(spec)
+    P["pr"]["frame_sub"] = (np.arange(len(P["pr"]["offsets"])) % groups).astype(np.int32)
+    runs = []
+    for stats in (False, True):
+        plan = gpu_plan(P, r=1.0, blind=blind, mu=4.0 if blind else 0.0)
+        assert plan.info.max_cover > (8 if groups > 8 else 4), plan.info.max_cover
+        st = _start(plan, P, blind)
+        plan.iterate(st, 4, stats=stats)
+        torch.cuda.synchronize()
+        runs.append(_parts(plan, st))
+    a, b = runs
+    differ = {k: int((a[k] != b[k]).sum()) for k in a if not torch.equal(a[k], b[k])}
+    assert not differ, differ
+
+
 def test_check_interval_stops_at_the_next_check():
     """every = 4: the rule is read after iterations 4, 8, ...; the problem stops at the
     first of those whose measure meets the tolerance, and the counts stay exact."""
